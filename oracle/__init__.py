@@ -1,0 +1,271 @@
+"""ctypes front-end of the FP64 CPU oracle (``qsym_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg call it; the HIP product path never does.  Arrays are
+numpy float64, positions/velocities shaped (n, 3).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "qsym_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class Params(C.Structure):
+    _fields_ = [("G", C.c_double), ("m0", C.c_double), ("aE", C.c_double), ("aH", C.c_double),
+                ("epsH", C.c_double), ("eta", C.c_double), ("eta_s", C.c_double),
+                ("crude_safety", C.c_double), ("hill_mode", C.c_int32),
+                ("kepler_mode", C.c_int32), ("max_substeps", C.c_int32), ("pad", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "n_candidates", "n_encounters", "n_sets", "max_set", "substeps", "kepler_iters",
+        "kepler_max", "kepler_fail", "hermite_fail", "cand_overflow")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+DEFAULTS = dict(G=1.0, m0=1.0, aE=3.0, aH=1.0, epsH=1e-8, eta=0.02, eta_s=0.01,
+                crude_safety=1.1, hill_mode=0, kepler_mode=0, max_substeps=100000)
+
+
+def make_params(**kw) -> Params:
+    d = dict(DEFAULTS)
+    d.update(kw)
+    return Params(d["G"], d["m0"], d["aE"], d["aH"], d["epsH"], d["eta"], d["eta_s"],
+                  d["crude_safety"], int(d["hill_mode"]), int(d["kepler_mode"]),
+                  int(d["max_substeps"]), 0)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-fno-fast-math", "-fopenmp", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        i64, i32, d = C.c_int64, C.c_int32, C.c_double
+        pp = C.POINTER(Params)
+        sig = {
+            "orc_stumpff": (None, [d, _dp, _dp]),
+            "orc_kepler_body": (C.c_int, [d, _dp, _dp, d, i32, _dp, _dp, _ip]),
+            "orc_kepler_root": (C.c_int, [d, _dp, _dp, d, i32, d, i32, _dp, _ip]),
+            "orc_kepler_all": (i64, [i64, d, _dp, _dp, d, i32, _dp, _dp, _ip]),
+            "orc_drift": (None, [i64, d, _dp, _dp, _dp, d]),
+            "orc_prepass": (None, [i64, d, _dp, _dp, _dp, _dp]),
+            "orc_accel": (None, [i64, d, _dp, _dp, _dp]),
+            "orc_kick": (None, [i64, d, _dp, _dp, _dp, d]),
+            "orc_crude": (i64, [i64, pp, d, _dp, _dp, _dp, _dp, _ip, i64]),
+            "orc_fine_pair": (C.c_int, [pp, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, i64, i64,
+                                        _dp, _dp, _dp]),
+            "orc_fine": (i64, [i64, _ip, pp, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _ip, _dp, _dp]),
+            "orc_sets": (i64, [i64, i64, _ip, _ip]),
+            "orc_transition": (None, [d, d, _dp, _dp, _dp]),
+            "orc_correct_set": (None, [i64, _ip, _dp, _dp, _dp, d, d, d]),
+            "orc_hermite_force": (None, [i64, _dp, _dp, _dp, d, d, d, d, _dp, _dp]),
+            "orc_hermite_set": (i64, [i64, _ip, _dp, _dp, _dp, pp, d, d]),
+            "orc_hkep_set": (d, [i64, _ip, _dp, _dp, _dp, pp, d]),
+            "orc_energy": (d, [i64, d, d, _dp, _dp, _dp]),
+            "orc_angmom": (None, [i64, _dp, _dp, _dp, _dp]),
+            "orc_step": (C.c_int, [i64, pp, d, _dp, _dp, _dp, _dp, i64, _ip, i64, _ip,
+                                   C.POINTER(Stats)]),
+            "orc_num_threads": (C.c_int, []),
+            "orc_set_threads": (None, [C.c_int]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a if shape is None else a.reshape(shape)
+
+
+# ----------------------------------------------------------------- wrappers
+def stumpff(y: float):
+    c, s = C.c_double(), C.c_double()
+    lib().orc_stumpff(float(y), C.byref(c), C.byref(s))
+    return c.value, s.value
+
+
+def kepler(mu, q, v, dt, mode=0):
+    """Advance every body by dt on its two-body orbit; returns q1, v1, iters, fails."""
+    q = _f64(q, (-1, 3)); v = _f64(v, (-1, 3))
+    n = q.shape[0]
+    q1 = np.empty_like(q); v1 = np.empty_like(v); it = np.zeros(n, np.int32)
+    fails = lib().orc_kepler_all(n, mu, _d(q), _d(v), dt, mode, _d(q1), _d(v1), _i(it))
+    return q1, v1, it, int(fails)
+
+
+def kepler_root(mu, x0, v0, dt, mode=0, x_start=None):
+    x0 = _f64(x0, (3,)); v0 = _f64(v0, (3,))
+    out = C.c_double(); it = C.c_int32()
+    fail = lib().orc_kepler_root(mu, _d(x0), _d(v0), dt, mode, 0.0 if x_start is None else x_start,
+                                 0 if x_start is None else 1, C.byref(out), C.byref(it))
+    return out.value, it.value, fail
+
+
+def drift(m0, m, q, v, dt):
+    q = _f64(q, (-1, 3)).copy(); v = _f64(v, (-1, 3)); m = _f64(m)
+    lib().orc_drift(q.shape[0], m0, _d(m), _d(v), _d(q), dt)
+    return q
+
+
+def prepass(mu, q, v):
+    q = _f64(q, (-1, 3)); v = _f64(v, (-1, 3))
+    n = q.shape[0]
+    A = np.empty(n); ve = np.empty(n)
+    lib().orc_prepass(n, mu, _d(q), _d(v), _d(A), _d(ve))
+    return A, ve
+
+
+def accel(G, m, q):
+    q = _f64(q, (-1, 3)); m = _f64(m)
+    a = np.empty_like(q)
+    lib().orc_accel(q.shape[0], G, _d(m), _d(q), _d(a))
+    return a
+
+
+def kick(G, m, q, v, dt):
+    q = _f64(q, (-1, 3)); v = _f64(v, (-1, 3)).copy(); m = _f64(m)
+    lib().orc_kick(q.shape[0], G, _d(m), _d(q), _d(v), dt)
+    return v
+
+
+def crude(params: Params, tau, q, h, A, ve, cap=None):
+    q = _f64(q, (-1, 3)); h = _f64(h); A = _f64(A); ve = _f64(ve)
+    n = q.shape[0]
+    cnt = lib().orc_crude(n, C.byref(params), tau, _d(q), _d(h), _d(A), _d(ve), None, 0)
+    pairs = np.zeros((max(cnt, 1), 2), np.int32)
+    lib().orc_crude(n, C.byref(params), tau, _d(q), _d(h), _d(A), _d(ve), _i(pairs), cnt)
+    return pairs[:cnt]
+
+
+def fine(params: Params, tau, pairs, m, h, A, q0, v0, q1, v1):
+    """Fine-sweep flags of candidate pairs plus the two sides of the comparison."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    k = pairs.shape[0]
+    flags = np.zeros(max(k, 1), np.int32); lhs = np.zeros(max(k, 1)); rhs = np.zeros(max(k, 1))
+    args = [_f64(x) for x in (m, h, A)] + [_f64(x, (-1, 3)) for x in (q0, v0, q1, v1)]
+    lib().orc_fine(k, _i(pairs), C.byref(params), tau, *[_d(x) for x in args], _i(flags),
+                   _d(lhs), _d(rhs))
+    return flags[:k].astype(bool), lhs[:k], rhs[:k]
+
+
+def sets(n, pairs):
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    label = np.empty(max(n, 1), np.int32)
+    ns = lib().orc_sets(n, pairs.shape[0], _i(pairs), _i(label))
+    return label[:n], int(ns)
+
+
+def transition(s, rcrit):
+    K, Kp, Kpp = C.c_double(), C.c_double(), C.c_double()
+    lib().orc_transition(s, rcrit, C.byref(K), C.byref(Kp), C.byref(Kpp))
+    return K.value, Kp.value, Kpp.value
+
+
+def correct_set(members, m, q, v, G, rcrit, dt):
+    mem = np.ascontiguousarray(members, dtype=np.int32)
+    v = _f64(v, (-1, 3)).copy()
+    lib().orc_correct_set(mem.shape[0], _i(mem), _d(_f64(m)), _d(_f64(q, (-1, 3))), _d(v), G,
+                          rcrit, dt)
+    return v
+
+
+def hermite_force(mm, x, u, G, mu, rcrit, eps):
+    x = _f64(x, (-1, 3)); u = _f64(u, (-1, 3)); mm = _f64(mm)
+    a = np.empty_like(x); j = np.empty_like(x)
+    lib().orc_hermite_force(x.shape[0], _d(mm), _d(x), _d(u), G, mu, rcrit, eps, _d(a), _d(j))
+    return a, j
+
+
+def hermite_set(members, m, q, v, params: Params, rcrit, dt):
+    mem = np.ascontiguousarray(members, dtype=np.int32)
+    q = _f64(q, (-1, 3)).copy(); v = _f64(v, (-1, 3)).copy()
+    ns = lib().orc_hermite_set(mem.shape[0], _i(mem), _d(_f64(m)), _d(q), _d(v),
+                               C.byref(params), rcrit, dt)
+    return q, v, int(ns)
+
+
+def hkep_set(members, m, q, v, params: Params, rcrit):
+    mem = np.ascontiguousarray(members, dtype=np.int32)
+    return lib().orc_hkep_set(mem.shape[0], _i(mem), _d(_f64(m)), _d(_f64(q, (-1, 3))),
+                              _d(_f64(v, (-1, 3))), C.byref(params), rcrit)
+
+
+def energy(G, m0, m, q, v):
+    q = _f64(q, (-1, 3)); v = _f64(v, (-1, 3))
+    return lib().orc_energy(q.shape[0], G, m0, _d(_f64(m)), _d(q), _d(v))
+
+
+def angmom(m, q, v):
+    q = _f64(q, (-1, 3)); v = _f64(v, (-1, 3))
+    L = np.zeros(3)
+    lib().orc_angmom(q.shape[0], _d(_f64(m)), _d(q), _d(v), _d(L))
+    return L
+
+
+class StepResult:
+    def __init__(self, rc, pairs, label, stats):
+        self.rc = rc
+        self.pairs = pairs
+        self.label = label
+        self.stats = stats
+
+
+def step(params: Params, tau, m, h, q, v, cand_cap=None, enc_cap=None):
+    """One hybrid step; returns (q, v, StepResult)."""
+    q = _f64(q, (-1, 3)).copy(); v = _f64(v, (-1, 3)).copy()
+    n = q.shape[0]
+    cand_cap = 8 * n + 64 if cand_cap is None else cand_cap
+    enc_cap = cand_cap if enc_cap is None else enc_cap
+    pairs = np.zeros((max(enc_cap, 1), 2), np.int32)
+    label = np.zeros(max(n, 1), np.int32)
+    st = Stats()
+    rc = lib().orc_step(n, C.byref(params), tau, _d(_f64(m)), _d(_f64(h)), _d(q), _d(v), cand_cap,
+                        _i(pairs), enc_cap, _i(label), C.byref(st))
+    ne = min(st.n_encounters, enc_cap)
+    return q, v, StepResult(rc, pairs[:ne].copy(), label[:n].copy(), st.as_dict())
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def set_threads(k: int) -> None:
+    lib().orc_set_threads(int(k))
