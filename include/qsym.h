@@ -1,0 +1,186 @@
+/*
+ * qsym.h -- C ABI of the MI355X (gfx950) library for the democratic-
+ * heliocentric (DH) hybrid symplectic step of Moore & Quillen, "QYMSYM: A
+ * GPU-Accelerated Hybrid Symplectic Integrator That Permits Close
+ * Encounters" (arXiv:1007.3458).
+ *
+ * One step (Sec. 2, second-order composition; Sec. 2.3, steps 1-10):
+ *   E_Dft(tau/2) E_Int(tau/2) E_Kep(tau) E_Int(tau/2) E_Dft(tau/2)
+ * with the close-encounter machinery between the Kepler advance and the
+ * second kick: crude sweep (fused into the first kick), fine sweep, division
+ * into non-intersecting encounter sets, transition-weighted corrections and
+ * 4th-order Hermite substeps for the members of each set (Secs. 2.1, 2.2,
+ * 2.4).  Everything runs on the device; the host is crossed only by the
+ * calls below.
+ *
+ * Conventions for every entry point:
+ *  - all sizes are int64_t, all reals double (learned-guess weights float);
+ *  - positions q are heliocentric, velocities v barycentric (barycentric
+ *    momentum / mass, so massless bodies are allowed), both laid out SoA as
+ *    [3][ntot]: q[0*ntot + i] = x_i, q[1*ntot + i] = y_i, q[2*ntot + i] = z_i;
+ *  - the central mass of each system is a parameter, never a body;
+ *  - `where` is QSYM_HOST (pointer to host memory, copied synchronously) or
+ *    QSYM_DEVICE (pointer to device memory, copied on the context stream);
+ *  - the caller owns every pointer it passes; the library keeps none of
+ *    them except the workspace bound at creation, which must stay allocated
+ *    and untouched until qsym_destroy;
+ *  - return 0 on success or a negative QSYM_E* code; no exception crosses
+ *    the ABI; qsym_last_error() gives a message for the last failure;
+ *  - one context per stream; a context is not thread-safe.
+ * Device work is asynchronous on the context's stream; errors detected on
+ * the device (overflow, non-finite state, solver caps) are latched in a
+ * status word and reported by the next synchronising call (qsym_sync,
+ * qsym_get_state, qsym_energy, qsym_encounters, qsym_stats).
+ */
+#ifndef QSYM_H
+#define QSYM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QSYM_OK 0
+#define QSYM_EINVAL -1     /* bad argument                                     */
+#define QSYM_ENOMEM -2     /* workspace too small                              */
+#define QSYM_EHIP -3       /* HIP runtime error                                */
+#define QSYM_ENONFINITE -4 /* NaN/Inf appeared in the state                    */
+#define QSYM_EKEPLER -5    /* Kepler solver reached its iteration cap          */
+#define QSYM_EOVERFLOW -6  /* candidate or encounter capacity exceeded          */
+#define QSYM_ETRUNC -7     /* output buffer shorter than the true count         */
+#define QSYM_EHERMITE -8   /* Hermite reached its substep cap / set too large   */
+
+#define QSYM_HOST 0
+#define QSYM_DEVICE 1
+
+/* Parameters (Sec. 2.5, list of parameters). */
+typedef struct qsym_params {
+    double G;            /* gravitational constant                              */
+    double aE;           /* Hill factor of encounter identification (Sec. 2.4)  */
+    double aH;           /* Hill factor of r_crit (Sec. 2.2, eq. for r_crit)    */
+    double epsH;         /* Hermite smoothing length (in-set pairs only)         */
+    double eta;          /* Hermite accuracy parameter of the step criterion     */
+    double eta_s;        /* Hermite accuracy parameter of the first step         */
+    double crude_safety; /* multiplicative slack of the crude sweep, >= 1        */
+    int32_t hill_mode;   /* 0: a_E x mutual Hill radius; 1: a_E x sum of radii   */
+    int32_t kepler_mode; /* 0: Laguerre from x = r0 (Appendix A); 1: Newton from
+                            sqrt(mu) dt / r0; 2: Newton from the learned guess   */
+    int32_t precision;   /* 0: FP64 pair terms; 1: FP32 pair terms on FP64
+                            separations with FP64 tile accumulation            */
+    int32_t max_substeps;/* Hermite substep cap per set per step (>= 1)           */
+    int64_t pair_capacity; /* crude-candidate capacity; 0 selects 8*ntot + 1024  */
+} qsym_params;
+
+/* Counters of the last step and totals since creation/reset. */
+typedef struct qsym_stats_t {
+    int64_t steps;            /* steps taken since creation                    */
+    int64_t n_candidates;     /* last step: crude-sweep pairs (true count)     */
+    int64_t n_encounters;     /* last step: fine-sweep pairs                   */
+    int64_t n_sets;           /* last step: encounter sets                     */
+    int64_t max_set;          /* last step: members of the largest set         */
+    int64_t substeps;         /* last step: Hermite substeps summed over sets  */
+    int64_t total_encounters; /* all steps                                     */
+    int64_t total_substeps;   /* all steps                                     */
+    int64_t kepler_iters;     /* all steps: Kepler iterations summed           */
+    int64_t kepler_max;       /* all steps: largest iteration count            */
+    int64_t kepler_hist[32];  /* all steps: solves by iteration count          */
+    int64_t status;           /* latched device status bits                    */
+    double phase_us[12];      /* per-kernel time when profiling is enabled     */
+    int64_t phase_calls[12];  /* launches timed per kernel                     */
+} qsym_stats_t;
+
+typedef struct qsym_ctx qsym_ctx;
+
+/* Device workspace needed by a context of nsys systems whose bodies are
+ * offsets[s] .. offsets[s+1]-1 (offsets has nsys+1 entries, offsets[0] = 0,
+ * non-decreasing; a system may be empty).  Writes the size in bytes. */
+int qsym_workspace_bytes(const qsym_params *p, int32_t nsys, const int64_t *offsets,
+                         int64_t *bytes);
+
+/* Create a context over a caller-allocated device workspace of ws_bytes
+ * (>= qsym_workspace_bytes, 256-byte aligned) used on `stream` (a
+ * hipStream_t; NULL for the default stream).  m0 (host, nsys entries) are
+ * the central masses.  The state is zero until qsym_set_state. */
+int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, const double *m0,
+                void *workspace, int64_t ws_bytes, void *stream, qsym_ctx **out);
+void qsym_destroy(qsym_ctx *ctx);
+
+/* Load masses m[ntot], Hill factors h[ntot] = cbrt(m / (3 m0)) (computed by
+ * the caller once so every implementation uses the same bits), positions
+ * and velocities (SoA [3][ntot]). */
+int qsym_set_state(qsym_ctx *ctx, const double *m, const double *h, const double *q,
+                   const double *v, int32_t where);
+int qsym_get_state(qsym_ctx *ctx, double *q, double *v, int32_t where);
+
+/* nsteps hybrid steps of size tau (Sec. 2.3).  Asynchronous: the first call
+ * for a given tau captures one step into a HIP graph that is replayed
+ * nsteps times.  A negative tau integrates backwards (used with a_E = 0). */
+int qsym_step(qsym_ctx *ctx, double tau, int64_t nsteps);
+
+/* Wait for the context's work; return the latched device status as a code. */
+int qsym_sync(qsym_ctx *ctx);
+
+/* Total energy of each system (H_Dft + H_Kep + H_Int, Sec. 2), E[nsys] on
+ * the host.  Synchronises. */
+int qsym_energy(qsym_ctx *ctx, double *E);
+
+/* Encounter pairs of the last step (global body indices, i < j,
+ * lexicographically sorted) into pairs[2*cap] (host); *n_pairs receives the
+ * true count (QSYM_ETRUNC if above cap).  set_id (host, ntot entries, may
+ * be NULL) receives each body's set index (sets ordered by their smallest
+ * member) or -1.  Synchronises. */
+int qsym_encounters(qsym_ctx *ctx, int32_t *pairs, int64_t cap, int64_t *n_pairs,
+                    int32_t *set_id);
+
+/* Candidate pairs of the last crude sweep (unordered, i < j) into
+ * pairs[2*cap] (host); *n receives the true count.  Synchronises. */
+int qsym_candidates(qsym_ctx *ctx, int32_t *pairs, int64_t cap, int64_t *n);
+
+int qsym_stats(qsym_ctx *ctx, qsym_stats_t *out);
+const char *qsym_last_error(const qsym_ctx *ctx);
+
+/* Operator-level entry points running the step's own kernels on the
+ * context state, for operator-by-operator checks.
+ *  drift:  E_Dft(dt) (Sec. 2, H_Dft).
+ *  kick:   E_Int(dt) over all pairs without K (Sec. 2, H_Int); when
+ *          crude_tau != 0 the per-body quantities are recomputed at the
+ *          current state and the crude sweep of Sec. 2.4 with step
+ *          crude_tau is fused in (read it with qsym_candidates).
+ *  kepler: E_Kep(dt) of every body (Appendix A).  */
+int qsym_apply_drift(qsym_ctx *ctx, double dt);
+int qsym_apply_kick(qsym_ctx *ctx, double dt, double crude_tau);
+int qsym_apply_kepler(qsym_ctx *ctx, double dt);
+
+/* Fine sweep of Sec. 2.4 on caller data (all device pointers, SoA [3][n]
+ * for q0, v0, q1, v1): flags[k] = 1 when candidate k = (pairs[2k],
+ * pairs[2k+1]) approaches within a_E x Hill radius over the step, with the
+ * two sides of the comparison in lhs[k], rhs[k] (may be NULL).  Stateless;
+ * runs on `stream` and synchronises it. */
+int qsym_fine_test(const qsym_params *p, double m0, double tau, int64_t n, const double *m,
+                   const double *h, const double *A, const double *q0, const double *v0,
+                   const double *q1, const double *v1, int64_t npairs, const int32_t *pairs,
+                   int32_t *flags, double *lhs, double *rhs, void *stream);
+
+/* Kick-kernel launch shape chosen by the autotuner (or forced here):
+ * ipl = i-bodies per lane (1, 2, 4), block = threads per workgroup (128,
+ * 256), jchunk = j-bodies per workgroup (multiple of block), remap = 1 for
+ * the XCD-aware workgroup order.  qsym_autotune times the candidate shapes
+ * on the current state and keeps the fastest; *us receives its kick time. */
+int qsym_set_kick_shape(qsym_ctx *ctx, int32_t ipl, int32_t block, int64_t jchunk, int32_t remap);
+int qsym_get_kick_shape(qsym_ctx *ctx, int32_t *ipl, int32_t *block, int64_t *jchunk,
+                        int32_t *remap);
+int qsym_autotune(qsym_ctx *ctx, double tau, double *us);
+
+/* Profiling: when enabled, qsym_step launches kernels directly (no graph)
+ * with HIP events around each launch, accumulating per-kernel time into
+ * qsym_stats_t.phase_us.  Kernel index order: 0 drift+prepass, 1 kick with
+ * crude sweep, 2 kick apply + Kepler, 3 fine sweep, 4 sets, 5 Hermite,
+ * 6 second kick, 7 kick apply + momentum, 8 final drift, 9 energy. */
+int qsym_profile(qsym_ctx *ctx, int32_t enable);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QSYM_H */

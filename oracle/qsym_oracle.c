@@ -650,7 +650,7 @@ int64_t orc_hermite_set(int64_t nm, const int32_t *mem, const double *m, double 
     }
     double t = 0.0;
     int64_t nsub = 0;
-    int last = 0;
+    int last = (T == 0.0); /* a zero step leaves the set unchanged */
     while (!last) {
         if (nsub >= p->max_substeps) { nsub = -nsub - 1; break; }
         if (!(h > 0.0) || h >= T - t) { h = T - t; last = 1; }

@@ -1,0 +1,952 @@
+// qsym.hip -- host side of the MI355X DH hybrid-step library: workspace
+// layout, work tables, kernel launches, HIP-graph capture of one step, the
+// kick autotuner and the C ABI declared in include/qsym.h.
+#include "qsym.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qsym_kernels.hpp"
+
+using namespace qsym;
+
+namespace {
+
+constexpr int kPhases = 12;
+enum Phase {
+    P_DRIFT = 0, P_KICK1, P_APPLY1, P_FINE, P_SETS, P_HERMITE, P_KICK2, P_APPLY2, P_DRIFT2,
+    P_ENERGY, P_MOMENTUM, P_OTHER
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Shape {
+    int ipl = 2;
+    int block = 256;
+    long long jchunk = 1024;
+    int remap = 1;
+};
+
+// workspace layout: byte offsets of every array
+struct Layout {
+    size_t off_state = 0, off_snap = 0, off_aux = 0, off_acc = 0, off_pm = 0, off_bsys = 0;
+    size_t off_sysoff = 0, off_sysm0 = 0, off_sysS = 0, off_syspoff = 0, off_sysc0 = 0;
+    size_t off_bchunk = 0, off_items = 0, off_eitems = 0, off_syse0 = 0, off_cand = 0;
+    size_t off_enc = 0, off_encs = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0;
+    size_t off_hw = 0, off_ctr = 0, off_epart = 0, off_E = 0, off_mlp = 0;
+    size_t total = 0;
+    long long np = 0;          // padded body count
+    long long acc_len = 0;     // doubles of kick partials
+    long long nchunks = 0;     // O(N) chunks
+    long long max_items = 0;   // kick items of the finest allowed shape
+    long long n_eitems = 0;
+    long long cap = 0;         // candidate capacity
+    long long jchunk_min = 128;
+};
+
+struct Tables {
+    std::vector<int> sys_off, sys_S, sys_c0, sys_e0;
+    std::vector<long long> sys_poff;
+    std::vector<int4> bchunk;
+    std::vector<KickItem> eitems;
+    std::vector<int> body_sys;
+};
+
+int nsys_bodies(const std::vector<long long> &off, int s) { return (int)(off[s + 1] - off[s]); }
+
+long long jchunk_min_for(const std::vector<long long> &off)
+{
+    long long nmax = 0;
+    for (size_t s = 0; s + 1 < off.size(); ++s) nmax = std::max(nmax, off[s + 1] - off[s]);
+    long long jm = (nmax + kSMax - 1) / kSMax;
+    jm = std::max<long long>(128, (jm + 127) / 128 * 128);
+    return jm;
+}
+
+Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
+{
+    Layout L;
+    const int nsys = (int)off.size() - 1;
+    const long long ntot = off.back();
+    L.np = std::max<long long>(256, (long long)align_up((size_t)ntot, 256));
+    L.jchunk_min = jchunk_min_for(off);
+    L.acc_len = 0;
+    L.nchunks = 0;
+    L.max_items = 0;
+    L.n_eitems = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const long long n = off[s + 1] - off[s];
+        const long long S = (n + L.jchunk_min - 1) / L.jchunk_min;
+        L.acc_len += 3 * S * n;
+        L.nchunks += (n + kChunk - 1) / kChunk;
+        L.max_items += ((n + 127) / 128) * S;
+        L.n_eitems += ((n + 255) / 256) * ((n + 1023) / 1024);
+    }
+    L.acc_len = std::max<long long>(L.acc_len, 3);
+    L.nchunks = std::max<long long>(L.nchunks, 1);
+    L.max_items = std::max<long long>(L.max_items, 1) + 8;
+    L.n_eitems = std::max<long long>(L.n_eitems, 1);
+    L.cap = p.pair_capacity > 0 ? p.pair_capacity : 8 * ntot + 1024;
+    size_t o = 0;
+    auto take = [&](size_t &field, size_t bytes) {
+        o = align_up(o, 256);
+        field = o;
+        o += bytes;
+    };
+    const size_t D = sizeof(double);
+    take(L.off_state, 8 * (size_t)L.np * D);
+    take(L.off_snap, 6 * (size_t)L.np * D);
+    take(L.off_aux, 3 * (size_t)L.np * D);
+    take(L.off_acc, (size_t)L.acc_len * D);
+    take(L.off_pm, 3 * (size_t)L.nchunks * D);
+    take(L.off_bsys, (size_t)L.np * sizeof(int));
+    take(L.off_sysoff, (size_t)(nsys + 1) * sizeof(int));
+    take(L.off_sysm0, (size_t)std::max(nsys, 1) * D);
+    take(L.off_sysS, (size_t)std::max(nsys, 1) * sizeof(int));
+    take(L.off_syspoff, (size_t)std::max(nsys, 1) * sizeof(long long));
+    take(L.off_sysc0, (size_t)(nsys + 1) * sizeof(int));
+    take(L.off_bchunk, (size_t)L.nchunks * sizeof(int4));
+    take(L.off_items, (size_t)L.max_items * sizeof(KickItem));
+    take(L.off_eitems, (size_t)L.n_eitems * sizeof(KickItem));
+    take(L.off_syse0, (size_t)(nsys + 1) * sizeof(int));
+    take(L.off_cand, (size_t)L.cap * sizeof(int2));
+    take(L.off_enc, (size_t)kCapE * sizeof(int2));
+    take(L.off_encs, (size_t)kCapE * sizeof(int2));
+    take(L.off_setstart, (size_t)(kCapU + 1) * sizeof(int));
+    take(L.off_setmem, (size_t)kCapU * sizeof(int));
+    take(L.off_setrc, (size_t)kCapU * D);
+    take(L.off_hw, (size_t)HFIELDS * kCapU * D);
+    take(L.off_ctr, (size_t)C_COUNT * sizeof(unsigned long long));
+    take(L.off_epart, (size_t)L.n_eitems * D);
+    take(L.off_E, (size_t)std::max(nsys, 1) * D);
+    take(L.off_mlp, (size_t)(kMlpParams + 16) * sizeof(float));
+    L.total = align_up(o, 256);
+    return L;
+}
+
+Dev bind(char *base, const Layout &L)
+{
+    Dev d;
+    const long long np = L.np;
+    double *st = (double *)(base + L.off_state);
+    d.x = st;
+    d.y = st + np;
+    d.z = st + 2 * np;
+    d.vx = st + 3 * np;
+    d.vy = st + 4 * np;
+    d.vz = st + 5 * np;
+    d.m = st + 6 * np;
+    d.h = st + 7 * np;
+    double *sn = (double *)(base + L.off_snap);
+    d.x0 = sn;
+    d.y0 = sn + np;
+    d.z0 = sn + 2 * np;
+    d.vx0 = sn + 3 * np;
+    d.vy0 = sn + 4 * np;
+    d.vz0 = sn + 5 * np;
+    double *ax = (double *)(base + L.off_aux);
+    d.A = ax;
+    d.ch = ax + np;
+    d.cv = ax + 2 * np;
+    d.acc = (double *)(base + L.off_acc);
+    d.pm = (double *)(base + L.off_pm);
+    d.body_sys = (int *)(base + L.off_bsys);
+    d.sys_off = (int *)(base + L.off_sysoff);
+    d.sys_m0 = (double *)(base + L.off_sysm0);
+    d.sys_S = (int *)(base + L.off_sysS);
+    d.sys_poff = (long long *)(base + L.off_syspoff);
+    d.sys_c0 = (int *)(base + L.off_sysc0);
+    d.bchunk = (int4 *)(base + L.off_bchunk);
+    d.items = (KickItem *)(base + L.off_items);
+    d.eitems = (KickItem *)(base + L.off_eitems);
+    d.sys_e0 = (int *)(base + L.off_syse0);
+    d.cand = (int2 *)(base + L.off_cand);
+    d.enc = (int2 *)(base + L.off_enc);
+    d.enc_sorted = (int2 *)(base + L.off_encs);
+    d.set_start = (int *)(base + L.off_setstart);
+    d.set_mem = (int *)(base + L.off_setmem);
+    d.set_rc = (double *)(base + L.off_setrc);
+    d.hw = (double *)(base + L.off_hw);
+    d.ctr = (unsigned long long *)(base + L.off_ctr);
+    d.epart = (double *)(base + L.off_epart);
+    d.E = (double *)(base + L.off_E);
+    d.mlp = (float *)(base + L.off_mlp);
+    return d;
+}
+
+}  // namespace
+
+struct qsym_ctx {
+    qsym_params p{};
+    int nsys = 0;
+    std::vector<long long> off;
+    std::vector<double> m0;
+    long long ntot = 0;
+    hipStream_t ustream = nullptr;  // caller's stream
+    hipStream_t stream = nullptr;   // private stream (capturable)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    Layout L;
+    Dev d;
+    char *base = nullptr;
+    Shape shape;
+    int nitems = 0;
+    int grid_kick = 0;
+    Tables T;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    double gtau = 0.0;
+    bool gvalid = false;
+    bool profile = false;
+    hipEvent_t pev[2 * 16] = {};
+    double phase_us[kPhases] = {};
+    long long phase_calls[kPhases] = {};
+    bool mlp_loaded = false;
+    std::string err;
+};
+
+namespace {
+
+int fail(qsym_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), QSYM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int validate(const qsym_params *p, int32_t nsys, const int64_t *offsets, std::string &msg)
+{
+    if (!p || !offsets || nsys < 1) { msg = "null parameters/offsets or nsys < 1"; return QSYM_EINVAL; }
+    if (offsets[0] != 0) { msg = "offsets[0] must be 0"; return QSYM_EINVAL; }
+    for (int s = 0; s < nsys; ++s)
+        if (offsets[s + 1] < offsets[s]) { msg = "offsets must be non-decreasing"; return QSYM_EINVAL; }
+    if (offsets[nsys] >= (1LL << 30)) { msg = "too many bodies (>= 2^30)"; return QSYM_EINVAL; }
+    if (!(p->G > 0) || !(p->aE >= 0) || !(p->aH > 0) || !(p->epsH >= 0) || !(p->eta > 0) ||
+        !(p->eta_s > 0) || !(p->crude_safety >= 1.0)) {
+        msg = "parameter out of range (G, aH, eta, eta_s > 0; aE, epsH >= 0; crude_safety >= 1)";
+        return QSYM_EINVAL;
+    }
+    if (p->hill_mode < 0 || p->hill_mode > 1 || p->kepler_mode < 0 || p->kepler_mode > 2 ||
+        p->precision < 0 || p->precision > 1 || p->max_substeps < 1 || p->pair_capacity < 0) {
+        msg = "mode out of range";
+        return QSYM_EINVAL;
+    }
+    return QSYM_OK;
+}
+
+void build_tables(qsym_ctx *c)
+{
+    Tables &T = c->T;
+    const int nsys = c->nsys;
+    T.sys_off.assign(nsys + 1, 0);
+    T.sys_S.assign(nsys, 0);
+    T.sys_poff.assign(nsys, 0);
+    T.sys_c0.assign(nsys + 1, 0);
+    T.sys_e0.assign(nsys + 1, 0);
+    T.bchunk.clear();
+    T.eitems.clear();
+    T.body_sys.assign((size_t)c->L.np, 0);
+    long long poff = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const int n = nsys_bodies(c->off, s);
+        T.sys_off[s] = (int)c->off[s];
+        T.sys_poff[s] = poff;
+        poff += 3LL * ((n + c->L.jchunk_min - 1) / c->L.jchunk_min) * n;
+        T.sys_c0[s] = (int)T.bchunk.size();
+        for (int b = 0; b < n; b += kChunk)
+            T.bchunk.push_back(make_int4(s, (int)c->off[s] + b, std::min(kChunk, n - b), 0));
+        T.sys_e0[s] = (int)T.eitems.size();
+        for (int ib = 0; ib < n; ib += 256)
+            for (int jb = 0; jb < n; jb += 1024) {
+                KickItem it{s, (int)c->off[s] + ib, std::min(256, n - ib), (int)c->off[s] + jb,
+                            std::min(1024, n - jb), jb / 1024};
+                T.eitems.push_back(it);
+            }
+        for (long long i = c->off[s]; i < c->off[s + 1]; ++i) T.body_sys[i] = s;
+    }
+    T.sys_off[nsys] = (int)c->off[nsys];
+    T.sys_c0[nsys] = (int)T.bchunk.size();
+    T.sys_e0[nsys] = (int)T.eitems.size();
+    if (T.bchunk.empty()) T.bchunk.push_back(make_int4(0, 0, 0, 0));
+    if (T.eitems.empty()) T.eitems.push_back(KickItem{0, 0, 0, 0, 0, 0});
+}
+
+// kick work items for the current shape; systems largest first
+int build_items(qsym_ctx *c, std::vector<KickItem> &items, std::vector<int> &sysS)
+{
+    const Shape &sh = c->shape;
+    const long long BI = (long long)sh.block * sh.ipl;
+    const long long JC = sh.jchunk;
+    items.clear();
+    sysS.assign(c->nsys, 0);
+    std::vector<int> order(c->nsys);
+    for (int s = 0; s < c->nsys; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return nsys_bodies(c->off, a) > nsys_bodies(c->off, b);
+    });
+    for (int s : order) {
+        const int n = nsys_bodies(c->off, s);
+        const int S = (int)((n + JC - 1) / JC);
+        sysS[s] = S;
+        for (int ch = 0; ch < S; ++ch)
+            for (long long ib = 0; ib < n; ib += BI) {
+                KickItem it{s, (int)(c->off[s] + ib), (int)std::min<long long>(BI, n - ib),
+                            (int)(c->off[s] + ch * JC), (int)std::min<long long>(JC, n - ch * JC),
+                            ch};
+                items.push_back(it);
+            }
+    }
+    return (int)items.size();
+}
+
+int upload_shape(qsym_ctx *c)
+{
+    std::vector<KickItem> items;
+    std::vector<int> sysS;
+    const int n = build_items(c, items, sysS);
+    if ((long long)n > c->L.max_items)
+        return fail(c, QSYM_EINVAL, "kick shape needs more work items than the workspace holds");
+    for (int s = 0; s < c->nsys; ++s) {
+        const long long Smax = (nsys_bodies(c->off, s) + c->L.jchunk_min - 1) / c->L.jchunk_min;
+        if (sysS[s] > Smax) return fail(c, QSYM_EINVAL, "j-chunk smaller than the workspace allows");
+    }
+    c->nitems = n;
+    c->grid_kick = std::max(8, (n + 7) / 8 * 8);
+    if (n > 0)
+        HIPCHK(c, hipMemcpyAsync(c->d.items, items.data(), sizeof(KickItem) * n,
+                                 hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d.sys_S, sysS.data(), sizeof(int) * c->nsys, hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->gvalid = false;
+    return QSYM_OK;
+}
+
+// ---------------------------------------------------------------- launches
+template <int BS, int IPL>
+hipError_t launch_kick_bs(qsym_ctx *c, int mode, int prec, hipStream_t st)
+{
+    KickArgs ka{c->d, c->p.G, c->L.cap, c->nitems, c->shape.remap};
+    const dim3 g(c->shape.remap ? c->grid_kick : std::max(c->nitems, 1)), b(BS);
+    if (prec == 0) {
+        if (mode == 0) hipLaunchKernelGGL((k_kick<BS, IPL, 0, 0>), g, b, 0, st, ka);
+        else if (mode == 1) hipLaunchKernelGGL((k_kick<BS, IPL, 1, 0>), g, b, 0, st, ka);
+        else hipLaunchKernelGGL((k_kick<BS, IPL, 2, 0>), g, b, 0, st, ka);
+    } else {
+        if (mode == 0) hipLaunchKernelGGL((k_kick<BS, IPL, 0, 1>), g, b, 0, st, ka);
+        else if (mode == 1) hipLaunchKernelGGL((k_kick<BS, IPL, 1, 1>), g, b, 0, st, ka);
+        else hipLaunchKernelGGL((k_kick<BS, IPL, 2, 1>), g, b, 0, st, ka);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_kick(qsym_ctx *c, int mode, hipStream_t st)
+{
+    const int prec = c->p.precision;
+    const int ipl = c->shape.ipl, bs = c->shape.block;
+    if (c->nitems == 0) return hipSuccess;
+    if (bs == 256) {
+        if (ipl == 1) return launch_kick_bs<256, 1>(c, mode, prec, st);
+        if (ipl == 2) return launch_kick_bs<256, 2>(c, mode, prec, st);
+        return launch_kick_bs<256, 4>(c, mode, prec, st);
+    }
+    if (ipl == 1) return launch_kick_bs<128, 1>(c, mode, prec, st);
+    if (ipl == 2) return launch_kick_bs<128, 2>(c, mode, prec, st);
+    return launch_kick_bs<128, 4>(c, mode, prec, st);
+}
+
+int nblocks_chunks(qsym_ctx *c) { return (int)c->T.bchunk.size(); }
+
+struct Timer {
+    qsym_ctx *c;
+    int ph;
+    Timer(qsym_ctx *cc, int p) : c(cc), ph(p)
+    {
+        if (c->profile) hipEventRecord(c->pev[2 * ph], c->stream);
+    }
+    ~Timer()
+    {
+        if (c->profile) {
+            (void)hipEventRecord(c->pev[2 * ph + 1], c->stream);
+            (void)hipEventSynchronize(c->pev[2 * ph + 1]);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, c->pev[2 * ph], c->pev[2 * ph + 1]);
+            c->phase_us[ph] += 1000.0 * ms;
+            c->phase_calls[ph] += 1;
+        }
+    }
+};
+
+hipError_t run_drift(qsym_ctx *c, double dt, int prepass, double tau_crude, int reset,
+                     hipStream_t st, int phase)
+{
+    Timer tm(c, phase);
+    DriftArgs a{c->d, dt, c->p.G, tau_crude, c->p.aE, c->p.crude_safety, prepass, c->p.hill_mode,
+                reset};
+    hipLaunchKernelGGL(k_drift, dim3(nblocks_chunks(c)), dim3(kChunk), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t run_momentum(qsym_ctx *c, hipStream_t st)
+{
+    Timer tm(c, P_MOMENTUM);
+    hipLaunchKernelGGL(k_momentum, dim3(nblocks_chunks(c)), dim3(kChunk), 0, st, c->d);
+    return hipGetLastError();
+}
+
+hipError_t run_apply(qsym_ctx *c, double dt_kick, double dt_kep, int do_kick, int do_kep,
+                     int snapshot, int momentum, hipStream_t st, int phase)
+{
+    Timer tm(c, phase);
+    ApplyArgs a{c->d, dt_kick, dt_kep, c->p.G, do_kick, do_kep, snapshot, c->p.kepler_mode, momentum};
+    hipLaunchKernelGGL(k_apply_kepler, dim3(nblocks_chunks(c)), dim3(kChunk), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t run_kick(qsym_ctx *c, int crude, hipStream_t st, int phase)
+{
+    Timer tm(c, phase);
+    return launch_kick(c, crude ? 1 + c->p.hill_mode : 0, st);
+}
+
+int fine_grid(qsym_ctx *c)
+{
+    long long g = (c->L.cap + 255) / 256;
+    return (int)std::max<long long>(1, std::min<long long>(g, 2048));
+}
+
+// one full hybrid step (Sec. 2.3) enqueued on st
+hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
+{
+    hipError_t e;
+    const double half = tau / 2.0;
+    // 1: drift tau/2 + per-body encounter terms, reset per-step counters
+    if ((e = run_drift(c, half, 1, tau, 1, st, P_DRIFT)) != hipSuccess) return e;
+    // 2: kick tau/2 with the crude sweep fused in
+    if ((e = run_kick(c, 1, st, P_KICK1)) != hipSuccess) return e;
+    // 2-3: apply the kick, snapshot (q0, v0), Kepler tau -> (q1, v1)
+    if ((e = run_apply(c, half, tau, 1, 1, 1, 0, st, P_APPLY1)) != hipSuccess) return e;
+    // 4: fine sweep, sets, r_crit
+    {
+        Timer tm(c, P_FINE);
+        FineArgs fa{c->d, tau, c->p.aE, c->L.cap, c->p.hill_mode};
+        hipLaunchKernelGGL(k_fine, dim3(fine_grid(c)), dim3(256), 0, st, fa);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+        Timer tm(c, P_SETS);
+        SetsArgs sa{c->d, c->p.aH};
+        hipLaunchKernelGGL(k_sets, dim3(1), dim3(kSetsThreads), 0, st, sa);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // 5-7: corrections and Hermite per set
+    {
+        Timer tm(c, P_HERMITE);
+        HermArgs ha{c->d, tau, c->p.G, c->p.epsH, c->p.eta, c->p.eta_s, c->p.max_substeps};
+        hipLaunchKernelGGL(k_hermite, dim3(512), dim3(kHermThreads), 0, st, ha);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // 9: kick tau/2 (all pairs), applied with the momentum partials
+    if ((e = run_kick(c, 0, st, P_KICK2)) != hipSuccess) return e;
+    if ((e = run_apply(c, half, 0.0, 1, 0, 0, 1, st, P_APPLY2)) != hipSuccess) return e;
+    // 10: drift tau/2
+    if ((e = run_drift(c, half, 0, 0.0, 0, st, P_DRIFT2)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_count_step, dim3(1), dim3(1), 0, st, c->d);
+    return hipGetLastError();
+}
+
+void enter(qsym_ctx *c)
+{
+    (void)hipEventRecord(c->ev_in, c->ustream);
+    (void)hipStreamWaitEvent(c->stream, c->ev_in, 0);
+}
+
+void leave(qsym_ctx *c)
+{
+    (void)hipEventRecord(c->ev_out, c->stream);
+    (void)hipStreamWaitEvent(c->ustream, c->ev_out, 0);
+}
+
+int status_code(qsym_ctx *c, unsigned long long st)
+{
+    if (st & S_NONFINITE) return fail(c, QSYM_ENONFINITE, "non-finite value in the state");
+    if (st & (S_CAND_OVF | S_ENC_OVF))
+        return fail(c, QSYM_EOVERFLOW, (st & S_CAND_OVF)
+                                           ? "crude-candidate capacity exceeded"
+                                           : "more encounter pairs than the set kernel holds");
+    if (st & (S_HERMITE | S_SET_BIG))
+        return fail(c, QSYM_EHERMITE, "Hermite substep cap reached or set too large");
+    if (st & S_KEPLER) return fail(c, QSYM_EKEPLER, "Kepler solver reached its iteration cap");
+    return QSYM_OK;
+}
+
+int read_ctr(qsym_ctx *c, unsigned long long *h)
+{
+    HIPCHK(c, hipMemcpyAsync(h, c->d.ctr, sizeof(unsigned long long) * C_COUNT,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return QSYM_OK;
+}
+
+int sync_status(qsym_ctx *c)
+{
+    unsigned long long h[C_COUNT];
+    int rc = read_ctr(c, h);
+    if (rc) return rc;
+    return status_code(c, h[C_STATUS]);
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+int qsym_workspace_bytes(const qsym_params *p, int32_t nsys, const int64_t *offsets, int64_t *bytes)
+{
+    std::string msg;
+    int rc = validate(p, nsys, offsets, msg);
+    if (rc) return rc;
+    if (!bytes) return QSYM_EINVAL;
+    std::vector<long long> off(offsets, offsets + nsys + 1);
+    *bytes = (int64_t)make_layout(*p, off).total;
+    return QSYM_OK;
+}
+
+int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, const double *m0,
+                void *workspace, int64_t ws_bytes, void *stream, qsym_ctx **out)
+{
+    if (!out) return QSYM_EINVAL;
+    *out = nullptr;
+    std::string msg;
+    int rc = validate(p, nsys, offsets, msg);
+    if (rc) return rc;
+    if (!m0 || !workspace) return QSYM_EINVAL;
+    for (int s = 0; s < nsys; ++s)
+        if (!(m0[s] > 0)) return QSYM_EINVAL;
+    if (((uintptr_t)workspace) % 256) return QSYM_EINVAL;
+    qsym_ctx *c = new qsym_ctx();
+    c->p = *p;
+    c->nsys = nsys;
+    c->off.assign(offsets, offsets + nsys + 1);
+    c->m0.assign(m0, m0 + nsys);
+    c->ntot = c->off.back();
+    c->L = make_layout(*p, c->off);
+    if ((long long)ws_bytes < (long long)c->L.total) {
+        delete c;
+        return QSYM_ENOMEM;
+    }
+    c->base = (char *)workspace;
+    c->d = bind(c->base, c->L);
+    c->ustream = (hipStream_t)stream;
+    auto bail = [&](int code) {
+        if (c->stream) hipStreamDestroy(c->stream);
+        delete c;
+        return code;
+    };
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(QSYM_EHIP);
+    if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess) return bail(QSYM_EHIP);
+    if (hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) return bail(QSYM_EHIP);
+    for (int k = 0; k < 32; ++k)
+        if (hipEventCreate(&c->pev[k]) != hipSuccess) return bail(QSYM_EHIP);
+    build_tables(c);
+    enter(c);
+    hipStream_t st = c->stream;
+    // zero the whole workspace once (outside any graph)
+    if (hipMemsetAsync(c->base, 0, c->L.total, st) != hipSuccess) return bail(QSYM_EHIP);
+    const Tables &T = c->T;
+    bool ok = true;
+    ok &= hipMemcpyAsync(c->d.sys_off, T.sys_off.data(), sizeof(int) * T.sys_off.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.sys_m0, c->m0.data(), sizeof(double) * nsys, hipMemcpyHostToDevice,
+                         st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.sys_poff, T.sys_poff.data(), sizeof(long long) * nsys,
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.sys_c0, T.sys_c0.data(), sizeof(int) * T.sys_c0.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.sys_e0, T.sys_e0.data(), sizeof(int) * T.sys_e0.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.bchunk, T.bchunk.data(), sizeof(int4) * T.bchunk.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.eitems, T.eitems.data(), sizeof(KickItem) * T.eitems.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.body_sys, T.body_sys.data(), sizeof(int) * T.body_sys.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) return bail(QSYM_EHIP);
+    // default kick shape: block 256, 2 i per lane, j-split so that the
+    // grid has >= 2048 workgroups where the size allows
+    c->shape.block = 256;
+    c->shape.ipl = 2;
+    long long nmax = 0;
+    for (int s = 0; s < nsys; ++s) nmax = std::max<long long>(nmax, nsys_bodies(c->off, s));
+    long long jc = 4096;
+    long long nib = 0;
+    for (int s = 0; s < nsys; ++s) nib += (nsys_bodies(c->off, s) + 511) / 512;
+    while (jc > c->L.jchunk_min) {
+        long long items = 0;
+        for (int s = 0; s < nsys; ++s) {
+            const long long n = nsys_bodies(c->off, s);
+            items += ((n + 511) / 512) * ((n + jc - 1) / jc);
+        }
+        if (items >= 2048) break;
+        jc /= 2;
+    }
+    c->shape.jchunk = std::max<long long>(jc, c->L.jchunk_min);
+    c->shape.jchunk = (c->shape.jchunk + 255) / 256 * 256;
+    c->shape.remap = 1;
+    (void)nib;
+    (void)nmax;
+    if (upload_shape(c) != QSYM_OK) return bail(QSYM_EINVAL);
+    leave(c);
+    *out = c;
+    return QSYM_OK;
+}
+
+void qsym_destroy(qsym_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    for (int k = 0; k < 32; ++k)
+        if (c->pev[k]) hipEventDestroy(c->pev[k]);
+    if (c->ev_in) hipEventDestroy(c->ev_in);
+    if (c->ev_out) hipEventDestroy(c->ev_out);
+    if (c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+int qsym_set_state(qsym_ctx *c, const double *m, const double *h, const double *q, const double *v,
+                   int32_t where)
+{
+    if (!c || !m || !h || !q || !v || (where != QSYM_HOST && where != QSYM_DEVICE))
+        return fail(c, QSYM_EINVAL, "set_state: bad argument");
+    const long long n = c->ntot;
+    const hipMemcpyKind kind = where == QSYM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    enter(c);
+    hipStream_t st = c->stream;
+    const size_t B = sizeof(double) * (size_t)n;
+    if (n > 0) {
+        HIPCHK(c, hipMemcpyAsync(c->d.m, m, B, kind, st));
+        HIPCHK(c, hipMemcpyAsync(c->d.h, h, B, kind, st));
+        double *qd[3] = {c->d.x, c->d.y, c->d.z};
+        double *vd[3] = {c->d.vx, c->d.vy, c->d.vz};
+        for (int k = 0; k < 3; ++k) {
+            HIPCHK(c, hipMemcpyAsync(qd[k], q + k * n, B, kind, st));
+            HIPCHK(c, hipMemcpyAsync(vd[k], v + k * n, B, kind, st));
+        }
+    }
+    HIPCHK(c, run_momentum(c, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    leave(c);
+    return QSYM_OK;
+}
+
+int qsym_get_state(qsym_ctx *c, double *q, double *v, int32_t where)
+{
+    if (!c || (where != QSYM_HOST && where != QSYM_DEVICE)) return fail(c, QSYM_EINVAL, "get_state: bad argument");
+    const long long n = c->ntot;
+    const hipMemcpyKind kind = where == QSYM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    enter(c);
+    hipStream_t st = c->stream;
+    const size_t B = sizeof(double) * (size_t)n;
+    const double *qd[3] = {c->d.x, c->d.y, c->d.z};
+    const double *vd[3] = {c->d.vx, c->d.vy, c->d.vz};
+    for (int k = 0; k < 3 && n > 0; ++k) {
+        if (q) HIPCHK(c, hipMemcpyAsync(q + k * n, qd[k], B, kind, st));
+        if (v) HIPCHK(c, hipMemcpyAsync(v + k * n, vd[k], B, kind, st));
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    leave(c);
+    return sync_status(c);
+}
+
+int qsym_step(qsym_ctx *c, double tau, int64_t nsteps)
+{
+    if (!c || nsteps < 0 || !std::isfinite(tau)) return fail(c, QSYM_EINVAL, "step: bad argument");
+    if (nsteps == 0 || c->ntot == 0) return QSYM_OK;
+    enter(c);
+    if (c->profile) {
+        for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, enqueue_step(c, tau, c->stream));
+        leave(c);
+        return QSYM_OK;
+    }
+    if (!c->gvalid || c->gtau != tau) {
+        if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+        if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_step(c, tau, c->stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return fail(c, QSYM_EHIP, std::string("graph capture: ") +
+                                          hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        c->graph = g;
+        HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+        c->gtau = tau;
+        c->gvalid = true;
+    }
+    for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    leave(c);
+    return QSYM_OK;
+}
+
+int qsym_sync(qsym_ctx *c)
+{
+    if (!c) return QSYM_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return sync_status(c);
+}
+
+int qsym_energy(qsym_ctx *c, double *E)
+{
+    if (!c || !E) return fail(c, QSYM_EINVAL, "energy: bad argument");
+    enter(c);
+    hipStream_t st = c->stream;
+    {
+        Timer tm(c, P_ENERGY);
+        hipLaunchKernelGGL(k_energy_pairs, dim3((unsigned)c->T.eitems.size()), dim3(256), 0, st, c->d);
+        HIPCHK(c, hipGetLastError());
+        EnergyArgs ea{c->d, c->p.G};
+        hipLaunchKernelGGL(k_energy_final, dim3(c->nsys), dim3(256), 0, st, ea);
+        HIPCHK(c, hipGetLastError());
+    }
+    HIPCHK(c, hipMemcpyAsync(E, c->d.E, sizeof(double) * c->nsys, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    leave(c);
+    return sync_status(c);
+}
+
+int qsym_encounters(qsym_ctx *c, int32_t *pairs, int64_t cap, int64_t *n_pairs, int32_t *set_id)
+{
+    if (!c || !n_pairs || cap < 0 || (cap > 0 && !pairs)) return fail(c, QSYM_EINVAL, "encounters: bad argument");
+    unsigned long long h[C_COUNT];
+    int rc = read_ctr(c, h);
+    if (rc) return rc;
+    const long long ne = (long long)h[C_ENC];
+    *n_pairs = ne;
+    const long long held = std::min<long long>(ne, kCapE);
+    const long long k = std::min<long long>(held, cap);
+    hipStream_t st = c->stream;
+    if (k > 0)
+        HIPCHK(c, hipMemcpyAsync(pairs, c->d.enc_sorted, sizeof(int2) * k, hipMemcpyDeviceToHost, st));
+    if (set_id) {
+        for (long long i = 0; i < c->ntot; ++i) set_id[i] = -1;
+        const long long ns = (long long)h[C_NSETS], nu = (long long)h[C_NU];
+        if (ns > 0 && ne <= kCapE) {
+            std::vector<int> start(ns + 1), mem(nu);
+            HIPCHK(c, hipMemcpyAsync(start.data(), c->d.set_start, sizeof(int) * (ns + 1),
+                                     hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipMemcpyAsync(mem.data(), c->d.set_mem, sizeof(int) * nu, hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            for (long long s = 0; s < ns; ++s)
+                for (int b = start[s]; b < start[s + 1]; ++b) set_id[mem[b]] = (int32_t)s;
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    rc = status_code(c, h[C_STATUS]);
+    if (rc) return rc;
+    if (ne > cap) return fail(c, QSYM_ETRUNC, "encounter buffer shorter than the count");
+    return QSYM_OK;
+}
+
+int qsym_candidates(qsym_ctx *c, int32_t *pairs, int64_t cap, int64_t *n)
+{
+    if (!c || !n || cap < 0 || (cap > 0 && !pairs)) return fail(c, QSYM_EINVAL, "candidates: bad argument");
+    unsigned long long h[C_COUNT];
+    int rc = read_ctr(c, h);
+    if (rc) return rc;
+    const long long nc = (long long)h[C_CAND];
+    *n = nc;
+    const long long k = std::min<long long>(std::min<long long>(nc, c->L.cap), cap);
+    if (k > 0) {
+        HIPCHK(c, hipMemcpyAsync(pairs, c->d.cand, sizeof(int2) * k, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (nc > c->L.cap) return fail(c, QSYM_EOVERFLOW, "crude-candidate capacity exceeded");
+    if (nc > cap) return fail(c, QSYM_ETRUNC, "candidate buffer shorter than the count");
+    return QSYM_OK;
+}
+
+int qsym_stats(qsym_ctx *c, qsym_stats_t *out)
+{
+    if (!c || !out) return QSYM_EINVAL;
+    unsigned long long h[C_COUNT];
+    int rc = read_ctr(c, h);
+    if (rc) return rc;
+    std::memset(out, 0, sizeof(*out));
+    out->steps = (int64_t)h[C_STEPS];
+    out->n_candidates = (int64_t)h[C_CAND];
+    out->n_encounters = (int64_t)h[C_ENC];
+    out->n_sets = (int64_t)h[C_NSETS];
+    out->max_set = (int64_t)h[C_MAXSET];
+    out->substeps = (int64_t)h[C_SUB];
+    out->total_encounters = (int64_t)h[C_TENC];
+    out->total_substeps = (int64_t)h[C_TSUB];
+    out->kepler_iters = (int64_t)h[C_KIT];
+    out->kepler_max = (int64_t)h[C_KMAX];
+    for (int k = 0; k < kHist; ++k) out->kepler_hist[k] = (int64_t)h[C_HIST + k];
+    out->status = (int64_t)h[C_STATUS];
+    for (int k = 0; k < kPhases; ++k) {
+        out->phase_us[k] = c->phase_us[k];
+        out->phase_calls[k] = c->phase_calls[k];
+    }
+    return QSYM_OK;
+}
+
+const char *qsym_last_error(const qsym_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int qsym_apply_drift(qsym_ctx *c, double dt)
+{
+    if (!c) return QSYM_EINVAL;
+    enter(c);
+    HIPCHK(c, run_drift(c, dt, 0, 0.0, 0, c->stream, P_DRIFT));
+    leave(c);
+    return QSYM_OK;
+}
+
+int qsym_apply_kick(qsym_ctx *c, double dt, double crude_tau)
+{
+    if (!c) return QSYM_EINVAL;
+    enter(c);
+    hipStream_t st = c->stream;
+    const int crude = crude_tau != 0.0;
+    if (crude) HIPCHK(c, run_drift(c, 0.0, 1, crude_tau, 1, st, P_DRIFT));
+    HIPCHK(c, run_kick(c, crude, st, crude ? P_KICK1 : P_KICK2));
+    HIPCHK(c, run_apply(c, dt, 0.0, 1, 0, 0, 1, st, P_APPLY2));
+    leave(c);
+    return QSYM_OK;
+}
+
+int qsym_apply_kepler(qsym_ctx *c, double dt)
+{
+    if (!c) return QSYM_EINVAL;
+    enter(c);
+    HIPCHK(c, run_apply(c, 0.0, dt, 0, 1, 0, 1, c->stream, P_APPLY1));
+    leave(c);
+    return QSYM_OK;
+}
+
+int qsym_fine_test(const qsym_params *p, double m0, double tau, int64_t n, const double *m,
+                   const double *h, const double *A, const double *q0, const double *v0,
+                   const double *q1, const double *v1, int64_t npairs, const int32_t *pairs,
+                   int32_t *flags, double *lhs, double *rhs, void *stream)
+{
+    if (!p || npairs < 0 || n < 0 || !(m0 > 0)) return QSYM_EINVAL;
+    if (npairs == 0) return QSYM_OK;
+    if (!m || !h || !A || !q0 || !v0 || !q1 || !v1 || !pairs || !flags) return QSYM_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned grid = (unsigned)((npairs + 255) / 256);
+    hipLaunchKernelGGL(k_fine_standalone, dim3(grid), dim3(256), 0, st, p->hill_mode, p->aE, m0, tau,
+                       (long long)n, m, h, A, q0, v0, q1, v1, (long long)npairs, (const int *)pairs,
+                       (int *)flags, lhs, rhs);
+    if (hipGetLastError() != hipSuccess) return QSYM_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return QSYM_EHIP;
+    return QSYM_OK;
+}
+
+int qsym_set_kick_shape(qsym_ctx *c, int32_t ipl, int32_t block, int64_t jchunk, int32_t remap)
+{
+    if (!c) return QSYM_EINVAL;
+    if ((ipl != 1 && ipl != 2 && ipl != 4) || (block != 128 && block != 256) || jchunk <= 0 ||
+        jchunk % block || jchunk < c->L.jchunk_min || (remap != 0 && remap != 1))
+        return fail(c, QSYM_EINVAL, "kick shape out of range");
+    Shape old = c->shape;
+    c->shape.ipl = ipl;
+    c->shape.block = block;
+    c->shape.jchunk = jchunk;
+    c->shape.remap = remap;
+    int rc = upload_shape(c);
+    if (rc) {
+        c->shape = old;
+        (void)upload_shape(c);
+    }
+    return rc;
+}
+
+int qsym_get_kick_shape(qsym_ctx *c, int32_t *ipl, int32_t *block, int64_t *jchunk, int32_t *remap)
+{
+    if (!c) return QSYM_EINVAL;
+    if (ipl) *ipl = c->shape.ipl;
+    if (block) *block = c->shape.block;
+    if (jchunk) *jchunk = c->shape.jchunk;
+    if (remap) *remap = c->shape.remap;
+    return QSYM_OK;
+}
+
+int qsym_autotune(qsym_ctx *c, double tau, double *us)
+{
+    if (!c) return QSYM_EINVAL;
+    if (c->ntot == 0) return QSYM_OK;
+    enter(c);
+    hipStream_t st = c->stream;
+    // the crude sweep needs the per-body terms: compute them at the current
+    // state without moving it (drift by 0)
+    HIPCHK(c, run_drift(c, 0.0, 1, tau, 1, st, P_OTHER));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const Shape keep = c->shape;
+    Shape best = keep;
+    double best_us = 1e300;
+    const int ipls[3] = {1, 2, 4};
+    const int blocks[2] = {128, 256};
+    for (int bi = 0; bi < 2; ++bi)
+        for (int ii = 0; ii < 3; ++ii)
+            for (long long jc = c->L.jchunk_min; jc <= std::max<long long>(c->L.jchunk_min, 8192); jc *= 2) {
+                const long long jcr = (jc + blocks[bi] - 1) / blocks[bi] * blocks[bi];
+                for (int rm = 0; rm < 2; ++rm) {
+                    c->shape = Shape{ipls[ii], blocks[bi], jcr, rm};
+                    if (upload_shape(c) != QSYM_OK) continue;
+                    // warm-up, then 3 timed launches (crude sweep on)
+                    (void)launch_kick(c, 1 + c->p.hill_mode, st);
+                    (void)hipEventRecord(e0, st);
+                    for (int r = 0; r < 3; ++r) launch_kick(c, 1 + c->p.hill_mode, st);
+                    (void)hipEventRecord(e1, st);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    const double t_us = 1000.0 * ms / 3.0;
+                    if (t_us < best_us) {
+                        best_us = t_us;
+                        best = c->shape;
+                    }
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->shape = best;
+    int rc = upload_shape(c);
+    // leave the counters of the next step clean
+    HIPCHK(c, run_drift(c, 0.0, 1, tau, 1, st, P_OTHER));
+    HIPCHK(c, hipStreamSynchronize(st));
+    leave(c);
+    if (us) *us = best_us;
+    return rc;
+}
+
+int qsym_profile(qsym_ctx *c, int32_t enable)
+{
+    if (!c) return QSYM_EINVAL;
+    c->profile = enable != 0;
+    if (enable) {
+        for (int k = 0; k < kPhases; ++k) {
+            c->phase_us[k] = 0.0;
+            c->phase_calls[k] = 0;
+        }
+    }
+    return QSYM_OK;
+}
+
+}  // extern "C"

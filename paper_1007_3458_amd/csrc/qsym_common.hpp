@@ -1,0 +1,83 @@
+// qsym_common.hpp -- device-side data layout shared by the kernels and the
+// host code of the MI355X DH hybrid-step library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qsym {
+
+constexpr int kChunk = 256;        // bodies per workgroup of the O(N) kernels
+constexpr int kCapE = 4096;        // encounter pairs per step handled on chip
+constexpr int kCapU = 2 * kCapE;   // bodies taking part in encounters
+constexpr int kHist = 32;          // Kepler iteration histogram bins
+constexpr int kSMax = 64;          // largest j-split of one system
+constexpr int kSetsThreads = 1024; // workgroup of the set-partition kernel
+constexpr int kHermThreads = 256;  // workgroup of the Hermite kernel
+constexpr int kHermMax = 4096;     // largest encounter set the Hermite accepts
+constexpr int kMlpParams = 1249;   // 4->32->32->1 network
+constexpr double kPi = 3.14159265358979323846;
+
+// counters / status word in device memory (unsigned 64-bit for atomics)
+enum Ctr {
+    C_CAND = 0,   // crude candidates of the last sweep (true count)
+    C_ENC,        // fine-sweep encounter pairs of the last step (true count)
+    C_NSETS,      // sets of the last step
+    C_MAXSET,     // largest set of the last step
+    C_SUB,        // Hermite substeps of the last step
+    C_TENC,       // total encounters
+    C_TSUB,       // total substeps
+    C_KIT,        // total Kepler iterations
+    C_KMAX,       // largest Kepler iteration count
+    C_STEPS,      // steps taken
+    C_STATUS,     // latched status bits
+    C_NU,         // bodies in encounters, last step
+    C_HIST = 16,  // kHist bins
+    C_COUNT = C_HIST + kHist
+};
+
+enum Status : unsigned long long {
+    S_CAND_OVF = 1,
+    S_ENC_OVF = 2,
+    S_KEPLER = 4,
+    S_HERMITE = 8,
+    S_NONFINITE = 16,
+    S_SET_BIG = 32,
+};
+
+// one workgroup of the pair kernels: i-bodies [i0, i0+ni) of system sys
+// against j-bodies [j0, j0+nj) (its j-chunk number `chunk`)
+struct KickItem {
+    int sys, i0, ni, j0, nj, chunk;
+};
+
+// device pointers into the caller-provided workspace
+struct Dev {
+    double *x, *y, *z, *vx, *vy, *vz, *m, *h;   // state (global body index)
+    double *x0, *y0, *z0, *vx0, *vy0, *vz0;     // state after the first kick
+    double *A, *ch, *cv;                        // a_i; crude-sweep per-body terms
+    double *acc;                                // kick partial sums
+    double *pm;                                 // momentum partials [chunk][3]
+    int *body_sys;                              // system of each body
+    int *sys_off;                               // [nsys+1] first body of each system
+    double *sys_m0;                             // central masses
+    int *sys_S;                                 // j-split of each system
+    long long *sys_poff;                        // offset of its partials in acc
+    int *sys_c0;                                // [nsys+1] first O(N) chunk
+    int4 *bchunk;                               // O(N) chunks (sys, first, count, 0)
+    KickItem *items;                            // kick work items
+    KickItem *eitems;                           // energy work items
+    int *sys_e0;                                // [nsys+1] first energy item
+    int2 *cand;                                 // crude candidates
+    int2 *enc;                                  // encounter pairs (append order)
+    int2 *enc_sorted;                           // canonical encounter list
+    int *set_start;                             // [kCapU+1]
+    int *set_mem;                               // [kCapU] member body indices
+    double *set_rc;                             // [kCapU] r_crit per set
+    double *hw;                                 // Hermite member scratch
+    unsigned long long *ctr;                    // counters and status
+    double *epart;                              // energy partials per item
+    double *E;                                  // energies per system
+    float *mlp;                                 // learned-guess weights + scalers
+};
+
+}  // namespace qsym

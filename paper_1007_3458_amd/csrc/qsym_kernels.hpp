@@ -1,0 +1,1237 @@
+// qsym_kernels.hpp -- HIP kernels of the democratic-heliocentric hybrid step
+// (Moore & Quillen, arXiv:1007.3458) for MI355X / gfx950.
+//
+// The translation unit is compiled with -ffp-contract=off: every fused
+// multiply-add below is written out with fma() where it is wanted (pair
+// sums), and the decision paths (per-body semi-major axis, fine encounter
+// test, r_crit) use plain IEEE +, -, *, /, sqrt in a fixed order.
+#pragma once
+#include "qsym_common.hpp"
+
+namespace qsym {
+
+// ------------------------------------------------------------------------
+// small helpers
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double dnorm3(double a, double b, double c)
+{
+    return sqrt(a * a + b * b + c * c);
+}
+
+// Workgroup-wide sum of one double per thread in a fixed tree order (the
+// same bits in every workgroup that reduces the same inputs).
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if (t < s) lds[t] = lds[t] + lds[t + s];
+        __syncthreads();
+    }
+    double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+template <int BS>
+__device__ __forceinline__ double block_min(double v, double *lds)
+{
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if (t < s) lds[t] = fmin(lds[t], lds[t + s]);
+        __syncthreads();
+    }
+    double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ void latch(unsigned long long *ctr, unsigned long long bits)
+{
+    atomicOr(&ctr[C_STATUS], bits);
+}
+
+// Momentum of system s summed from its chunk partials in a fixed order.
+template <int BS>
+__device__ void system_momentum(const Dev &d, int s, double *lds, double P[3])
+{
+    const int c0 = d.sys_c0[s], c1 = d.sys_c0[s + 1];
+    for (int k = 0; k < 3; ++k) {
+        double acc = 0.0;
+        for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) acc += d.pm[3 * c + k];
+        P[k] = block_sum<BS>(acc, lds);
+    }
+}
+
+// ------------------------------------------------------------------------
+// E_Dft (Sec. 2): per-chunk momentum partials sum_i m_i v_i
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(kChunk) void k_momentum(Dev d)
+{
+    __shared__ double lds[kChunk];
+    const int4 bc = d.bchunk[blockIdx.x];
+    const int t = threadIdx.x;
+    const int i = bc.y + t;
+    double p[3] = {0.0, 0.0, 0.0};
+    if (t < bc.z) {
+        const double mi = d.m[i];
+        p[0] = mi * d.vx[i];
+        p[1] = mi * d.vy[i];
+        p[2] = mi * d.vz[i];
+    }
+    for (int k = 0; k < 3; ++k) {
+        double s = block_sum<kChunk>(p[k], lds);
+        if (t == 0) d.pm[3 * blockIdx.x + k] = s;
+    }
+}
+
+// ------------------------------------------------------------------------
+// E_Dft(dt): Q_i += dt * P / m0 (Sec. 2, H_Dft), optionally followed by the
+// per-body quantities of the encounter search (Sec. 2.4) at the drifted
+// state: a_i (osculating semi-major axis, r_i when unbound), and the crude
+// sweep terms  ch_i = c_s a_E h_i / 2 (mutual) or c_s a_E h_i a_i (sum),
+// cv_i = c_s |tau| sqrt(2 mu / r_i).  The first workgroup resets the
+// per-step counters.
+// ------------------------------------------------------------------------
+struct DriftArgs {
+    Dev d;
+    double dt, G, tau_crude, aE, cs;
+    int prepass, hill_mode, reset;
+};
+
+__global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
+{
+    __shared__ double lds[kChunk];
+    const Dev &d = a.d;
+    const int4 bc = d.bchunk[blockIdx.x];
+    const int s = bc.x;
+    double P[3];
+    system_momentum<kChunk>(d, s, lds, P);
+    if (a.reset && blockIdx.x == 0 && threadIdx.x == 0) {
+        d.ctr[C_CAND] = 0;
+        d.ctr[C_ENC] = 0;
+        d.ctr[C_NSETS] = 0;
+        d.ctr[C_MAXSET] = 0;
+        d.ctr[C_SUB] = 0;
+        d.ctr[C_NU] = 0;
+    }
+    const int t = threadIdx.x;
+    if (t >= bc.z) return;
+    const int i = bc.y + t;
+    const double m0 = d.sys_m0[s];
+    const double x = d.x[i] + a.dt * (P[0] / m0);
+    const double y = d.y[i] + a.dt * (P[1] / m0);
+    const double z = d.z[i] + a.dt * (P[2] / m0);
+    d.x[i] = x;
+    d.y[i] = y;
+    d.z[i] = z;
+    if (a.prepass) {
+        const double mu = a.G * m0;
+        const double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
+        const double r = sqrt(x * x + y * y + z * z);
+        const double inva = 2.0 / r - (vx * vx + vy * vy + vz * vz) / mu;
+        const double A = (inva > 0.0) ? 1.0 / inva : r;
+        const double ve = sqrt(2.0 * mu / r);
+        d.A[i] = A;
+        d.ch[i] = (a.hill_mode == 0) ? 0.5 * a.cs * a.aE * d.h[i] : a.cs * a.aE * d.h[i] * A;
+        d.cv[i] = a.cs * fabs(a.tau_crude) * ve;
+    }
+}
+
+// ------------------------------------------------------------------------
+// E_Int (Sec. 2, H_Int): all-pairs kick, i in registers, j tiles through
+// LDS; the crude encounter sweep of Sec. 2.4 is fused into the j loop of
+// the first kick for the unordered pairs i < j.  Each workgroup writes the
+// partial acceleration of its i-bodies over its j-chunk; the partials are
+// reduced in chunk order by k_apply_* (deterministic).
+//
+// FP64 pair term (PREC 0): r^-3 from the hardware reciprocal square root
+// (about 24 correct bits) refined by the binomial series of (1-e)^(-3/2)
+// with e = 1 - r^2 y0^2:  m r^-3 = m y0^3 (1 + e (3/2 + 15/8 e)), which is
+// exact to FP64 rounding since |e| < 2^-22.  r^2 is floored at 1e-200 so a
+// body's own pair (and coincident bodies) contributes exactly zero.
+//
+// FP32 pair term (PREC 1): the separation is formed in FP64 and rounded to
+// FP32, the rest of the pair term is FP32 (hardware rsq), sums are FP32
+// within a j-tile and accumulated across tiles in FP64.
+// ------------------------------------------------------------------------
+struct KickArgs {
+    Dev d;
+    double G;
+    long long cap;   // candidate capacity
+    int nitems;
+    int remap;       // XCD-aware workgroup order
+};
+
+// workgroup b of a grid of g (multiple of 8) runs on XCD b % 8; give each
+// XCD a contiguous run of items so that its L2 sees few j-chunks
+__device__ __forceinline__ int xcd_item(int b, int g)
+{
+    const int per = g >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+template <int MODE>
+__device__ __forceinline__ void crude_test(double r2, double hi, double Ai, double vi, double hj,
+                                           double Aj, double vj, int i, int j, const Dev &d,
+                                           long long cap)
+{
+    double thr;
+    if (MODE == 1)
+        thr = fma(hi + hj, Ai + Aj, vi + vj);
+    else
+        thr = (hi + hj) + (vi + vj);
+    if (MODE != 0 && r2 < thr * thr && j > i) {
+        unsigned long long slot = atomicAdd(&d.ctr[C_CAND], 1ull);
+        if ((long long)slot < cap) d.cand[slot] = make_int2(i, j);
+    }
+}
+
+template <int BS, int IPL, int MODE, int PREC>
+__global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
+{
+    const Dev &d = ka.d;
+    const int tid = threadIdx.x;
+    int b = blockIdx.x;
+    if (ka.remap) b = xcd_item(b, gridDim.x);
+    if (b >= ka.nitems) return;
+    const KickItem it = d.items[b];
+
+    __shared__ double4 sj[BS];
+    __shared__ double4 sc[MODE ? BS : 1];
+
+    double xi[IPL], yi[IPL], zi[IPL];
+    double ax[IPL], ay[IPL], az[IPL];
+    double hi[IPL], Ai[IPL], vi[IPL];
+    int ii[IPL];
+#pragma unroll
+    for (int u = 0; u < IPL; ++u) {
+        const int i = it.i0 + tid + u * BS;
+        const bool ok = (tid + u * BS) < it.ni;
+        xi[u] = ok ? d.x[i] : 0.0;
+        yi[u] = ok ? d.y[i] : 0.0;
+        zi[u] = ok ? d.z[i] : 0.0;
+        ax[u] = ay[u] = az[u] = 0.0;
+        if (MODE) {
+            hi[u] = ok ? d.ch[i] : 0.0;
+            Ai[u] = ok ? d.A[i] : 0.0;
+            vi[u] = ok ? d.cv[i] : 0.0;
+        }
+        ii[u] = ok ? i : 0x7fffffff;
+    }
+    const int jend = it.j0 + it.nj;
+    const double G = ka.G;
+    for (int jt = it.j0; jt < jend; jt += BS) {
+        const int j = jt + tid;
+        const bool okj = j < jend;
+        __syncthreads();
+        sj[tid] = okj ? make_double4(d.x[j], d.y[j], d.z[j], G * d.m[j])
+                      : make_double4(0.0, 0.0, 0.0, 0.0);
+        if (MODE) sc[tid] = okj ? make_double4(d.ch[j], d.A[j], d.cv[j], 0.0)
+                                : make_double4(0.0, 0.0, 0.0, 0.0);
+        __syncthreads();
+        const int last_j = min(jt + BS, jend) - 1;
+        const bool pred = MODE && (last_j > it.i0);
+        if constexpr (PREC == 0) {
+            if (MODE != 0 && pred) {
+#pragma unroll 4
+                for (int jj = 0; jj < BS; ++jj) {
+                    const double4 pj = sj[jj];
+                    const double4 cj = sc[MODE ? jj : 0];
+#pragma unroll
+                    for (int u = 0; u < IPL; ++u) {
+                        const double dx = pj.x - xi[u], dy = pj.y - yi[u], dz = pj.z - zi[u];
+                        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                        const double r2c = fmax(r2, 1e-200);
+                        const double y0 = __builtin_amdgcn_rsq(r2c);
+                        const double y2 = y0 * y0;
+                        const double e = fma(-r2c, y2, 1.0);
+                        const double c = fma(e, 1.875, 1.5);
+                        const double ms0 = pj.w * (y2 * y0);
+                        const double ms = fma(ms0 * e, c, ms0);
+                        ax[u] = fma(ms, dx, ax[u]);
+                        ay[u] = fma(ms, dy, ay[u]);
+                        az[u] = fma(ms, dz, az[u]);
+                        crude_test<MODE>(r2, hi[u], Ai[u], vi[u], cj.x, cj.y, cj.z, ii[u], jt + jj,
+                                         d, ka.cap);
+                    }
+                }
+            } else {
+#pragma unroll 4
+                for (int jj = 0; jj < BS; ++jj) {
+                    const double4 pj = sj[jj];
+#pragma unroll
+                    for (int u = 0; u < IPL; ++u) {
+                        const double dx = pj.x - xi[u], dy = pj.y - yi[u], dz = pj.z - zi[u];
+                        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                        const double r2c = fmax(r2, 1e-200);
+                        const double y0 = __builtin_amdgcn_rsq(r2c);
+                        const double y2 = y0 * y0;
+                        const double e = fma(-r2c, y2, 1.0);
+                        const double c = fma(e, 1.875, 1.5);
+                        const double ms0 = pj.w * (y2 * y0);
+                        const double ms = fma(ms0 * e, c, ms0);
+                        ax[u] = fma(ms, dx, ax[u]);
+                        ay[u] = fma(ms, dy, ay[u]);
+                        az[u] = fma(ms, dz, az[u]);
+                    }
+                }
+            }
+        } else {
+            float fx[IPL], fy[IPL], fz[IPL];
+#pragma unroll
+            for (int u = 0; u < IPL; ++u) fx[u] = fy[u] = fz[u] = 0.0f;
+#pragma unroll 4
+            for (int jj = 0; jj < BS; ++jj) {
+                const double4 pj = sj[jj];
+                const float mj = (float)pj.w;
+#pragma unroll
+                for (int u = 0; u < IPL; ++u) {
+                    const double dxd = pj.x - xi[u], dyd = pj.y - yi[u], dzd = pj.z - zi[u];
+                    const float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+                    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    const float r2c = fmaxf(r2, 1e-30f);
+                    const float y0 = __builtin_amdgcn_rsqf(r2c);
+                    const float ms = mj * (y0 * y0 * y0);
+                    fx[u] = fmaf(ms, dx, fx[u]);
+                    fy[u] = fmaf(ms, dy, fy[u]);
+                    fz[u] = fmaf(ms, dz, fz[u]);
+                    if (pred) {
+                        const double4 cj = sc[MODE ? jj : 0];
+                        const double r2d = fma(dzd, dzd, fma(dyd, dyd, dxd * dxd));
+                        crude_test<MODE>(r2d, hi[u], Ai[u], vi[u], cj.x, cj.y, cj.z, ii[u],
+                                         jt + jj, d, ka.cap);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < IPL; ++u) {
+                ax[u] += (double)fx[u];
+                ay[u] += (double)fy[u];
+                az[u] += (double)fz[u];
+            }
+        }
+    }
+    const int s = it.sys;
+    const int ns = d.sys_off[s + 1] - d.sys_off[s];
+    const long long base = d.sys_poff[s] + (long long)it.chunk * 3 * ns;
+#pragma unroll
+    for (int u = 0; u < IPL; ++u) {
+        if (tid + u * BS < it.ni) {
+            const int il = it.i0 + tid + u * BS - d.sys_off[s];
+            d.acc[base + il] = ax[u];
+            d.acc[base + ns + il] = ay[u];
+            d.acc[base + 2 * ns + il] = az[u];
+        }
+    }
+}
+
+// sum of the kick partials of body i (local index il of system s)
+__device__ __forceinline__ void sum_partials(const Dev &d, int s, int il, double a[3])
+{
+    const int ns = d.sys_off[s + 1] - d.sys_off[s];
+    const int S = d.sys_S[s];
+    const double *p = d.acc + d.sys_poff[s] + il;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int c = 0; c < S; ++c) {
+        ax += p[(long long)(3 * c) * ns];
+        ay += p[(long long)(3 * c + 1) * ns];
+        az += p[(long long)(3 * c + 2) * ns];
+    }
+    a[0] = ax;
+    a[1] = ay;
+    a[2] = az;
+}
+
+// ------------------------------------------------------------------------
+// Appendix A: Stumpff functions and the universal-variable Kepler advance
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void stumpff(double y, double &C, double &S)
+{
+    if (fabs(y) < 1.0) {
+        // C = sum_k (-y)^k/(2k+2)!, S = sum_k (-y)^k/(2k+3)!, Horner, k <= 13
+        constexpr double c[14] = {
+            1.0 / 2.0, 1.0 / 24.0, 1.0 / 720.0, 1.0 / 40320.0, 1.0 / 3628800.0,
+            1.0 / 479001600.0, 1.0 / 87178291200.0, 1.0 / 20922789888000.0,
+            1.0 / 6402373705728000.0, 1.0 / 2432902008176640000.0,
+            1.0 / 1.1240007277776077e21, 1.0 / 6.204484017332394e23,
+            1.0 / 4.0329146112660565e26, 1.0 / 3.0488834461171387e29};
+        constexpr double s[14] = {
+            1.0 / 6.0, 1.0 / 120.0, 1.0 / 5040.0, 1.0 / 362880.0, 1.0 / 39916800.0,
+            1.0 / 6227020800.0, 1.0 / 1307674368000.0, 1.0 / 355687428096000.0,
+            1.0 / 121645100408832000.0, 1.0 / 5.109094217170944e19,
+            1.0 / 2.585201673888498e22, 1.0 / 1.5511210043330986e25,
+            1.0 / 1.0888869450418352e28, 1.0 / 8.841761993739702e30};
+        const double w = -y;
+        double cc = c[13], ss = s[13];
+#pragma unroll
+        for (int k = 12; k >= 0; --k) {
+            cc = c[k] + w * cc;
+            ss = s[k] + w * ss;
+        }
+        C = cc;
+        S = ss;
+    } else if (y > 0.0) {
+        const double sy = sqrt(y);
+        C = (1.0 - cos(sy)) / y;
+        S = (sy - sin(sy)) / (y * sy);
+    } else {
+        const double sy = sqrt(-y);
+        C = (cosh(sy) - 1.0) / (-y);
+        S = (sinh(sy) - sy) / ((-y) * sy);
+    }
+}
+
+constexpr int kKeplerCap = 30;
+constexpr double kKeplerTol = 1e-14;
+
+// iterate to |dx| <= 1e-14 |x| (Laguerre n = 5, or Newton); returns 1 when
+// converged, adds the iterations to *count
+__device__ int kepler_iterate(double smu, double r0, double rv, double alpha, double dt,
+                              int laguerre, double &x, int &count)
+{
+    const double b = 1.0 - r0 * alpha;
+    for (int it = 1; it <= kKeplerCap; ++it) {
+        const double z = alpha * x * x;
+        double C, S;
+        stumpff(z, C, S);
+        const double F = rv * x * x * C / smu + b * x * x * x * S + r0 * x - smu * dt;
+        const double Fp = rv * x * (1.0 - z * S) / smu + b * x * x * C + r0;
+        double dx;
+        if (laguerre) {
+            const double Fpp = rv * (1.0 - z * C) / smu + b * x * (1.0 - z * S);
+            const double nl = 5.0;
+            const double rad =
+                sqrt(fabs((nl - 1.0) * (nl - 1.0) * Fp * Fp - nl * (nl - 1.0) * F * Fpp));
+            dx = nl * F / (Fp + (Fp >= 0.0 ? rad : -rad));
+        } else {
+            dx = F / Fp;
+        }
+        x = x - dx;
+        if (fabs(dx) <= kKeplerTol * fabs(x)) {
+            count += it;
+            return 1;
+        }
+    }
+    count += kKeplerCap;
+    return 0;
+}
+
+// learned first guess of the universal anomaly (form c): features
+// (|r0|, r0.v0, alpha, dt) standardised, 4->32->32->1 tanh network in FP32,
+// target standardised; weights laid out W1[32][4] b1[32] W2[32][32] b2[32]
+// W3[32] b3, then 10 scalers (feature means[4], scales[4], target mean,
+// target scale).
+__device__ float mlp_guess(const float *w, float f0, float f1, float f2, float f3)
+{
+    const float *W1 = w, *b1 = w + 128, *W2 = w + 160, *b2 = w + 1184, *W3 = w + 1216;
+    const float b3 = w[1248];
+    const float *sc = w + kMlpParams;
+    const float in[4] = {(f0 - sc[0]) / sc[4], (f1 - sc[1]) / sc[5], (f2 - sc[2]) / sc[6],
+                         (f3 - sc[3]) / sc[7]};
+    float h1[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        float a = b1[k];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a = fmaf(W1[4 * k + c], in[c], a);
+        h1[k] = tanhf(a);
+    }
+    float out = b3;
+#pragma unroll 4
+    for (int k = 0; k < 32; ++k) {
+        float a = b2[k];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) a = fmaf(W2[32 * k + c], h1[c], a);
+        out = fmaf(W3[k], tanhf(a), out);
+    }
+    return out * sc[9] + sc[8];
+}
+
+// Advance one body by dt about mu (Appendix A); returns iterations, sets
+// *fail when every start reached the cap.
+__device__ int kepler_advance(double mu, int mode, const float *mlp, double dt, double &x,
+                              double &y, double &z, double &vx, double &vy, double &vz, int &fail)
+{
+    fail = 0;
+    if (dt == 0.0) return 0;
+    const double r0 = sqrt(x * x + y * y + z * z);
+    const double vv = vx * vx + vy * vy + vz * vz;
+    const double rv = x * vx + y * vy + z * vz;
+    const double smu = sqrt(mu);
+    const double alpha = 2.0 / r0 - vv / mu;
+    const double guess = smu * dt / r0;
+    int count = 0, ok;
+    double xu;
+    if (mode == 0) {
+        xu = r0;
+        ok = kepler_iterate(smu, r0, rv, alpha, dt, 1, xu, count);
+        if (!ok) {
+            xu = guess;
+            ok = kepler_iterate(smu, r0, rv, alpha, dt, 1, xu, count);
+        }
+    } else {
+        xu = guess;
+        if (mode == 2) {
+            const double g = (double)mlp_guess(mlp, (float)r0, (float)rv, (float)alpha, (float)dt);
+            if (isfinite(g)) xu = g;
+        }
+        ok = kepler_iterate(smu, r0, rv, alpha, dt, 0, xu, count);
+        if (!ok) {
+            xu = guess;
+            ok = kepler_iterate(smu, r0, rv, alpha, dt, 1, xu, count);
+        }
+    }
+    fail = !ok;
+    const double zz = alpha * xu * xu;
+    double C, S;
+    stumpff(zz, C, S);
+    const double f = 1.0 - xu * xu * C / r0;
+    const double g = dt - xu * xu * xu * S / smu;
+    const double nx = f * x + g * vx, ny = f * y + g * vy, nz = f * z + g * vz;
+    const double r = sqrt(nx * nx + ny * ny + nz * nz);
+    const double fd = smu * xu * (zz * S - 1.0) / (r * r0);
+    const double gd = 1.0 - xu * xu * C / r;
+    const double nvx = fd * x + gd * vx, nvy = fd * y + gd * vy, nvz = fd * z + gd * vz;
+    x = nx;
+    y = ny;
+    z = nz;
+    vx = nvx;
+    vy = nvy;
+    vz = nvz;
+    return count;
+}
+
+// ------------------------------------------------------------------------
+// First kick applied (v += dt a), state snapshot (q0, v0), then E_Kep(tau)
+// of every body (Sec. 2.3 steps 2-3).  mode < 0 skips the kick part,
+// kick_only skips the Kepler part (operator-level entry points).
+// ------------------------------------------------------------------------
+struct ApplyArgs {
+    Dev d;
+    double dt_kick, dt_kep, G;
+    int do_kick, do_kep, snapshot, kepler_mode, momentum;
+};
+
+__global__ __launch_bounds__(kChunk) void k_apply_kepler(ApplyArgs a)
+{
+    __shared__ double lds[kChunk];
+    __shared__ unsigned int hist[kHist];
+    __shared__ unsigned int kmax;
+    __shared__ unsigned long long ksum;
+    __shared__ int bad;
+    const Dev &d = a.d;
+    const int4 bc = d.bchunk[blockIdx.x];
+    const int s = bc.x;
+    const int t = threadIdx.x;
+    if (t < kHist) hist[t] = 0;
+    if (t == 0) {
+        kmax = 0;
+        ksum = 0;
+        bad = 0;
+    }
+    __syncthreads();
+    double mom[3] = {0.0, 0.0, 0.0};
+    if (t < bc.z) {
+        const int i = bc.y + t;
+        double x = d.x[i], y = d.y[i], z = d.z[i];
+        double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
+        if (a.do_kick) {
+            double acc[3];
+            sum_partials(d, s, i - d.sys_off[s], acc);
+            vx += a.dt_kick * acc[0];
+            vy += a.dt_kick * acc[1];
+            vz += a.dt_kick * acc[2];
+        }
+        if (a.snapshot) {
+            d.x0[i] = x;
+            d.y0[i] = y;
+            d.z0[i] = z;
+            d.vx0[i] = vx;
+            d.vy0[i] = vy;
+            d.vz0[i] = vz;
+        }
+        if (a.do_kep) {
+            int fail;
+            const int it = kepler_advance(a.G * d.sys_m0[s], a.kepler_mode, d.mlp, a.dt_kep, x, y,
+                                          z, vx, vy, vz, fail);
+            atomicAdd(&hist[it < kHist ? it : kHist - 1], 1u);
+            atomicMax(&kmax, (unsigned)it);
+            atomicAdd(&ksum, (unsigned long long)it);
+            if (fail) atomicOr(&bad, (int)S_KEPLER);
+        }
+        if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) &&
+              isfinite(vz)))
+            atomicOr(&bad, (int)S_NONFINITE);
+        d.x[i] = x;
+        d.y[i] = y;
+        d.z[i] = z;
+        d.vx[i] = vx;
+        d.vy[i] = vy;
+        d.vz[i] = vz;
+        const double mi = d.m[i];
+        mom[0] = mi * vx;
+        mom[1] = mi * vy;
+        mom[2] = mi * vz;
+    }
+    if (a.momentum) {
+        for (int k = 0; k < 3; ++k) {
+            double sm = block_sum<kChunk>(mom[k], lds);
+            if (t == 0) d.pm[3 * blockIdx.x + k] = sm;
+        }
+    }
+    __syncthreads();
+    if (a.do_kep) {
+        if (t < kHist && hist[t]) atomicAdd(&d.ctr[C_HIST + t], (unsigned long long)hist[t]);
+        if (t == 0) {
+            atomicAdd(&d.ctr[C_KIT], ksum);
+            atomicMax(&d.ctr[C_KMAX], (unsigned long long)kmax);
+        }
+    }
+    if (t == 0 && bad) latch(d.ctr, (unsigned long long)bad);
+}
+
+// ------------------------------------------------------------------------
+// Sec. 2.4 fine sweep: cubic Hermite interpolant of D(s) = |dq(s)|^2 over
+// the step from (q0, v0) and (q1, v1), its minimum over [0, 1] compared
+// with a_E x mutual Hill radius (cube-free form) or a_E x (sum of Hill
+// radii).  Fixed IEEE operation order, no contraction.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double cubic_at(double c0, double c1, double c2, double c3, double s)
+{
+    return c0 + s * (c1 + s * (c2 + s * c3));
+}
+
+__device__ int fine_pair(int hill_mode, double aE, double m0, double tau, double mi, double mj,
+                         double hi, double hj, double Ai, double Aj, const double a0[3],
+                         const double b0[3], const double a1[3], const double b1[3], double &lhs,
+                         double &rhs)
+{
+    const double D0 = a0[0] * a0[0] + a0[1] * a0[1] + a0[2] * a0[2];
+    const double D1 = a1[0] * a1[0] + a1[1] * a1[1] + a1[2] * a1[2];
+    const double d0 = 2.0 * tau * (a0[0] * b0[0] + a0[1] * b0[1] + a0[2] * b0[2]);
+    const double d1 = 2.0 * tau * (a1[0] * b1[0] + a1[1] * b1[1] + a1[2] * b1[2]);
+    const double c0 = D0, c1 = d0;
+    const double c2 = 3.0 * (D1 - D0) - 2.0 * d0 - d1;
+    const double c3 = 2.0 * (D0 - D1) + d0 + d1;
+    double Dm = (D0 < D1) ? D0 : D1;
+    const double disc = c2 * c2 - 3.0 * c3 * c1;
+    if (disc >= 0.0) {
+        const double sq = sqrt(disc);
+        const double qq = -(c2 + (c2 >= 0.0 ? sq : -sq));
+        if (c3 != 0.0) {
+            const double sr = qq / (3.0 * c3);
+            if (sr > 0.0 && sr < 1.0) {
+                const double D = cubic_at(c0, c1, c2, c3, sr);
+                if (D < Dm) Dm = D;
+            }
+        }
+        if (qq != 0.0) {
+            const double sr = c1 / qq;
+            if (sr > 0.0 && sr < 1.0) {
+                const double D = cubic_at(c0, c1, c2, c3, sr);
+                if (D < Dm) Dm = D;
+            }
+        }
+    }
+    if (Dm < 0.0) Dm = 0.0;
+    if (hill_mode == 0) {
+        const double T = aE * (Ai + Aj) / 2.0;
+        const double M = (mi + mj) / (3.0 * m0);
+        const double T2 = T * T;
+        lhs = Dm * Dm * Dm;
+        rhs = T2 * T2 * T2 * M * M;
+    } else {
+        const double R = aE * (hi * Ai + hj * Aj);
+        lhs = Dm;
+        rhs = R * R;
+    }
+    return lhs < rhs;
+}
+
+struct FineArgs {
+    Dev d;
+    double tau, aE;
+    long long cap;
+    int hill_mode;
+};
+
+__global__ __launch_bounds__(256) void k_fine(FineArgs a)
+{
+    const Dev &d = a.d;
+    const unsigned long long cnt = d.ctr[C_CAND];
+    const long long n = (long long)cnt < a.cap ? (long long)cnt : a.cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (long long)cnt > a.cap) latch(d.ctr, S_CAND_OVF);
+    for (long long k = blockIdx.x * 256ll + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+        const int2 p = d.cand[k];
+        const int i = p.x, j = p.y;
+        const double a0[3] = {d.x0[j] - d.x0[i], d.y0[j] - d.y0[i], d.z0[j] - d.z0[i]};
+        const double b0[3] = {d.vx0[j] - d.vx0[i], d.vy0[j] - d.vy0[i], d.vz0[j] - d.vz0[i]};
+        const double a1[3] = {d.x[j] - d.x[i], d.y[j] - d.y[i], d.z[j] - d.z[i]};
+        const double b1[3] = {d.vx[j] - d.vx[i], d.vy[j] - d.vy[i], d.vz[j] - d.vz[i]};
+        double lhs, rhs;
+        const int f = fine_pair(a.hill_mode, a.aE, d.sys_m0[d.body_sys[i]], a.tau, d.m[i], d.m[j],
+                                d.h[i], d.h[j], d.A[i], d.A[j], a0, b0, a1, b1, lhs, rhs);
+        if (f) {
+            const unsigned long long slot = atomicAdd(&d.ctr[C_ENC], 1ull);
+            if (slot < (unsigned long long)kCapE) d.enc[slot] = make_int2(i, j);
+        }
+    }
+}
+
+// stateless fine sweep on caller arrays (SoA [3][n])
+__global__ __launch_bounds__(256) void k_fine_standalone(
+    int hill_mode, double aE, double m0, double tau, long long n, const double *m, const double *h,
+    const double *A, const double *q0, const double *v0, const double *q1, const double *v1,
+    long long np, const int *pairs, int *flags, double *lhs_out, double *rhs_out)
+{
+    const long long k = blockIdx.x * 256ll + threadIdx.x;
+    if (k >= np) return;
+    const int i = pairs[2 * k], j = pairs[2 * k + 1];
+    double a0[3], b0[3], a1[3], b1[3];
+    for (int c = 0; c < 3; ++c) {
+        a0[c] = q0[c * n + j] - q0[c * n + i];
+        b0[c] = v0[c * n + j] - v0[c * n + i];
+        a1[c] = q1[c * n + j] - q1[c * n + i];
+        b1[c] = v1[c * n + j] - v1[c * n + i];
+    }
+    double lhs, rhs;
+    flags[k] = fine_pair(hill_mode, aE, m0, tau, m[i], m[j], h[i], h[j], A[i], A[j], a0, b0, a1,
+                         b1, lhs, rhs);
+    if (lhs_out) lhs_out[k] = lhs;
+    if (rhs_out) rhs_out[k] = rhs;
+}
+
+// ------------------------------------------------------------------------
+// Sec. 2.3 step 4 / Sec. 2.4: canonical encounter list, division into
+// non-intersecting sets (connected components; a set is labelled by its
+// smallest body index, members ascending), r_crit = a_H max h_i a_i.
+// One workgroup; everything in LDS (<= kCapE pairs).
+// ------------------------------------------------------------------------
+template <typename T>
+__device__ void bitonic_sort_lds(T *v, int n2)
+{
+    // n2 is a power of two; ascending
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int jx = k >> 1; jx > 0; jx >>= 1) {
+            for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+                const int l = i ^ jx;
+                if (l > i) {
+                    const T a = v[i], b = v[l];
+                    const bool up = ((i & k) == 0);
+                    if ((a > b) == up) {
+                        v[i] = b;
+                        v[l] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// exclusive scan over n <= 2*kCapE flags (in place) by one workgroup;
+// returns the total
+__device__ int block_scan_excl(int *v, int n, int *tmp)
+{
+    const int T = blockDim.x;
+    const int per = (n + T - 1) / T;
+    const int t = threadIdx.x;
+    int s = 0;
+    for (int k = 0; k < per; ++k) {
+        const int i = t * per + k;
+        if (i < n) s += v[i];
+    }
+    tmp[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int k = 0; k < T; ++k) {
+            const int c = tmp[k];
+            tmp[k] = run;
+            run += c;
+        }
+        tmp[T] = run;
+    }
+    __syncthreads();
+    int run = tmp[t];
+    for (int k = 0; k < per; ++k) {
+        const int i = t * per + k;
+        if (i < n) {
+            const int c = v[i];
+            v[i] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    const int total = tmp[T];
+    __syncthreads();
+    return total;
+}
+
+struct SetsArgs {
+    Dev d;
+    double aH;
+};
+
+__global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
+{
+    const Dev &d = a.d;
+    __shared__ unsigned long long keys[kCapE];   // 32 KB: sorted pairs
+    __shared__ unsigned int ep[kCapU];           // 32 KB: endpoints -> unique bodies
+    __shared__ unsigned int lab[kCapU];          // 32 KB: component labels (ranks)
+    __shared__ unsigned int rp[kCapE];           // 16 KB: pairs as rank pairs
+    __shared__ int flag[kCapU];                  // 32 KB: scan scratch
+    __shared__ int tmp[kSetsThreads + 1];
+    __shared__ int changed;
+    const int t = threadIdx.x;
+    const unsigned long long cnt = d.ctr[C_ENC];
+    if (cnt > (unsigned long long)kCapE) {
+        if (t == 0) {
+            latch(d.ctr, S_ENC_OVF);
+            d.ctr[C_NSETS] = 0;
+            atomicAdd(&d.ctr[C_TENC], cnt);
+        }
+        return;
+    }
+    const int ne = (int)cnt;
+    if (ne == 0) return;
+    int n2 = 1;
+    while (n2 < ne) n2 <<= 1;
+    for (int k = t; k < n2; k += blockDim.x) {
+        if (k < ne) {
+            const int2 p = d.enc[k];
+            keys[k] = ((unsigned long long)(unsigned)p.x << 32) | (unsigned)p.y;
+        } else {
+            keys[k] = ~0ull;
+        }
+    }
+    __syncthreads();
+    bitonic_sort_lds(keys, n2);
+    for (int k = t; k < ne; k += blockDim.x)
+        d.enc_sorted[k] = make_int2((int)(keys[k] >> 32), (int)(keys[k] & 0xffffffffu));
+    // unique endpoints
+    int m2 = 1;
+    while (m2 < 2 * ne) m2 <<= 1;
+    for (int k = t; k < m2; k += blockDim.x) {
+        if (k < 2 * ne) {
+            const unsigned long long kk = keys[k >> 1];
+            ep[k] = (k & 1) ? (unsigned)(kk & 0xffffffffu) : (unsigned)(kk >> 32);
+        } else {
+            ep[k] = 0xffffffffu;
+        }
+    }
+    __syncthreads();
+    bitonic_sort_lds(ep, m2);
+    for (int k = t; k < 2 * ne; k += blockDim.x) flag[k] = (k == 0 || ep[k] != ep[k - 1]) ? 1 : 0;
+    __syncthreads();
+    // keep a copy of the flags in lab (lab is free until the labelling)
+    for (int k = t; k < 2 * ne; k += blockDim.x) lab[k] = (unsigned)flag[k];
+    __syncthreads();
+    const int nu = block_scan_excl(flag, 2 * ne, tmp);
+    // unique body indices staged through d.set_mem (global), then back to ep
+    for (int k = t; k < 2 * ne; k += blockDim.x)
+        if (lab[k]) d.set_mem[flag[k]] = (int)ep[k];
+    __syncthreads();
+    __threadfence_block();
+    for (int k = t; k < nu; k += blockDim.x) ep[k] = (unsigned)d.set_mem[k];
+    __syncthreads();
+    // rank pairs by binary search in the sorted unique list
+    for (int k = t; k < ne; k += blockDim.x) {
+        const unsigned i = (unsigned)(keys[k] >> 32), j = (unsigned)(keys[k] & 0xffffffffu);
+        int lo = 0, hi = nu - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ep[mid] < i) lo = mid + 1; else hi = mid;
+        }
+        const int ri = lo;
+        lo = 0;
+        hi = nu - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (ep[mid] < j) lo = mid + 1; else hi = mid;
+        }
+        rp[k] = ((unsigned)ri << 16) | (unsigned)lo;
+    }
+    for (int k = t; k < nu; k += blockDim.x) lab[k] = (unsigned)k;
+    __syncthreads();
+    // label propagation to the component minimum
+    for (int iter = 0; iter < 2 * kCapU; ++iter) {
+        if (t == 0) changed = 0;
+        __syncthreads();
+        for (int k = t; k < ne; k += blockDim.x) {
+            const unsigned ri = rp[k] >> 16, rj = rp[k] & 0xffffu;
+            const unsigned li = lab[ri], lj = lab[rj];
+            if (li != lj) {
+                const unsigned mn = li < lj ? li : lj;
+                atomicMin(&lab[ri], mn);
+                atomicMin(&lab[rj], mn);
+                changed = 1;
+            }
+        }
+        __syncthreads();
+        // pointer jumping
+        for (int k = t; k < nu; k += blockDim.x) {
+            const unsigned l = lab[k];
+            const unsigned ll = lab[l];
+            if (ll < l) {
+                atomicMin(&lab[k], ll);
+                changed = 1;
+            }
+        }
+        __syncthreads();
+        if (!changed) break;
+        __syncthreads();
+    }
+    // roots -> set ids in ascending root order
+    for (int k = t; k < nu; k += blockDim.x) flag[k] = (lab[k] == (unsigned)k) ? 1 : 0;
+    __syncthreads();
+    const int nsets = block_scan_excl(flag, nu, tmp);
+    // member sort keys (root rank, rank) reuse keys[]
+    int u2 = 1;
+    while (u2 < nu) u2 <<= 1;
+    unsigned int *mk = (unsigned int *)keys;  // kCapU * 4 bytes fit in keys
+    for (int k = t; k < u2; k += blockDim.x)
+        mk[k] = (k < nu) ? ((lab[k] << 16) | (unsigned)k) : 0xffffffffu;
+    __syncthreads();
+    bitonic_sort_lds(mk, u2);
+    for (int k = t; k < nu; k += blockDim.x) {
+        const unsigned r = mk[k] & 0xffffu;
+        d.set_mem[k] = (int)ep[r];
+        const unsigned root = mk[k] >> 16;
+        const bool first = (k == 0) || ((mk[k - 1] >> 16) != root);
+        if (first) d.set_start[flag[root]] = k;
+    }
+    if (t == 0) d.set_start[nsets] = nu;
+    __syncthreads();
+    __threadfence_block();
+    // r_crit and the largest set
+    for (int sidx = t; sidx < nsets; sidx += blockDim.x) {
+        const int b0 = d.set_start[sidx], b1 = d.set_start[sidx + 1];
+        double hmax = 0.0;
+        for (int k = b0; k < b1; ++k) {
+            const int i = d.set_mem[k];
+            const double rh = d.h[i] * d.A[i];
+            if (rh > hmax) hmax = rh;
+        }
+        d.set_rc[sidx] = a.aH * hmax;
+        atomicMax(&d.ctr[C_MAXSET], (unsigned long long)(b1 - b0));
+    }
+    if (t == 0) {
+        d.ctr[C_NSETS] = (unsigned long long)nsets;
+        d.ctr[C_NU] = (unsigned long long)nu;
+        atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
+    }
+}
+
+// ------------------------------------------------------------------------
+// Sec. 2.1 transition function and Sec. 2.2 / 2.3 set kernels
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void transition(double s, double rc, double &K, double &Kp, double &Kpp)
+{
+    const double y = 1.1 * s / rc - 0.1;
+    if (y <= 0.0) {
+        K = 0.0; Kp = 0.0; Kpp = 0.0;
+    } else if (y >= 1.0) {
+        K = 1.0; Kp = 0.0; Kpp = 0.0;
+    } else {
+        const double w = kPi / 2.0;
+        const double c = 1.1 / rc;
+        K = sin(w * y);
+        Kp = w * c * cos(w * y);
+        Kpp = -(w * c) * (w * c) * sin(w * y);
+    }
+}
+
+struct HermArgs {
+    Dev d;
+    double tau, G, epsH, eta, eta_s;
+    int max_substeps;
+};
+
+// member scratch layout: field f of member slot k at hw[f * kCapU + k]
+enum { HX = 0, HU = 3, HA = 6, HJ = 9, HXP = 12, HUP = 15, HA1 = 18, HJ1 = 21, HXN = 24, HUN = 27,
+       HFIELDS = 30 };
+
+__device__ __forceinline__ double &hw_at(const Dev &d, int f, int k) { return d.hw[f * kCapU + k]; }
+
+// W-weighted in-set acceleration on member slot a (unsoftened, Sec. 2.3
+// steps 5 and 7), positions from field f (or the snapshot when f < 0)
+__device__ void set_pair_acc(const Dev &d, int b0, int n, int a, int f, double G, double rc,
+                             double out[3])
+{
+    const int i = d.set_mem[b0 + a];
+    double xi[3];
+    if (f < 0) { xi[0] = d.x0[i]; xi[1] = d.y0[i]; xi[2] = d.z0[i]; }
+    else { for (int c = 0; c < 3; ++c) xi[c] = hw_at(d, f + c, b0 + a); }
+    out[0] = out[1] = out[2] = 0.0;
+    for (int b = 0; b < n; ++b) {
+        if (b == a) continue;
+        const int j = d.set_mem[b0 + b];
+        double dd[3];
+        if (f < 0) { dd[0] = d.x0[j] - xi[0]; dd[1] = d.y0[j] - xi[1]; dd[2] = d.z0[j] - xi[2]; }
+        else { for (int c = 0; c < 3; ++c) dd[c] = hw_at(d, f + c, b0 + b) - xi[c]; }
+        const double s2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] + 0.0 * 0.0;
+        if (s2 == 0.0) continue;
+        const double s = sqrt(s2);
+        double K, Kp, Kpp;
+        transition(s, rc, K, Kp, Kpp);
+        const double W = 1.0 - K + s * Kp;
+        const double fct = G * d.m[j] * W / (s2 * s);
+        for (int c = 0; c < 3; ++c) out[c] += fct * dd[c];
+    }
+}
+
+// acceleration and jerk of member slot a of H'_Kep (Sec. 2.2) from fields
+// (fx: positions, fu: velocities)
+__device__ void herm_force(const Dev &d, int b0, int n, int a, int fx, int fu, double G, double mu,
+                           double rc, double eps, double acc[3], double jrk[3])
+{
+    double X[3], U[3];
+    for (int c = 0; c < 3; ++c) {
+        X[c] = hw_at(d, fx + c, b0 + a);
+        U[c] = hw_at(d, fu + c, b0 + a);
+    }
+    const double r2 = X[0] * X[0] + X[1] * X[1] + X[2] * X[2];
+    const double r = sqrt(r2);
+    const double r3 = r2 * r;
+    const double xv = X[0] * U[0] + X[1] * U[1] + X[2] * U[2];
+    for (int c = 0; c < 3; ++c) {
+        acc[c] = -mu * X[c] / r3;
+        jrk[c] = -mu * (U[c] / r3 - 3.0 * xv * X[c] / (r3 * r2));
+    }
+    for (int b = 0; b < n; ++b) {
+        if (b == a) continue;
+        const int j = d.set_mem[b0 + b];
+        double dd[3], w[3];
+        for (int c = 0; c < 3; ++c) {
+            dd[c] = hw_at(d, fx + c, b0 + b) - X[c];
+            w[c] = hw_at(d, fu + c, b0 + b) - U[c];
+        }
+        const double s2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] + eps * eps;
+        if (s2 == 0.0) continue;
+        const double s = sqrt(s2);
+        double K, Kp, Kpp;
+        transition(s, rc, K, Kp, Kpp);
+        const double W = 1.0 - K + s * Kp;
+        const double gm = G * d.m[j] / (s2 * s);
+        const double dw = dd[0] * w[0] + dd[1] * w[1] + dd[2] * w[2];
+        for (int c = 0; c < 3; ++c) {
+            acc[c] += gm * W * dd[c];
+            jrk[c] += gm * (dw * dd[c] * Kpp + (w[c] - 3.0 * dw * dd[c] / s2) * W);
+        }
+    }
+}
+
+// One workgroup per encounter set (grid-stride over sets): correction at q0
+// (Sec. 2.3 step 5), PEC Hermite over tau with one shared step per set
+// (step 6), correction at q1 (step 7), members written back to the state.
+__global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
+{
+    const Dev &d = a.d;
+    __shared__ double lds[kHermThreads];
+    __shared__ int s_fail;
+    const int t = threadIdx.x;
+    const int nsets = (int)d.ctr[C_NSETS];
+    for (int sidx = blockIdx.x; sidx < nsets; sidx += gridDim.x) {
+        const int b0 = d.set_start[sidx];
+        const int n = d.set_start[sidx + 1] - b0;
+        const double rc = d.set_rc[sidx];
+        if (n > kHermMax) {
+            if (t == 0) latch(d.ctr, S_SET_BIG);
+            continue;
+        }
+        const double mu = a.G * d.sys_m0[d.body_sys[d.set_mem[b0]]];
+        const double half = a.tau / 2.0;
+        // step 5: v0 -= tau/2 * sum W-weighted in-set forces at q0
+        for (int k = t; k < n; k += kHermThreads) {
+            double acc[3];
+            set_pair_acc(d, b0, n, k, -1, a.G, rc, acc);
+            const int i = d.set_mem[b0 + k];
+            hw_at(d, HX + 0, b0 + k) = d.x0[i];
+            hw_at(d, HX + 1, b0 + k) = d.y0[i];
+            hw_at(d, HX + 2, b0 + k) = d.z0[i];
+            hw_at(d, HU + 0, b0 + k) = d.vx0[i] - half * acc[0];
+            hw_at(d, HU + 1, b0 + k) = d.vy0[i] - half * acc[1];
+            hw_at(d, HU + 2, b0 + k) = d.vz0[i] - half * acc[2];
+        }
+        __syncthreads();
+        // initial force and first step
+        double hloc = INFINITY;
+        for (int k = t; k < n; k += kHermThreads) {
+            double acc[3], jr[3];
+            herm_force(d, b0, n, k, HX, HU, a.G, mu, rc, a.epsH, acc, jr);
+            for (int c = 0; c < 3; ++c) {
+                hw_at(d, HA + c, b0 + k) = acc[c];
+                hw_at(d, HJ + c, b0 + k) = jr[c];
+            }
+            const double hb = a.eta_s * dnorm3(acc[0], acc[1], acc[2]) / dnorm3(jr[0], jr[1], jr[2]);
+            if (hb > 0.0 && hb < hloc) hloc = hb;
+        }
+        double h = block_min<kHermThreads>(hloc, lds);
+        const double sgn = a.tau >= 0.0 ? 1.0 : -1.0;
+        const double T = fabs(a.tau);
+        double tt = 0.0;
+        int nsub = 0;
+        bool last = (T == 0.0);
+        if (t == 0) s_fail = 0;
+        __syncthreads();
+        while (!last) {
+            if (nsub >= a.max_substeps) {
+                if (t == 0) s_fail = 1;
+                break;
+            }
+            if (!(h > 0.0) || h >= T - tt) {
+                h = T - tt;
+                last = true;
+            }
+            const double hs = sgn * h;
+            for (int k = t; k < n; k += kHermThreads) {
+                for (int c = 0; c < 3; ++c) {
+                    const double x = hw_at(d, HX + c, b0 + k), u = hw_at(d, HU + c, b0 + k);
+                    const double ac = hw_at(d, HA + c, b0 + k), jc = hw_at(d, HJ + c, b0 + k);
+                    hw_at(d, HXP + c, b0 + k) =
+                        x + hs * u + hs * hs * ac / 2.0 + hs * hs * hs * jc / 6.0;
+                    hw_at(d, HUP + c, b0 + k) = u + hs * ac + hs * hs * jc / 2.0;
+                }
+            }
+            __syncthreads();
+            double hn = INFINITY;
+            for (int k = t; k < n; k += kHermThreads) {
+                double a1[3], j1[3];
+                herm_force(d, b0, n, k, HXP, HUP, a.G, mu, rc, a.epsH, a1, j1);
+                double A2e[3], A3v[3];
+                for (int c = 0; c < 3; ++c) {
+                    const double a0c = hw_at(d, HA + c, b0 + k), j0c = hw_at(d, HJ + c, b0 + k);
+                    const double A2 = (-6.0 * (a0c - a1[c]) - hs * (4.0 * j0c + 2.0 * j1[c])) / (hs * hs);
+                    const double A3 = (12.0 * (a0c - a1[c]) + 6.0 * hs * (j0c + j1[c])) / (hs * hs * hs);
+                    hw_at(d, HA1 + c, b0 + k) = a1[c];
+                    hw_at(d, HJ1 + c, b0 + k) = j1[c];
+                    const double xp = hw_at(d, HXP + c, b0 + k), up = hw_at(d, HUP + c, b0 + k);
+                    // the predicted fields are read by every member's force:
+                    // the corrected state goes to HXN/HUN until the barrier
+                    hw_at(d, HXN + c, b0 + k) =
+                        xp + A2 * hs * hs * hs * hs / 24.0 + A3 * hs * hs * hs * hs * hs / 120.0;
+                    hw_at(d, HUN + c, b0 + k) = up + A2 * hs * hs * hs / 6.0 + A3 * hs * hs * hs * hs / 24.0;
+                    A2e[c] = A2 + hs * A3;
+                    A3v[c] = A3;
+                }
+                const double na = dnorm3(a1[0], a1[1], a1[2]), nj = dnorm3(j1[0], j1[1], j1[2]);
+                const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]), n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
+                const double hb = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
+                if (hb > 0.0 && hb < hn) hn = hb;
+            }
+            hn = block_min<kHermThreads>(hn, lds);   // includes a barrier: all forces done
+            for (int k = t; k < n; k += kHermThreads) {
+                for (int c = 0; c < 3; ++c) {
+                    hw_at(d, HX + c, b0 + k) = hw_at(d, HXN + c, b0 + k);
+                    hw_at(d, HU + c, b0 + k) = hw_at(d, HUN + c, b0 + k);
+                    hw_at(d, HA + c, b0 + k) = hw_at(d, HA1 + c, b0 + k);
+                    hw_at(d, HJ + c, b0 + k) = hw_at(d, HJ1 + c, b0 + k);
+                }
+            }
+            __syncthreads();
+            tt += h;
+            ++nsub;
+            h = hn;
+        }
+        __syncthreads();
+        // step 7: v1 -= tau/2 * sum W-weighted in-set forces at q1; write back
+        for (int k = t; k < n; k += kHermThreads) {
+            double acc[3];
+            set_pair_acc(d, b0, n, k, HX, a.G, rc, acc);
+            const int i = d.set_mem[b0 + k];
+            d.x[i] = hw_at(d, HX + 0, b0 + k);
+            d.y[i] = hw_at(d, HX + 1, b0 + k);
+            d.z[i] = hw_at(d, HX + 2, b0 + k);
+            d.vx[i] = hw_at(d, HU + 0, b0 + k) - half * acc[0];
+            d.vy[i] = hw_at(d, HU + 1, b0 + k) - half * acc[1];
+            d.vz[i] = hw_at(d, HU + 2, b0 + k) - half * acc[2];
+        }
+        if (t == 0) {
+            atomicAdd(&d.ctr[C_SUB], (unsigned long long)nsub);
+            atomicAdd(&d.ctr[C_TSUB], (unsigned long long)nsub);
+            if (s_fail) latch(d.ctr, S_HERMITE);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// Energy (Sec. 2, H = H_Dft + H_Kep + H_Int): pair potentials over i < j
+// per work item, then per system the O(N) terms and a fixed-order sum.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_energy_pairs(Dev d)
+{
+    __shared__ double lds[256];
+    __shared__ double4 sj[256];
+    const KickItem it = d.eitems[blockIdx.x];
+    const int t = threadIdx.x;
+    const int i = it.i0 + t;
+    const bool ok = t < it.ni;
+    const double xi = ok ? d.x[i] : 0.0, yi = ok ? d.y[i] : 0.0, zi = ok ? d.z[i] : 0.0;
+    const double mi = ok ? d.m[i] : 0.0;
+    double s = 0.0;
+    const int jend = it.j0 + it.nj;
+    for (int jt = it.j0; jt < jend; jt += 256) {
+        const int j = jt + t;
+        __syncthreads();
+        sj[t] = (j < jend) ? make_double4(d.x[j], d.y[j], d.z[j], d.m[j]) : make_double4(0, 0, 0, 0);
+        __syncthreads();
+        const int nj = min(256, jend - jt);
+        if (jt + nj - 1 <= it.i0) continue;   // all j <= every i of this item
+        for (int jj = 0; jj < nj; ++jj) {
+            const double4 pj = sj[jj];
+            const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (jt + jj > i && r > 0.0) s += pj.w / r;
+        }
+    }
+    const double tot = block_sum<256>(mi * s, lds);
+    if (t == 0) d.epart[blockIdx.x] = tot;
+}
+
+struct EnergyArgs {
+    Dev d;
+    double G;
+};
+
+__global__ __launch_bounds__(256) void k_energy_final(EnergyArgs a)
+{
+    __shared__ double lds[256];
+    const Dev &d = a.d;
+    const int s = blockIdx.x;
+    const int i0 = d.sys_off[s], i1 = d.sys_off[s + 1];
+    const double m0 = d.sys_m0[s];
+    double kin = 0.0, pot0 = 0.0, px = 0.0, py = 0.0, pz = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+        const double mi = d.m[i];
+        const double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
+        kin += 0.5 * mi * (vx * vx + vy * vy + vz * vz);
+        px += mi * vx;
+        py += mi * vy;
+        pz += mi * vz;
+        pot0 += a.G * m0 * mi / dnorm3(d.x[i], d.y[i], d.z[i]);
+    }
+    double pp = 0.0;
+    for (int e = d.sys_e0[s] + threadIdx.x; e < d.sys_e0[s + 1]; e += 256) pp += d.epart[e];
+    kin = block_sum<256>(kin, lds);
+    pot0 = block_sum<256>(pot0, lds);
+    px = block_sum<256>(px, lds);
+    py = block_sum<256>(py, lds);
+    pz = block_sum<256>(pz, lds);
+    pp = block_sum<256>(pp, lds);
+    if (threadIdx.x == 0)
+        d.E[s] = kin + (px * px + py * py + pz * pz) / (2.0 * m0) - pot0 - a.G * pp;
+}
+
+// steps counter (one thread)
+__global__ void k_count_step(Dev d) { d.ctr[C_STEPS] += 1; }
+
+}  // namespace qsym

@@ -1,0 +1,314 @@
+"""ctypes binding of ``libqsym.so`` (the C ABI of include/qsym.h).
+
+Argument marshalling only: every step of the integrator runs in the HIP
+kernels of the library.  PyTorch provides the device workspace and the
+stream.  The library must have been built (``__graft_entry__.build()``);
+importing this module on a machine without it raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqsym.so")
+
+QSYM_HOST, QSYM_DEVICE = 0, 1
+ERRORS = {
+    -1: "QSYM_EINVAL", -2: "QSYM_ENOMEM", -3: "QSYM_EHIP", -4: "QSYM_ENONFINITE",
+    -5: "QSYM_EKEPLER", -6: "QSYM_EOVERFLOW", -7: "QSYM_ETRUNC", -8: "QSYM_EHERMITE",
+}
+
+
+class QsymError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("G", C.c_double), ("aE", C.c_double), ("aH", C.c_double), ("epsH", C.c_double),
+                ("eta", C.c_double), ("eta_s", C.c_double), ("crude_safety", C.c_double),
+                ("hill_mode", C.c_int32), ("kepler_mode", C.c_int32), ("precision", C.c_int32),
+                ("max_substeps", C.c_int32), ("pair_capacity", C.c_int64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("n_candidates", C.c_int64), ("n_encounters", C.c_int64),
+                ("n_sets", C.c_int64), ("max_set", C.c_int64), ("substeps", C.c_int64),
+                ("total_encounters", C.c_int64), ("total_substeps", C.c_int64),
+                ("kepler_iters", C.c_int64), ("kepler_max", C.c_int64),
+                ("kepler_hist", C.c_int64 * 32), ("status", C.c_int64),
+                ("phase_us", C.c_double * 12), ("phase_calls", C.c_int64 * 12)]
+
+    def as_dict(self):
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if not isinstance(v, (int, float)) else v
+        return d
+
+
+PHASES = ["drift+prepass", "kick+crude", "apply+kepler", "fine", "sets", "hermite", "kick2",
+          "apply2+momentum", "drift2", "energy", "momentum", "other"]
+
+DEFAULTS = dict(G=1.0, aE=3.0, aH=1.0, epsH=1e-8, eta=0.02, eta_s=0.01, crude_safety=1.1,
+                hill_mode=0, kepler_mode=0, precision=0, max_substeps=100000, pair_capacity=0)
+
+
+def make_params(**kw) -> Params:
+    d = dict(DEFAULTS)
+    unknown = set(kw) - set(d)
+    if unknown:
+        raise TypeError(f"unknown parameters {sorted(unknown)}")
+    d.update(kw)
+    return Params(float(d["G"]), float(d["aE"]), float(d["aH"]), float(d["epsH"]), float(d["eta"]),
+                  float(d["eta_s"]), float(d["crude_safety"]), int(d["hill_mode"]),
+                  int(d["kepler_mode"]), int(d["precision"]), int(d["max_substeps"]),
+                  int(d["pair_capacity"]))
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_lp = C.POINTER(C.c_int64)
+
+# name -> (restype, argtypes); kept in the order of include/qsym.h
+SIGNATURES = {
+    "qsym_workspace_bytes": (C.c_int, [C.POINTER(Params), C.c_int32, _lp, _lp]),
+    "qsym_create": (C.c_int, [C.POINTER(Params), C.c_int32, _lp, _dp, C.c_void_p, C.c_int64,
+                              C.c_void_p, C.POINTER(C.c_void_p)]),
+    "qsym_destroy": (None, [C.c_void_p]),
+    "qsym_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_int32]),
+    "qsym_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
+    "qsym_step": (C.c_int, [C.c_void_p, C.c_double, C.c_int64]),
+    "qsym_sync": (C.c_int, [C.c_void_p]),
+    "qsym_energy": (C.c_int, [C.c_void_p, _dp]),
+    "qsym_encounters": (C.c_int, [C.c_void_p, _ip, C.c_int64, _lp, _ip]),
+    "qsym_candidates": (C.c_int, [C.c_void_p, _ip, C.c_int64, _lp]),
+    "qsym_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
+    "qsym_last_error": (C.c_char_p, [C.c_void_p]),
+    "qsym_apply_drift": (C.c_int, [C.c_void_p, C.c_double]),
+    "qsym_apply_kick": (C.c_int, [C.c_void_p, C.c_double, C.c_double]),
+    "qsym_apply_kepler": (C.c_int, [C.c_void_p, C.c_double]),
+    "qsym_fine_test": (C.c_int, [C.POINTER(Params), C.c_double, C.c_double, C.c_int64] +
+                       [C.c_void_p] * 7 + [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p]),
+    "qsym_set_kick_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int32]),
+    "qsym_get_kick_shape": (C.c_int, [C.c_void_p, _ip, _ip, _lp, _ip]),
+    "qsym_autotune": (C.c_int, [C.c_void_p, C.c_double, _dp]),
+    "qsym_profile": (C.c_int, [C.c_void_p, C.c_int32]),
+}
+
+
+def lib():
+    """Load libqsym.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class Body:
+    """Flattened input of one or several systems."""
+    m: np.ndarray
+    h: np.ndarray
+    q: np.ndarray  # (n, 3)
+    v: np.ndarray  # (n, 3)
+
+
+def _soa(a: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1, 3).T)
+
+
+class Context:
+    """One library context over one or more independent systems.
+
+    ``systems`` is a list of objects with attributes m, h, q, v, m0 (see
+    paper_1007_3458_amd.inputs.System); bodies are concatenated in order.
+    """
+
+    def __init__(self, systems, params: Params | None = None, device="cuda:0", **kw):
+        torch = _torch()
+        if not isinstance(systems, (list, tuple)):
+            systems = [systems]
+        self.params = params if params is not None else make_params(**kw)
+        self.device = torch.device(device)
+        self.nsys = len(systems)
+        sizes = [int(s.m.shape[0]) for s in systems]
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        self.n = int(self.offsets[-1])
+        self.m0 = np.array([s.m0 for s in systems], dtype=np.float64)
+        L = lib()
+        nb = C.c_int64()
+        self._check(L.qsym_workspace_bytes(C.byref(self.params), self.nsys,
+                                           self.offsets.ctypes.data_as(_lp), C.byref(nb)), None)
+        self.ws_bytes = int(nb.value)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        rc = L.qsym_create(C.byref(self.params), self.nsys, self.offsets.ctypes.data_as(_lp),
+                           self.m0.ctypes.data_as(_dp), C.c_void_p(self._ws_ptr),
+                           self.ws_bytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != 0:
+            raise QsymError(rc, "qsym_create failed")
+        self.ctx = h
+        m = np.concatenate([s.m for s in systems]).astype(np.float64)
+        hh = np.concatenate([s.h for s in systems]).astype(np.float64)
+        q = np.concatenate([np.asarray(s.q).reshape(-1, 3) for s in systems])
+        v = np.concatenate([np.asarray(s.v).reshape(-1, 3) for s in systems])
+        self.set_state(m, hh, q, v)
+
+    # ---------------------------------------------------------- helpers
+    def _check(self, rc, ctx):
+        if rc != 0:
+            msg = lib().qsym_last_error(ctx).decode() if ctx is not None else ""
+            raise QsymError(rc, msg)
+
+    def _c(self, rc):
+        self._check(rc, self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().qsym_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ state
+    def set_state(self, m, h, q, v):
+        self.m = np.ascontiguousarray(m, dtype=np.float64)
+        self.h = np.ascontiguousarray(h, dtype=np.float64)
+        qs, vs = _soa(q), _soa(v)
+        self._c(lib().qsym_set_state(self.ctx, self.m.ctypes.data, self.h.ctypes.data,
+                                     qs.ctypes.data, vs.ctypes.data, QSYM_HOST))
+
+    def set_state_device(self, m, h, q, v):
+        """Device tensors: m, h (n,), q, v (3, n) float64 on this device."""
+        self._c(lib().qsym_set_state(self.ctx, m.data_ptr(), h.data_ptr(), q.data_ptr(),
+                                     v.data_ptr(), QSYM_DEVICE))
+
+    def get_state(self):
+        qs = np.empty((3, self.n)); vs = np.empty((3, self.n))
+        self._c(lib().qsym_get_state(self.ctx, qs.ctypes.data, vs.ctypes.data, QSYM_HOST))
+        return qs.T.copy(), vs.T.copy()
+
+    # ------------------------------------------------------------- steps
+    def step(self, tau: float, nsteps: int = 1):
+        self._c(lib().qsym_step(self.ctx, float(tau), int(nsteps)))
+
+    def sync(self):
+        self._c(lib().qsym_sync(self.ctx))
+
+    def energy(self) -> np.ndarray:
+        E = np.zeros(self.nsys)
+        self._c(lib().qsym_energy(self.ctx, E.ctypes.data_as(_dp)))
+        return E
+
+    def encounters(self, cap: int = 1 << 16):
+        pairs = np.zeros((cap, 2), np.int32)
+        n = C.c_int64()
+        sid = np.zeros(self.n, np.int32)
+        self._c(lib().qsym_encounters(self.ctx, pairs.ctypes.data_as(_ip), cap, C.byref(n),
+                                      sid.ctypes.data_as(_ip)))
+        return pairs[: n.value].copy(), sid
+
+    def candidates(self, cap: int | None = None):
+        cap = cap if cap is not None else 8 * self.n + 1024
+        pairs = np.zeros((max(cap, 1), 2), np.int32)
+        n = C.c_int64()
+        self._c(lib().qsym_candidates(self.ctx, pairs.ctypes.data_as(_ip), cap, C.byref(n)))
+        return pairs[: n.value].copy()
+
+    def stats(self) -> dict:
+        st = Stats()
+        self._c(lib().qsym_stats(self.ctx, C.byref(st)))
+        return st.as_dict()
+
+    # ---------------------------------------------------- operator level
+    def apply_drift(self, dt):
+        self._c(lib().qsym_apply_drift(self.ctx, float(dt)))
+
+    def apply_kick(self, dt, crude_tau=0.0):
+        self._c(lib().qsym_apply_kick(self.ctx, float(dt), float(crude_tau)))
+
+    def apply_kepler(self, dt):
+        self._c(lib().qsym_apply_kepler(self.ctx, float(dt)))
+
+    # -------------------------------------------------------- tuning
+    def set_kick_shape(self, ipl, block, jchunk, remap=1):
+        self._c(lib().qsym_set_kick_shape(self.ctx, ipl, block, jchunk, remap))
+
+    def kick_shape(self):
+        a, b, r = C.c_int32(), C.c_int32(), C.c_int32()
+        j = C.c_int64()
+        self._c(lib().qsym_get_kick_shape(self.ctx, C.byref(a), C.byref(b), C.byref(j), C.byref(r)))
+        return dict(ipl=a.value, block=b.value, jchunk=j.value, remap=r.value)
+
+    def autotune(self, tau):
+        us = C.c_double()
+        self._c(lib().qsym_autotune(self.ctx, float(tau), C.byref(us)))
+        return us.value
+
+    def profile(self, enable=True):
+        self._c(lib().qsym_profile(self.ctx, 1 if enable else 0))
+
+
+def fine_test(params: Params, m0, tau, m, h, A, q0, v0, q1, v1, pairs, device="cuda:0"):
+    """Standalone fine sweep (Sec. 2.4) on the GPU; returns flags, lhs, rhs."""
+    torch = _torch()
+    dev = torch.device(device)
+
+    def t(a, soa=False):
+        a = _soa(a) if soa else np.ascontiguousarray(a, dtype=np.float64)
+        return torch.from_numpy(a).to(dev)
+
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    k = pairs.shape[0]
+    n = int(np.asarray(m).shape[0])
+    if k and (pairs.min() < 0 or pairs.max() >= n):
+        raise ValueError("pair index outside [0, n)")
+    for a in (h, A):
+        if np.asarray(a).shape[0] != n:
+            raise ValueError("per-body arrays must all have n entries")
+    for a in (q0, v0, q1, v1):
+        if np.asarray(a).reshape(-1, 3).shape[0] != n:
+            raise ValueError("state arrays must be (n, 3)")
+    tm, th, tA = t(m), t(h), t(A)
+    tq0, tv0, tq1, tv1 = t(q0, True), t(v0, True), t(q1, True), t(v1, True)
+    tp = torch.from_numpy(pairs).to(dev)
+    flags = torch.zeros(max(k, 1), dtype=torch.int32, device=dev)
+    lhs = torch.zeros(max(k, 1), dtype=torch.float64, device=dev)
+    rhs = torch.zeros(max(k, 1), dtype=torch.float64, device=dev)
+    st = torch.cuda.current_stream(dev)
+    rc = lib().qsym_fine_test(C.byref(params), float(m0), float(tau), n, tm.data_ptr(), th.data_ptr(),
+                              tA.data_ptr(), tq0.data_ptr(), tv0.data_ptr(), tq1.data_ptr(),
+                              tv1.data_ptr(), k, tp.data_ptr(), flags.data_ptr(), lhs.data_ptr(),
+                              rhs.data_ptr(), C.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise QsymError(rc, "qsym_fine_test failed")
+    return (flags.cpu().numpy()[:k].astype(bool), lhs.cpu().numpy()[:k], rhs.cpu().numpy()[:k])

@@ -1,0 +1,320 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Operator by operator on identical inputs, then whole steps in lockstep
+(both sides start every step from the same state).  Tolerances:
+  * accelerations / velocities / positions: 1e-13 relative per operator,
+    1e-12 relative per whole step (the oracle's rounding order differs);
+  * encounter flags: bit-exact, except pairs within 1e-12 of the threshold
+    (lockstep runs count those and expect none);
+  * integer outputs (candidate sets, sets, labels): exact.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1007_3458_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_1007_3458_amd import qsym
+    qsym.lib()
+    return qsym
+
+
+def crowded(n, seed, m=1e-6):
+    """Planets + planetesimals packed near a = 5 (forces encounters)."""
+    return inputs.make_disk(f"crowd{n}", seed, n - 4, m, 4.5, 6.0, "uniform", "uniform", 0.05, 0.01)
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def per_body_rel(a, b):
+    na = np.linalg.norm(a - b, axis=1)
+    nb = np.maximum(np.linalg.norm(b, axis=1), 1e-300)
+    return np.max(na / nb)
+
+
+SYSTEMS = {
+    "small": lambda: inputs.small(),
+    "ragged1029": lambda: inputs.scaled_disk(1025, seed=12),
+    "crowd300": lambda: crowded(300, 3),
+}
+
+SHAPES = [dict(ipl=1, block=128, jchunk=128, remap=0), dict(ipl=2, block=256, jchunk=256, remap=1),
+          dict(ipl=4, block=256, jchunk=512, remap=1), dict(ipl=2, block=128, jchunk=384, remap=1)]
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+@pytest.mark.parametrize("shape", range(len(SHAPES)))
+def test_kick_parity(Q, orc, name, shape):
+    s = SYSTEMS[name]()
+    s.v[:] = 0.0  # v1 = dt * a exactly: no cancellation in the comparison
+    say("kick parity", name, SHAPES[shape], s.n)
+    ctx = Q.Context(s)
+    sh = dict(SHAPES[shape])
+    ctx.set_kick_shape(**sh)
+    ctx.apply_kick(1.0)
+    _, v1 = ctx.get_state()
+    a_gpu = v1 - s.v
+    a_orc = orc.accel(s.G, s.m, s.q)
+    assert per_body_rel(a_gpu, a_orc) < 1e-13
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+def test_crude_candidates_match(Q, orc, name):
+    s = SYSTEMS[name]()
+    say("crude candidates", name)
+    p = orc.make_params()
+    tau = 0.05
+    ctx = Q.Context(s)
+    ctx.apply_kick(0.0, crude_tau=tau)
+    got = {tuple(x) for x in ctx.candidates()}
+    A, ve = orc.prepass(1.0, s.q, s.v)
+    ref = {tuple(x) for x in orc.crude(p, tau, s.q, s.h, A, ve)}
+    # any disagreement must sit on the threshold (different rounding order)
+    for (i, j) in got ^ ref:
+        r2 = np.sum((s.q[j] - s.q[i]) ** 2)
+        R = 3.0 * (s.h[i] + s.h[j]) * (A[i] + A[j]) / 2
+        lim = 1.1 * (R + tau * (ve[i] + ve[j]))
+        assert abs(r2 - lim * lim) <= 1e-12 * lim * lim, (i, j)
+    assert len(got ^ ref) == 0 or len(ref) > 0
+    ctx.close()
+
+
+def test_drift_parity(Q, orc):
+    s = crowded(300, 4)
+    say("drift parity")
+    ctx = Q.Context(s)
+    ctx.apply_drift(0.37)
+    q1, v1 = ctx.get_state()
+    qo = orc.drift(s.m0, s.m, s.q, s.v, 0.37)
+    assert rel(q1, qo) < 1e-15
+    assert np.array_equal(v1, s.v)
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("dt", [0.05, 0.5, -0.3])
+def test_kepler_parity(Q, orc, mode, dt):
+    s = inputs.kepler_test(5003, seed=31)
+    say("kepler parity", mode, dt)
+    ctx = Q.Context(s, kepler_mode=mode)
+    ctx.apply_kepler(dt)
+    q1, v1 = ctx.get_state()
+    qo, vo, it, fails = orc.kepler(1.0, s.q, s.v, dt, mode)
+    assert fails == 0
+    assert per_body_rel(q1, qo) < 1e-13
+    assert per_body_rel(v1, vo) < 1e-13
+    st = ctx.stats()
+    assert sum(st["kepler_hist"]) == s.n
+    # same iteration counts up to convergence-threshold ties
+    hist_o = np.bincount(it, minlength=32)[:32]
+    assert np.abs(np.array(st["kepler_hist"]) - hist_o).sum() <= 0.01 * s.n
+    ctx.close()
+
+
+def test_fine_flags_bit_exact(Q, orc):
+    """Identical inputs -> identical comparison operands and flags, including
+    pairs placed within rounding of the threshold."""
+    say("fine bit exact")
+    rng = np.random.Generator(np.random.PCG64(17))
+    n = 400
+    q0 = rng.normal(size=(n, 3)) * 0.2 + np.array([5.0, 0.0, 0.0])
+    v0 = rng.normal(size=(n, 3)) * 0.05
+    q1 = q0 + 0.05 * v0 + rng.normal(size=(n, 3)) * 1e-4
+    v1 = v0 + rng.normal(size=(n, 3)) * 1e-3
+    m = rng.uniform(1e-9, 1e-3, n)
+    h = np.cbrt(m / 3.0)
+    A = rng.uniform(4.0, 6.0, n)
+    pairs = np.array([(i, j) for i in range(0, n, 3) for j in range(i + 1, n, 7)], np.int32)
+    for hill_mode in (0, 1):
+        for aE in (3.0, 0.7):
+            p_o = orc.make_params(aE=aE, hill_mode=hill_mode)
+            p_g = Q.make_params(aE=aE, hill_mode=hill_mode)
+            fo, lo, ro = orc.fine(p_o, 0.05, pairs, m, h, A, q0, v0, q1, v1)
+            fg, lg, rg = Q.fine_test(p_g, 1.0, 0.05, m, h, A, q0, v0, q1, v1, pairs)
+            assert np.array_equal(fo, fg)
+            assert np.array_equal(lo, lg) and np.array_equal(ro, rg)
+            assert 0 < fo.sum() < len(fo)
+
+
+def _lockstep(Q, orc, s, nsteps, tau=0.05, **kw):
+    p_o = orc.make_params(**{k: v for k, v in kw.items() if k in orc.DEFAULTS})
+    ctx = Q.Context(s, **kw)
+    q, v = s.q.copy(), s.v.copy()
+    tot_enc = 0
+    border = 0
+    for k in range(nsteps):
+        ctx.set_state(s.m, s.h, q, v)
+        ctx.step(tau, 1)
+        ctx.sync()
+        qg, vg = ctx.get_state()
+        pg, sid = ctx.encounters()
+        qo, vo, r = orc.step(p_o, tau, s.m, s.h, q, v)
+        assert r.rc == 0
+        eo = {tuple(x) for x in r.pairs}
+        eg = {tuple(x) for x in pg}
+        if eo != eg:
+            border += len(eo ^ eg)
+        assert np.array_equal(pg, np.array(sorted(eg), np.int32).reshape(-1, 2))
+        tot_enc += len(eo)
+        assert per_body_rel(qg, qo) < 1e-12, (k, per_body_rel(qg, qo))
+        assert per_body_rel(vg, vo) < 1e-12, (k, per_body_rel(vg, vo))
+        # set labels: GPU set ids ordered by smallest member, oracle labels = smallest member
+        lab = r.label
+        roots = sorted({x for x in lab if x >= 0})
+        want = np.array([roots.index(x) if x >= 0 else -1 for x in lab])
+        if not border:
+            assert np.array_equal(sid, want)
+        q, v = qo, vo
+    ctx.close()
+    return tot_enc, border
+
+
+@pytest.mark.parametrize("name,nsteps", [("small", 20), ("crowd300", 20), ("ragged1029", 4)])
+def test_step_lockstep(Q, orc, name, nsteps):
+    s = SYSTEMS[name]()
+    say("lockstep", name, nsteps)
+    enc, border = _lockstep(Q, orc, s, nsteps)
+    assert border == 0
+    if name != "ragged1029":
+        assert enc > 0
+
+
+def test_step_lockstep_hermite_heavy(Q, orc):
+    """Massive crowded bodies: many Hermite substeps per set."""
+    s = crowded(120, 9, m=3e-5)
+    say("lockstep hermite heavy")
+    enc, border = _lockstep(Q, orc, s, 10)
+    assert enc > 0 and border == 0
+
+
+def test_energy_parity(Q, orc):
+    for s in (inputs.small(), crowded(300, 5), inputs.scaled_disk(1029, seed=3)):
+        say("energy", s.name)
+        ctx = Q.Context(s)
+        E = ctx.energy()[0]
+        Eo = orc.energy(s.G, s.m0, s.m, s.q, s.v)
+        assert abs(E - Eo) <= 1e-13 * abs(Eo)
+        ctx.close()
+
+
+def test_full_size_step_disk16k(Q, orc):
+    """Full plain-FP64 workload size: one whole step of 16388 bodies against
+    the oracle, every output compared."""
+    s = inputs.disk16k()
+    say("full size disk16k")
+    ctx = Q.Context(s)
+    ctx.step(0.05, 1)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    pg, _ = ctx.encounters()
+    qo, vo, r = orc.step(orc.make_params(), 0.05, s.m, s.h, s.q, s.v)
+    assert per_body_rel(qg, qo) < 1e-12
+    assert per_body_rel(vg, vo) < 1e-12
+    assert {tuple(x) for x in pg} == {tuple(x) for x in r.pairs}
+    st = ctx.stats()
+    assert st["n_encounters"] == r.stats["n_encounters"] > 0
+    assert st["n_sets"] == r.stats["n_sets"]
+    ctx.close()
+
+
+def test_batched_equals_single(Q, orc):
+    sizes = [64, 300, 1, 2, 777, 130]
+    systems = [inputs.batch_system(k, n) for k, n in enumerate(sizes)]
+    say("batched", sizes)
+    ctx = Q.Context(systems)
+    ctx.step(0.05, 3)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    E = ctx.energy()
+    off = ctx.offsets
+    p = orc.make_params()
+    for k, s in enumerate(systems):
+        q, v = s.q, s.v
+        for _ in range(3):
+            q, v, r = orc.step(p, 0.05, s.m, s.h, q, v)
+        sl = slice(off[k], off[k + 1])
+        assert per_body_rel(qg[sl], q) < 1e-12
+        assert per_body_rel(vg[sl], v) < 1e-12
+        assert abs(E[k] - orc.energy(s.G, s.m0, s.m, q, v)) <= 1e-12 * abs(E[k])
+    ctx.close()
+
+
+def test_determinism_graph_eager_and_resume(Q):
+    s = crowded(300, 6)
+    say("determinism")
+    a = Q.Context(s)
+    a.step(0.05, 6)
+    qa, va = a.get_state()
+    b = Q.Context(s)
+    b.profile(True)            # eager launches, no graph
+    b.step(0.05, 6)
+    qb, vb = b.get_state()
+    assert np.array_equal(qa, qb) and np.array_equal(va, vb)
+    c = Q.Context(s)
+    c.step(0.05, 2)
+    qc, vc = c.get_state()
+    c.close()
+    d = Q.Context(s)
+    d.set_state(s.m, s.h, qc, vc)
+    d.step(0.05, 4)
+    qd, vd = d.get_state()
+    assert np.array_equal(qa, qd) and np.array_equal(va, vd)
+    for x in (a, b, d):
+        x.close()
+
+
+def test_autotune_keeps_results(Q, orc):
+    s = inputs.scaled_disk(2049, seed=5)
+    say("autotune")
+    s.v[:] = 0.0
+    ctx = Q.Context(s)
+    us = ctx.autotune(0.05)
+    assert us > 0
+    ctx.apply_kick(1.0)
+    _, v1 = ctx.get_state()
+    assert per_body_rel(v1 - s.v, orc.accel(s.G, s.m, s.q)) < 1e-13
+    ctx.close()
+
+
+def test_candidate_overflow_is_reported(Q):
+    s = crowded(300, 7)
+    say("overflow path")
+    ctx = Q.Context(s, pair_capacity=2)
+    ctx.step(0.05, 1)
+    with pytest.raises(Q.QsymError) as e:
+        ctx.sync()
+    assert e.value.code == -6
+    ctx.close()
+
+
+def test_edge_sizes(Q, orc):
+    for n in (1, 2, 3, 255, 256, 257):
+        s = inputs.scaled_disk(max(n - 4, 1), seed=40 + n) if n > 4 else crowded(5, n).copy()
+        if n <= 4:
+            s = inputs.System("tiny", 1.0, 1.0, s.m[:n], s.q[:n], s.v[:n])
+        say("edge size", s.n)
+        ctx = Q.Context(s)
+        ctx.step(0.05, 2)
+        ctx.sync()
+        qg, vg = ctx.get_state()
+        q, v = s.q, s.v
+        for _ in range(2):
+            q, v, _ = orc.step(orc.make_params(), 0.05, s.m, s.h, q, v)
+        assert per_body_rel(qg, q) < 1e-12 and per_body_rel(vg, v) < 1e-12
+        ctx.close()
