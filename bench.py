@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the hybrid symplectic step on one MI355X.
+
+Default workload: the plain FP64 path on a 16388-body disk (4 planets +
+16384 planetesimals of 1e-8, a ~ U[15, 40], Rayleigh e and i), tau = 0.05,
+encounter radius 3 mutual Hill radii, encounters on.  One "step" is the
+whole hybrid step: drift, kick with the fused crude sweep, Kepler, fine
+sweep, sets, corrections + Hermite, second kick, drift.
+
+Prints one JSON line.  `value` is pair-interactions per second (two all-pairs
+kicks per step, N(N-1) ordered pairs each) over the timed steps, inputs
+resident in HBM.  The timed steps run with HIP events around every kernel
+(no graph) so the kick kernel's average duration comes from the same region;
+graph-replay throughput is reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
+FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector
+FLOP_PAIR = 20               # per ordered pair (sub 3, r^2 5, rsqrt 2, m/r^3 4, fma 6)
+FLOP_CRUDE = 6               # per unordered pair (fused crude sweep)
+
+
+def workload(name):
+    from paper_1007_3458_amd import inputs
+    if name == "disk16k":
+        return [inputs.disk16k()], "4 planets + 16384 planetesimals (m=1e-8, a~U[15,40], e~Rayleigh(0.05), i~Rayleigh(0.025)), tau=0.05, aE=3 mutual Hill radii, encounters on"
+    if name == "disk128k":
+        return [inputs.disk128k()], "4 planets + 131072 planetesimals (m=2e-9), tau=0.05, aE=3 mutual Hill radii, encounters on"
+    if name == "small":
+        return [inputs.small()], "4 planets + 100 planetesimals, tau=0.05"
+    if name == "batch":
+        return inputs.batch(), "512 systems, N~logU[64,4096]: 1 Jupiter-mass planet + planetesimals (m=1e-8, a~U[3,10]), tau=0.05"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("qsym_kernels.hpp", "qsym_common.hpp", "qsym.hip"):
+        with open(os.path.join(ROOT, "paper_1007_3458_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name, prec):
+    """HBM bytes per kick launch from the committed rocprofv3 counter summary,
+    when it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"kick_{name}_p{prec}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(systems, tau, seconds):
+    """The oracle (as it stands) on the host cores, a bounded sample of steps."""
+    import oracle
+    oracle.build()
+    p = oracle.make_params()
+    s = systems[0]
+    q, v = s.q, s.v
+    t0 = time.perf_counter()
+    q, v, _ = oracle.step(p, tau, s.m, s.h, q, v)
+    one = time.perf_counter() - t0
+    k = max(1, min(200, int(seconds / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    for _ in range(k):
+        q, v, _ = oracle.step(p, tau, s.m, s.h, q, v)
+    dt = time.perf_counter() - t0
+    n = s.n
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": 2.0 * n * (n - 1) * k / dt, "unit": "pair-interactions/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{k} whole hybrid steps of the first system ({n} bodies) after 1 untimed step",
+            "steps_per_s": k / dt, "cpu": model}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="disk16k", choices=["disk16k", "disk128k", "small", "batch"])
+    ap.add_argument("--precision", type=int, default=0, choices=[0, 1])
+    ap.add_argument("--tau", type=float, default=0.05)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph-pass", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs one process on one MI355X "
+              "(the multi-GPU design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1007_3458_amd import qsym
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    systems, desc = workload(args.workload)
+    ntot = sum(s.n for s in systems)
+    pairs_per_step = sum(2.0 * s.n * (s.n - 1) for s in systems)
+    ctx = qsym.Context(systems, precision=args.precision)
+    tune_us = None if args.no_autotune else ctx.autotune(args.tau)
+    shape = ctx.kick_shape()
+    ctx.step(args.tau, args.warmup)
+    ctx.sync()
+    E0 = ctx.energy()
+
+    # timed region: eager launches with HIP events around each kernel
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(args.tau, args.steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = ctx.stats()
+    ctx.profile(False)
+    T = t1 - t0
+    value = pairs_per_step * args.steps / T
+    kern = {}
+    for k, name in enumerate(qsym.PHASES):
+        if st["phase_calls"][k]:
+            kern[name] = st["phase_us"][k] / st["phase_calls"][k]
+
+    graph_sps = None
+    if not args.no_graph_pass:
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        ctx.step(args.tau, args.steps)
+        ctx.sync()
+        torch.cuda.synchronize()
+        graph_sps = args.steps / (time.perf_counter() - g0)
+    E1 = ctx.energy()
+    st2 = ctx.stats()
+    energy_err = float(max(abs(E1[k] / E0[k] - 1.0) for k in range(len(E0))))
+
+    # roofline of the dominant kernel: the kick with the fused crude sweep
+    t_kick = kern.get("kick+crude")
+    flops = sum(s.n * (s.n - 1) * FLOP_PAIR + s.n * (s.n - 1) / 2 * FLOP_CRUDE for s in systems)
+    peak = FP64_PEAK_TFLOPS if args.precision == 0 else FP32_PEAK_TFLOPS
+    achieved = flops / (t_kick * 1e-6) / 1e12 if t_kick else None
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": (achieved / peak) if achieved else None,
+            "traffic": measured_traffic(args.workload, args.precision),
+            "kernel": "k_kick (E_Int + fused crude sweep)",
+            "flop_per_launch": flops, "avg_launch_us": t_kick,
+            "pairs_per_s_kernel": (sum(s.n * (s.n - 1) for s in systems) / (t_kick * 1e-6)) if t_kick else None}
+    out = {
+        "metric": "pair-interactions/s and steps/s vs plain FP64 path at matched energy error",
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * T / args.steps,
+        "steps_per_s": args.steps / T,
+        "steps_per_s_graph": graph_sps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f32 pair terms, f64 elsewhere",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "n_bodies": ntot, "n_systems": len(systems),
+                   "tau": args.tau, "precision": args.precision, "kick_shape": shape,
+                   "autotune_kick_us": tune_us},
+        "energy_error": energy_err,
+        "encounters_last_step": st["n_encounters"],
+        "encounters_total": st2["total_encounters"],
+        "hermite_substeps_total": st2["total_substeps"],
+        "kernel_avg_us": kern,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(systems, args.tau, args.cpu_seconds)
+    out["host"] = platform.node()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -201,7 +201,11 @@ struct qsym_ctx {
     double gtau = 0.0;
     bool gvalid = false;
     bool profile = false;
-    hipEvent_t pev[2 * 16] = {};
+    // profiling: event pairs recorded around launches without waiting; the
+    // pending pairs are read (and the events recycled) at the next flush
+    std::vector<hipEvent_t> pool;
+    std::vector<int> pend_phase;
+    size_t pool_used = 0;
     double phase_us[kPhases] = {};
     long long phase_calls[kPhases] = {};
     bool mlp_loaded = false;
@@ -366,23 +370,48 @@ hipError_t launch_kick(qsym_ctx *c, int mode, hipStream_t st)
 
 int nblocks_chunks(qsym_ctx *c) { return (int)c->T.bchunk.size(); }
 
+// accumulate the timings of all pending event pairs (waits for them)
+void flush_profile(qsym_ctx *c)
+{
+    for (size_t k = 0; k < c->pend_phase.size(); ++k) {
+        float ms = 0.f;
+        (void)hipEventSynchronize(c->pool[2 * k + 1]);
+        if (hipEventElapsedTime(&ms, c->pool[2 * k], c->pool[2 * k + 1]) == hipSuccess) {
+            c->phase_us[c->pend_phase[k]] += 1000.0 * ms;
+            c->phase_calls[c->pend_phase[k]] += 1;
+        }
+    }
+    c->pend_phase.clear();
+    c->pool_used = 0;
+}
+
+hipEvent_t pool_event(qsym_ctx *c)
+{
+    if (c->pool_used == c->pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->pool.push_back(e);
+    }
+    return c->pool[c->pool_used++];
+}
+
 struct Timer {
     qsym_ctx *c;
     int ph;
+    hipEvent_t e1 = nullptr;
     Timer(qsym_ctx *cc, int p) : c(cc), ph(p)
     {
-        if (c->profile) hipEventRecord(c->pev[2 * ph], c->stream);
+        if (!c->profile) return;
+        if (c->pend_phase.size() >= 4096) flush_profile(c);
+        hipEvent_t e0 = pool_event(c);
+        e1 = pool_event(c);
+        if (!e0 || !e1) { e1 = nullptr; return; }
+        c->pend_phase.push_back(ph);
+        (void)hipEventRecord(e0, c->stream);
     }
     ~Timer()
     {
-        if (c->profile) {
-            (void)hipEventRecord(c->pev[2 * ph + 1], c->stream);
-            (void)hipEventSynchronize(c->pev[2 * ph + 1]);
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, c->pev[2 * ph], c->pev[2 * ph + 1]);
-            c->phase_us[ph] += 1000.0 * ms;
-            c->phase_calls[ph] += 1;
-        }
+        if (e1) (void)hipEventRecord(e1, c->stream);
     }
 };
 
@@ -555,8 +584,6 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(QSYM_EHIP);
     if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess) return bail(QSYM_EHIP);
     if (hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) return bail(QSYM_EHIP);
-    for (int k = 0; k < 32; ++k)
-        if (hipEventCreate(&c->pev[k]) != hipSuccess) return bail(QSYM_EHIP);
     build_tables(c);
     enter(c);
     hipStream_t st = c->stream;
@@ -617,8 +644,7 @@ void qsym_destroy(qsym_ctx *c)
     if (c->stream) hipStreamSynchronize(c->stream);
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     if (c->graph) hipGraphDestroy(c->graph);
-    for (int k = 0; k < 32; ++k)
-        if (c->pev[k]) hipEventDestroy(c->pev[k]);
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
     if (c->stream) hipStreamDestroy(c->stream);
@@ -785,6 +811,7 @@ int qsym_stats(qsym_ctx *c, qsym_stats_t *out)
     unsigned long long h[C_COUNT];
     int rc = read_ctr(c, h);
     if (rc) return rc;
+    flush_profile(c);
     std::memset(out, 0, sizeof(*out));
     out->steps = (int64_t)h[C_STEPS];
     out->n_candidates = (int64_t)h[C_CAND];
@@ -939,6 +966,8 @@ int qsym_autotune(qsym_ctx *c, double tau, double *us)
 int qsym_profile(qsym_ctx *c, int32_t enable)
 {
     if (!c) return QSYM_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    flush_profile(c);
     c->profile = enable != 0;
     if (enable) {
         for (int k = 0; k < kPhases; ++k) {
