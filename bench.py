@@ -107,7 +107,8 @@ def main():
     ap.add_argument("--tau", type=float, default=0.05)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the kick shapes now instead of using the tuned table")
     ap.add_argument("--no-graph-pass", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -125,8 +126,11 @@ def main():
     ntot = sum(s.n for s in systems)
     pairs_per_step = sum(2.0 * s.n * (s.n - 1) for s in systems)
     ctx = qsym.Context(systems, precision=args.precision)
-    tune_us = None if args.no_autotune else ctx.autotune(args.tau)
-    shape = ctx.kick_shape()
+    tune_us = None
+    if args.autotune or ctx.tuned is None:
+        tune_us = ctx.autotune(args.tau)
+    shape_source = "autotuned now" if tune_us is not None else "tuned table"
+    shape = {"plain": ctx.kick_shape(0), "crude": ctx.kick_shape(1)}
     ctx.step(args.tau, args.warmup)
     ctx.sync()
     E0 = ctx.energy()
@@ -188,7 +192,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n_bodies": ntot, "n_systems": len(systems),
                    "tau": args.tau, "precision": args.precision, "kick_shape": shape,
-                   "autotune_kick_us": tune_us},
+                   "kick_shape_source": shape_source, "autotune_kick_us": tune_us},
         "energy_error": energy_err,
         "encounters_last_step": st["n_encounters"],
         "encounters_total": st2["total_encounters"],

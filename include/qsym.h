@@ -162,14 +162,19 @@ int qsym_fine_test(const qsym_params *p, double m0, double tau, int64_t n, const
                    const double *q1, const double *v1, int64_t npairs, const int32_t *pairs,
                    int32_t *flags, double *lhs, double *rhs, void *stream);
 
-/* Kick-kernel launch shape chosen by the autotuner (or forced here):
+/* Launch shape of the two kick kernels, which = 0 for the plain kick,
+ * 1 for the kick with the fused crude sweep (-1: both, set only):
  * ipl = i-bodies per lane (1, 2, 4), block = threads per workgroup (128,
- * 256), jchunk = j-bodies per workgroup (multiple of block), remap = 1 for
- * the XCD-aware workgroup order.  qsym_autotune times the candidate shapes
- * on the current state and keeps the fastest; *us receives its kick time. */
-int qsym_set_kick_shape(qsym_ctx *ctx, int32_t ipl, int32_t block, int64_t jchunk, int32_t remap);
-int qsym_get_kick_shape(qsym_ctx *ctx, int32_t *ipl, int32_t *block, int64_t *jchunk,
-                        int32_t *remap);
+ * 256), jchunk = j-bodies per workgroup (a multiple of block and at least
+ * the smallest j-chunk the workspace was sized for), remap = 1 for the
+ * XCD-aware workgroup order.  qsym_autotune times every candidate shape of
+ * both kicks on the current state (without moving it), keeps the fastest,
+ * and writes the two kick times in microseconds to us[0] (plain) and us[1]
+ * (crude sweep).  Results do not depend on the shape beyond rounding. */
+int qsym_set_kick_shape(qsym_ctx *ctx, int32_t which, int32_t ipl, int32_t block, int64_t jchunk,
+                        int32_t remap);
+int qsym_get_kick_shape(qsym_ctx *ctx, int32_t which, int32_t *ipl, int32_t *block,
+                        int64_t *jchunk, int32_t *remap);
 int qsym_autotune(qsym_ctx *ctx, double tau, double *us);
 
 /* Profiling: when enabled, qsym_step launches kernels directly (no graph)

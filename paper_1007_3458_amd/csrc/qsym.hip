@@ -35,13 +35,14 @@ struct Shape {
 struct Layout {
     size_t off_state = 0, off_snap = 0, off_aux = 0, off_acc = 0, off_pm = 0, off_bsys = 0;
     size_t off_sysoff = 0, off_sysm0 = 0, off_sysS = 0, off_syspoff = 0, off_sysc0 = 0;
-    size_t off_bchunk = 0, off_items = 0, off_eitems = 0, off_syse0 = 0, off_cand = 0;
-    size_t off_enc = 0, off_encs = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0;
+    size_t off_bchunk = 0, off_kchunk = 0, off_items = 0, off_eitems = 0, off_syse0 = 0, off_cand = 0;
+    size_t off_enc = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0;
     size_t off_hw = 0, off_ctr = 0, off_epart = 0, off_E = 0, off_mlp = 0;
     size_t total = 0;
     long long np = 0;          // padded body count
     long long acc_len = 0;     // doubles of kick partials
     long long nchunks = 0;     // O(N) chunks
+    long long nkchunks = 0;    // Kepler-pass chunks
     long long max_items = 0;   // kick items of the finest allowed shape
     long long n_eitems = 0;
     long long cap = 0;         // candidate capacity
@@ -51,7 +52,7 @@ struct Layout {
 struct Tables {
     std::vector<int> sys_off, sys_S, sys_c0, sys_e0;
     std::vector<long long> sys_poff;
-    std::vector<int4> bchunk;
+    std::vector<int4> bchunk, kchunk;
     std::vector<KickItem> eitems;
     std::vector<int> body_sys;
 };
@@ -83,11 +84,13 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
         const long long S = (n + L.jchunk_min - 1) / L.jchunk_min;
         L.acc_len += 3 * S * n;
         L.nchunks += (n + kChunk - 1) / kChunk;
+        L.nkchunks += (n + kChunkK - 1) / kChunkK;
         L.max_items += ((n + 127) / 128) * S;
         L.n_eitems += ((n + 255) / 256) * ((n + 1023) / 1024);
     }
     L.acc_len = std::max<long long>(L.acc_len, 3);
     L.nchunks = std::max<long long>(L.nchunks, 1);
+    L.nkchunks = std::max<long long>(L.nkchunks, 1);
     L.max_items = std::max<long long>(L.max_items, 1) + 8;
     L.n_eitems = std::max<long long>(L.n_eitems, 1);
     L.cap = p.pair_capacity > 0 ? p.pair_capacity : 8 * ntot + 1024;
@@ -106,16 +109,16 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_bsys, (size_t)L.np * sizeof(int));
     take(L.off_sysoff, (size_t)(nsys + 1) * sizeof(int));
     take(L.off_sysm0, (size_t)std::max(nsys, 1) * D);
-    take(L.off_sysS, (size_t)std::max(nsys, 1) * sizeof(int));
+    take(L.off_sysS, 2 * (size_t)std::max(nsys, 1) * sizeof(int));
     take(L.off_syspoff, (size_t)std::max(nsys, 1) * sizeof(long long));
     take(L.off_sysc0, (size_t)(nsys + 1) * sizeof(int));
     take(L.off_bchunk, (size_t)L.nchunks * sizeof(int4));
-    take(L.off_items, (size_t)L.max_items * sizeof(KickItem));
+    take(L.off_kchunk, (size_t)L.nkchunks * sizeof(int4));
+    take(L.off_items, 2 * (size_t)L.max_items * sizeof(KickItem));
     take(L.off_eitems, (size_t)L.n_eitems * sizeof(KickItem));
     take(L.off_syse0, (size_t)(nsys + 1) * sizeof(int));
     take(L.off_cand, (size_t)L.cap * sizeof(int2));
     take(L.off_enc, (size_t)kCapE * sizeof(int2));
-    take(L.off_encs, (size_t)kCapE * sizeof(int2));
     take(L.off_setstart, (size_t)(kCapU + 1) * sizeof(int));
     take(L.off_setmem, (size_t)kCapU * sizeof(int));
     take(L.off_setrc, (size_t)kCapU * D);
@@ -161,12 +164,12 @@ Dev bind(char *base, const Layout &L)
     d.sys_poff = (long long *)(base + L.off_syspoff);
     d.sys_c0 = (int *)(base + L.off_sysc0);
     d.bchunk = (int4 *)(base + L.off_bchunk);
+    d.kchunk = (int4 *)(base + L.off_kchunk);
     d.items = (KickItem *)(base + L.off_items);
     d.eitems = (KickItem *)(base + L.off_eitems);
     d.sys_e0 = (int *)(base + L.off_syse0);
     d.cand = (int2 *)(base + L.off_cand);
     d.enc = (int2 *)(base + L.off_enc);
-    d.enc_sorted = (int2 *)(base + L.off_encs);
     d.set_start = (int *)(base + L.off_setstart);
     d.set_mem = (int *)(base + L.off_setmem);
     d.set_rc = (double *)(base + L.off_setrc);
@@ -192,9 +195,9 @@ struct qsym_ctx {
     Layout L;
     Dev d;
     char *base = nullptr;
-    Shape shape;
-    int nitems = 0;
-    int grid_kick = 0;
+    Shape shape[2];      // [0] plain kick, [1] kick with the crude sweep
+    int nitems[2] = {0, 0};
+    int grid_kick[2] = {0, 0};
     Tables T;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -209,6 +212,7 @@ struct qsym_ctx {
     double phase_us[kPhases] = {};
     long long phase_calls[kPhases] = {};
     bool mlp_loaded = false;
+    double tau_crude = 0.0;  // |tau| of the crude sweep being enqueued
     std::string err;
 };
 
@@ -257,6 +261,7 @@ void build_tables(qsym_ctx *c)
     T.sys_c0.assign(nsys + 1, 0);
     T.sys_e0.assign(nsys + 1, 0);
     T.bchunk.clear();
+    T.kchunk.clear();
     T.eitems.clear();
     T.body_sys.assign((size_t)c->L.np, 0);
     long long poff = 0;
@@ -268,6 +273,8 @@ void build_tables(qsym_ctx *c)
         T.sys_c0[s] = (int)T.bchunk.size();
         for (int b = 0; b < n; b += kChunk)
             T.bchunk.push_back(make_int4(s, (int)c->off[s] + b, std::min(kChunk, n - b), 0));
+        for (int b = 0; b < n; b += kChunkK)
+            T.kchunk.push_back(make_int4(s, (int)c->off[s] + b, std::min(kChunkK, n - b), 0));
         T.sys_e0[s] = (int)T.eitems.size();
         for (int ib = 0; ib < n; ib += 256)
             for (int jb = 0; jb < n; jb += 1024) {
@@ -281,13 +288,14 @@ void build_tables(qsym_ctx *c)
     T.sys_c0[nsys] = (int)T.bchunk.size();
     T.sys_e0[nsys] = (int)T.eitems.size();
     if (T.bchunk.empty()) T.bchunk.push_back(make_int4(0, 0, 0, 0));
+    if (T.kchunk.empty()) T.kchunk.push_back(make_int4(0, 0, 0, 0));
     if (T.eitems.empty()) T.eitems.push_back(KickItem{0, 0, 0, 0, 0, 0});
 }
 
-// kick work items for the current shape; systems largest first
-int build_items(qsym_ctx *c, std::vector<KickItem> &items, std::vector<int> &sysS)
+// kick work items for a launch shape; systems largest first, each system's
+// items j-chunk major (consecutive items share j data)
+int build_items(qsym_ctx *c, const Shape &sh, std::vector<KickItem> &items, std::vector<int> &sysS)
 {
-    const Shape &sh = c->shape;
     const long long BI = (long long)sh.block * sh.ipl;
     const long long JC = sh.jchunk;
     items.clear();
@@ -312,24 +320,24 @@ int build_items(qsym_ctx *c, std::vector<KickItem> &items, std::vector<int> &sys
     return (int)items.size();
 }
 
-int upload_shape(qsym_ctx *c)
+int upload_shape(qsym_ctx *c, int which)
 {
     std::vector<KickItem> items;
     std::vector<int> sysS;
-    const int n = build_items(c, items, sysS);
+    const int n = build_items(c, c->shape[which], items, sysS);
     if ((long long)n > c->L.max_items)
         return fail(c, QSYM_EINVAL, "kick shape needs more work items than the workspace holds");
     for (int s = 0; s < c->nsys; ++s) {
         const long long Smax = (nsys_bodies(c->off, s) + c->L.jchunk_min - 1) / c->L.jchunk_min;
         if (sysS[s] > Smax) return fail(c, QSYM_EINVAL, "j-chunk smaller than the workspace allows");
     }
-    c->nitems = n;
-    c->grid_kick = std::max(8, (n + 7) / 8 * 8);
+    c->nitems[which] = n;
+    c->grid_kick[which] = std::max(8, (n + 7) / 8 * 8);
     if (n > 0)
-        HIPCHK(c, hipMemcpyAsync(c->d.items, items.data(), sizeof(KickItem) * n,
-                                 hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->d.sys_S, sysS.data(), sizeof(int) * c->nsys, hipMemcpyHostToDevice,
-                             c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->d.items + (size_t)which * c->L.max_items, items.data(),
+                                 sizeof(KickItem) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d.sys_S + (size_t)which * c->nsys, sysS.data(), sizeof(int) * c->nsys,
+                             hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->gvalid = false;
     return QSYM_OK;
@@ -339,8 +347,10 @@ int upload_shape(qsym_ctx *c)
 template <int BS, int IPL>
 hipError_t launch_kick_bs(qsym_ctx *c, int mode, int prec, hipStream_t st)
 {
-    KickArgs ka{c->d, c->p.G, c->L.cap, c->nitems, c->shape.remap};
-    const dim3 g(c->shape.remap ? c->grid_kick : std::max(c->nitems, 1)), b(BS);
+    const int w = mode ? 1 : 0;
+    KickArgs ka{c->d, c->d.items + (size_t)w * c->L.max_items, c->p.G, c->L.cap, c->nitems[w],
+                c->shape[w].remap, c->p.hill_mode, c->p.aE, c->p.crude_safety, c->tau_crude, 1e-200};
+    const dim3 g(c->shape[w].remap ? c->grid_kick[w] : std::max(c->nitems[w], 1)), b(BS);
     if (prec == 0) {
         if (mode == 0) hipLaunchKernelGGL((k_kick<BS, IPL, 0, 0>), g, b, 0, st, ka);
         else if (mode == 1) hipLaunchKernelGGL((k_kick<BS, IPL, 1, 0>), g, b, 0, st, ka);
@@ -353,11 +363,13 @@ hipError_t launch_kick_bs(qsym_ctx *c, int mode, int prec, hipStream_t st)
     return hipGetLastError();
 }
 
+// mode 0: plain kick; 1, 2: kick with the crude sweep (mutual, sum)
 hipError_t launch_kick(qsym_ctx *c, int mode, hipStream_t st)
 {
+    const int w = mode ? 1 : 0;
     const int prec = c->p.precision;
-    const int ipl = c->shape.ipl, bs = c->shape.block;
-    if (c->nitems == 0) return hipSuccess;
+    const int ipl = c->shape[w].ipl, bs = c->shape[w].block;
+    if (c->nitems[w] == 0) return hipSuccess;
     if (bs == 256) {
         if (ipl == 1) return launch_kick_bs<256, 1>(c, mode, prec, st);
         if (ipl == 2) return launch_kick_bs<256, 2>(c, mode, prec, st);
@@ -416,11 +428,11 @@ struct Timer {
 };
 
 hipError_t run_drift(qsym_ctx *c, double dt, int prepass, double tau_crude, int reset,
-                     hipStream_t st, int phase)
+                     hipStream_t st, int phase, int count_step = 0)
 {
     Timer tm(c, phase);
     DriftArgs a{c->d, dt, c->p.G, tau_crude, c->p.aE, c->p.crude_safety, prepass, c->p.hill_mode,
-                reset};
+                reset, count_step};
     hipLaunchKernelGGL(k_drift, dim3(nblocks_chunks(c)), dim3(kChunk), 0, st, a);
     return hipGetLastError();
 }
@@ -432,25 +444,35 @@ hipError_t run_momentum(qsym_ctx *c, hipStream_t st)
     return hipGetLastError();
 }
 
+// kick apply (+ snapshot, + Kepler, + momentum partials).  Launches with a
+// Kepler pass use 64-body workgroups (the solve is latency bound, so every
+// CU gets work); the momentum partials need the 256-body chunks.
 hipError_t run_apply(qsym_ctx *c, double dt_kick, double dt_kep, int do_kick, int do_kep,
-                     int snapshot, int momentum, hipStream_t st, int phase)
+                     int snapshot, int momentum, hipStream_t st, int phase, int which)
 {
     Timer tm(c, phase);
-    ApplyArgs a{c->d, dt_kick, dt_kep, c->p.G, do_kick, do_kep, snapshot, c->p.kepler_mode, momentum};
-    hipLaunchKernelGGL(k_apply_kepler, dim3(nblocks_chunks(c)), dim3(kChunk), 0, st, a);
+    const bool small = do_kep && !momentum;
+    ApplyArgs a{c->d, small ? c->d.kchunk : c->d.bchunk, c->d.sys_S + (size_t)which * c->nsys,
+                dt_kick, dt_kep, c->p.G, do_kick, do_kep, snapshot, c->p.kepler_mode, momentum};
+    if (small)
+        hipLaunchKernelGGL(k_apply_kepler<kChunkK>, dim3((unsigned)c->T.kchunk.size()), dim3(kChunkK), 0,
+                           st, a);
+    else
+        hipLaunchKernelGGL(k_apply_kepler<kChunk>, dim3(nblocks_chunks(c)), dim3(kChunk), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t run_kick(qsym_ctx *c, int crude, hipStream_t st, int phase)
+hipError_t run_kick(qsym_ctx *c, int crude, double tau_crude, hipStream_t st, int phase)
 {
     Timer tm(c, phase);
+    c->tau_crude = std::fabs(tau_crude);
     return launch_kick(c, crude ? 1 + c->p.hill_mode : 0, st);
 }
 
 int fine_grid(qsym_ctx *c)
 {
     long long g = (c->L.cap + 255) / 256;
-    return (int)std::max<long long>(1, std::min<long long>(g, 2048));
+    return (int)std::max<long long>(1, std::min<long long>(g, 128));
 }
 
 // one full hybrid step (Sec. 2.3) enqueued on st
@@ -461,9 +483,9 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
     // 1: drift tau/2 + per-body encounter terms, reset per-step counters
     if ((e = run_drift(c, half, 1, tau, 1, st, P_DRIFT)) != hipSuccess) return e;
     // 2: kick tau/2 with the crude sweep fused in
-    if ((e = run_kick(c, 1, st, P_KICK1)) != hipSuccess) return e;
+    if ((e = run_kick(c, 1, tau, st, P_KICK1)) != hipSuccess) return e;
     // 2-3: apply the kick, snapshot (q0, v0), Kepler tau -> (q1, v1)
-    if ((e = run_apply(c, half, tau, 1, 1, 1, 0, st, P_APPLY1)) != hipSuccess) return e;
+    if ((e = run_apply(c, half, tau, 1, 1, 1, 0, st, P_APPLY1, 1)) != hipSuccess) return e;
     // 4: fine sweep, sets, r_crit
     {
         Timer tm(c, P_FINE);
@@ -481,16 +503,14 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
     {
         Timer tm(c, P_HERMITE);
         HermArgs ha{c->d, tau, c->p.G, c->p.epsH, c->p.eta, c->p.eta_s, c->p.max_substeps};
-        hipLaunchKernelGGL(k_hermite, dim3(512), dim3(kHermThreads), 0, st, ha);
+        hipLaunchKernelGGL(k_hermite, dim3(256), dim3(kHermThreads), 0, st, ha);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // 9: kick tau/2 (all pairs), applied with the momentum partials
-    if ((e = run_kick(c, 0, st, P_KICK2)) != hipSuccess) return e;
-    if ((e = run_apply(c, half, 0.0, 1, 0, 0, 1, st, P_APPLY2)) != hipSuccess) return e;
+    if ((e = run_kick(c, 0, 0.0, st, P_KICK2)) != hipSuccess) return e;
+    if ((e = run_apply(c, half, 0.0, 1, 0, 0, 1, st, P_APPLY2, 0)) != hipSuccess) return e;
     // 10: drift tau/2
-    if ((e = run_drift(c, half, 0, 0.0, 0, st, P_DRIFT2)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_count_step, dim3(1), dim3(1), 0, st, c->d);
-    return hipGetLastError();
+    return run_drift(c, half, 0, 0.0, 0, st, P_DRIFT2, 1);
 }
 
 void enter(qsym_ctx *c)
@@ -603,36 +623,36 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.bchunk, T.bchunk.data(), sizeof(int4) * T.bchunk.size(),
                          hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.kchunk, T.kchunk.data(), sizeof(int4) * T.kchunk.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.eitems, T.eitems.data(), sizeof(KickItem) * T.eitems.size(),
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.body_sys, T.body_sys.data(), sizeof(int) * T.body_sys.size(),
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipStreamSynchronize(st) == hipSuccess;
     if (!ok) return bail(QSYM_EHIP);
-    // default kick shape: block 256, 2 i per lane, j-split so that the
-    // grid has >= 2048 workgroups where the size allows
-    c->shape.block = 256;
-    c->shape.ipl = 2;
-    long long nmax = 0;
-    for (int s = 0; s < nsys; ++s) nmax = std::max<long long>(nmax, nsys_bodies(c->off, s));
-    long long jc = 4096;
-    long long nib = 0;
-    for (int s = 0; s < nsys; ++s) nib += (nsys_bodies(c->off, s) + 511) / 512;
-    while (jc > c->L.jchunk_min) {
-        long long items = 0;
-        for (int s = 0; s < nsys; ++s) {
-            const long long n = nsys_bodies(c->off, s);
-            items += ((n + 511) / 512) * ((n + jc - 1) / jc);
+    // default kick shapes (the autotuner or a tuned table replaces them):
+    // block 128, one i per lane, j-split so that the grid has >= 4096
+    // workgroups where the size allows
+    for (int w = 0; w < 2; ++w) {
+        Shape &sh = c->shape[w];
+        sh.block = 128;
+        sh.ipl = 1;
+        sh.remap = 0;
+        long long jc = 8192;
+        while (jc > c->L.jchunk_min) {
+            long long items = 0;
+            for (int s = 0; s < nsys; ++s) {
+                const long long n = nsys_bodies(c->off, s);
+                items += ((n + 127) / 128) * ((n + jc - 1) / jc);
+            }
+            if (items >= 4096) break;
+            jc /= 2;
         }
-        if (items >= 2048) break;
-        jc /= 2;
+        sh.jchunk = std::max<long long>(jc, c->L.jchunk_min);
+        sh.jchunk = (sh.jchunk + 127) / 128 * 128;
     }
-    c->shape.jchunk = std::max<long long>(jc, c->L.jchunk_min);
-    c->shape.jchunk = (c->shape.jchunk + 255) / 256 * 256;
-    c->shape.remap = 1;
-    (void)nib;
-    (void)nmax;
-    if (upload_shape(c) != QSYM_OK) return bail(QSYM_EINVAL);
+    if (upload_shape(c, 0) != QSYM_OK || upload_shape(c, 1) != QSYM_OK) return bail(QSYM_EINVAL);
     leave(c);
     *out = c;
     return QSYM_OK;
@@ -765,8 +785,20 @@ int qsym_encounters(qsym_ctx *c, int32_t *pairs, int64_t cap, int64_t *n_pairs, 
     const long long held = std::min<long long>(ne, kCapE);
     const long long k = std::min<long long>(held, cap);
     hipStream_t st = c->stream;
-    if (k > 0)
-        HIPCHK(c, hipMemcpyAsync(pairs, c->d.enc_sorted, sizeof(int2) * k, hipMemcpyDeviceToHost, st));
+    if (k > 0) {
+        // the device keeps the append order; the canonical (i < j,
+        // lexicographic) order is produced here
+        std::vector<int2> raw((size_t)held);
+        HIPCHK(c, hipMemcpyAsync(raw.data(), c->d.enc, sizeof(int2) * held, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        std::sort(raw.begin(), raw.end(), [](const int2 &a, const int2 &b) {
+            return a.x != b.x ? a.x < b.x : a.y < b.y;
+        });
+        for (long long q = 0; q < k; ++q) {
+            pairs[2 * q] = raw[q].x;
+            pairs[2 * q + 1] = raw[q].y;
+        }
+    }
     if (set_id) {
         for (long long i = 0; i < c->ntot; ++i) set_id[i] = -1;
         const long long ns = (long long)h[C_NSETS], nu = (long long)h[C_NU];
@@ -850,8 +882,8 @@ int qsym_apply_kick(qsym_ctx *c, double dt, double crude_tau)
     hipStream_t st = c->stream;
     const int crude = crude_tau != 0.0;
     if (crude) HIPCHK(c, run_drift(c, 0.0, 1, crude_tau, 1, st, P_DRIFT));
-    HIPCHK(c, run_kick(c, crude, st, crude ? P_KICK1 : P_KICK2));
-    HIPCHK(c, run_apply(c, dt, 0.0, 1, 0, 0, 1, st, P_APPLY2));
+    HIPCHK(c, run_kick(c, crude, crude_tau, st, crude ? P_KICK1 : P_KICK2));
+    HIPCHK(c, run_apply(c, dt, 0.0, 1, 0, 0, 1, st, P_APPLY2, crude ? 1 : 0));
     leave(c);
     return QSYM_OK;
 }
@@ -860,7 +892,7 @@ int qsym_apply_kepler(qsym_ctx *c, double dt)
 {
     if (!c) return QSYM_EINVAL;
     enter(c);
-    HIPCHK(c, run_apply(c, 0.0, dt, 0, 1, 0, 1, c->stream, P_APPLY1));
+    HIPCHK(c, run_apply(c, 0.0, dt, 0, 1, 0, 1, c->stream, P_APPLY1, 0));
     leave(c);
     return QSYM_OK;
 }
@@ -883,32 +915,37 @@ int qsym_fine_test(const qsym_params *p, double m0, double tau, int64_t n, const
     return QSYM_OK;
 }
 
-int qsym_set_kick_shape(qsym_ctx *c, int32_t ipl, int32_t block, int64_t jchunk, int32_t remap)
+int qsym_set_kick_shape(qsym_ctx *c, int32_t which, int32_t ipl, int32_t block, int64_t jchunk,
+                        int32_t remap)
 {
     if (!c) return QSYM_EINVAL;
-    if ((ipl != 1 && ipl != 2 && ipl != 4) || (block != 128 && block != 256) || jchunk <= 0 ||
-        jchunk % block || jchunk < c->L.jchunk_min || (remap != 0 && remap != 1))
+    if ((which < -1 || which > 1) || (ipl != 1 && ipl != 2 && ipl != 4) ||
+        (block != 128 && block != 256) || jchunk <= 0 || jchunk % block ||
+        jchunk < c->L.jchunk_min || (remap != 0 && remap != 1))
         return fail(c, QSYM_EINVAL, "kick shape out of range");
-    Shape old = c->shape;
-    c->shape.ipl = ipl;
-    c->shape.block = block;
-    c->shape.jchunk = jchunk;
-    c->shape.remap = remap;
-    int rc = upload_shape(c);
-    if (rc) {
-        c->shape = old;
-        (void)upload_shape(c);
+    for (int w = 0; w < 2; ++w) {
+        if (which >= 0 && w != which) continue;
+        const Shape old = c->shape[w];
+        c->shape[w] = Shape{ipl, block, jchunk, remap};
+        const int rc = upload_shape(c, w);
+        if (rc) {
+            c->shape[w] = old;
+            (void)upload_shape(c, w);
+            return rc;
+        }
     }
-    return rc;
+    return QSYM_OK;
 }
 
-int qsym_get_kick_shape(qsym_ctx *c, int32_t *ipl, int32_t *block, int64_t *jchunk, int32_t *remap)
+int qsym_get_kick_shape(qsym_ctx *c, int32_t which, int32_t *ipl, int32_t *block, int64_t *jchunk,
+                        int32_t *remap)
 {
-    if (!c) return QSYM_EINVAL;
-    if (ipl) *ipl = c->shape.ipl;
-    if (block) *block = c->shape.block;
-    if (jchunk) *jchunk = c->shape.jchunk;
-    if (remap) *remap = c->shape.remap;
+    if (!c || which < 0 || which > 1) return QSYM_EINVAL;
+    const Shape &sh = c->shape[which];
+    if (ipl) *ipl = sh.ipl;
+    if (block) *block = sh.block;
+    if (jchunk) *jchunk = sh.jchunk;
+    if (remap) *remap = sh.remap;
     return QSYM_OK;
 }
 
@@ -921,45 +958,51 @@ int qsym_autotune(qsym_ctx *c, double tau, double *us)
     // the crude sweep needs the per-body terms: compute them at the current
     // state without moving it (drift by 0)
     HIPCHK(c, run_drift(c, 0.0, 1, tau, 1, st, P_OTHER));
+    c->tau_crude = std::fabs(tau);
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    const Shape keep = c->shape;
-    Shape best = keep;
-    double best_us = 1e300;
     const int ipls[3] = {1, 2, 4};
     const int blocks[2] = {128, 256};
-    for (int bi = 0; bi < 2; ++bi)
-        for (int ii = 0; ii < 3; ++ii)
-            for (long long jc = c->L.jchunk_min; jc <= std::max<long long>(c->L.jchunk_min, 8192); jc *= 2) {
-                const long long jcr = (jc + blocks[bi] - 1) / blocks[bi] * blocks[bi];
-                for (int rm = 0; rm < 2; ++rm) {
-                    c->shape = Shape{ipls[ii], blocks[bi], jcr, rm};
-                    if (upload_shape(c) != QSYM_OK) continue;
-                    // warm-up, then 3 timed launches (crude sweep on)
-                    (void)launch_kick(c, 1 + c->p.hill_mode, st);
-                    (void)hipEventRecord(e0, st);
-                    for (int r = 0; r < 3; ++r) launch_kick(c, 1 + c->p.hill_mode, st);
-                    (void)hipEventRecord(e1, st);
-                    (void)hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    (void)hipEventElapsedTime(&ms, e0, e1);
-                    const double t_us = 1000.0 * ms / 3.0;
-                    if (t_us < best_us) {
-                        best_us = t_us;
-                        best = c->shape;
+    int rc = QSYM_OK;
+    for (int w = 0; w < 2; ++w) {
+        const int mode = w ? 1 + c->p.hill_mode : 0;
+        Shape best = c->shape[w];
+        double best_us = 1e300;
+        for (int bi = 0; bi < 2; ++bi)
+            for (int ii = 0; ii < 3; ++ii)
+                for (long long jc = c->L.jchunk_min; jc <= std::max<long long>(c->L.jchunk_min, 8192);
+                     jc *= 2) {
+                    const long long jcr = (jc + blocks[bi] - 1) / blocks[bi] * blocks[bi];
+                    for (int rm = 0; rm < 2; ++rm) {
+                        c->shape[w] = Shape{ipls[ii], blocks[bi], jcr, rm};
+                        if (upload_shape(c, w) != QSYM_OK) continue;
+                        // warm-up, then 3 timed launches
+                        (void)launch_kick(c, mode, st);
+                        (void)hipEventRecord(e0, st);
+                        for (int r = 0; r < 3; ++r) (void)launch_kick(c, mode, st);
+                        (void)hipEventRecord(e1, st);
+                        (void)hipEventSynchronize(e1);
+                        float ms = 0.f;
+                        (void)hipEventElapsedTime(&ms, e0, e1);
+                        const double t_us = 1000.0 * ms / 3.0;
+                        if (t_us < best_us) {
+                            best_us = t_us;
+                            best = c->shape[w];
+                        }
                     }
                 }
-            }
+        c->shape[w] = best;
+        const int r = upload_shape(c, w);
+        if (r) rc = r;
+        if (us) us[w] = best_us;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    c->shape = best;
-    int rc = upload_shape(c);
     // leave the counters of the next step clean
     HIPCHK(c, run_drift(c, 0.0, 1, tau, 1, st, P_OTHER));
     HIPCHK(c, hipStreamSynchronize(st));
     leave(c);
-    if (us) *us = best_us;
     return rc;
 }
 

@@ -7,13 +7,13 @@
 namespace qsym {
 
 constexpr int kChunk = 256;        // bodies per workgroup of the O(N) kernels
+constexpr int kChunkK = 64;        // bodies per workgroup of the Kepler pass
 constexpr int kCapE = 4096;        // encounter pairs per step handled on chip
 constexpr int kCapU = 2 * kCapE;   // bodies taking part in encounters
 constexpr int kHist = 32;          // Kepler iteration histogram bins
 constexpr int kSMax = 64;          // largest j-split of one system
-constexpr int kSetsThreads = 1024; // workgroup of the set-partition kernel
-constexpr int kHermThreads = 256;  // workgroup of the Hermite kernel
-constexpr int kHermMax = 4096;     // largest encounter set the Hermite accepts
+constexpr int kSetsThreads = 256;  // workgroup of the set-partition kernel
+constexpr int kHermThreads = 512;  // workgroup of the Hermite kernel
 constexpr int kMlpParams = 1249;   // 4->32->32->1 network
 constexpr double kPi = 3.14159265358979323846;
 
@@ -60,16 +60,16 @@ struct Dev {
     int *body_sys;                              // system of each body
     int *sys_off;                               // [nsys+1] first body of each system
     double *sys_m0;                             // central masses
-    int *sys_S;                                 // j-split of each system
+    int *sys_S;                                 // [2][nsys] j-split per kick shape
     long long *sys_poff;                        // offset of its partials in acc
     int *sys_c0;                                // [nsys+1] first O(N) chunk
     int4 *bchunk;                               // O(N) chunks (sys, first, count, 0)
-    KickItem *items;                            // kick work items
+    int4 *kchunk;                               // kChunkK-body chunks of the Kepler pass
+    KickItem *items;                            // [2][max_items] kick work items
     KickItem *eitems;                           // energy work items
     int *sys_e0;                                // [nsys+1] first energy item
     int2 *cand;                                 // crude candidates
     int2 *enc;                                  // encounter pairs (append order)
-    int2 *enc_sorted;                           // canonical encounter list
     int *set_start;                             // [kCapU+1]
     int *set_mem;                               // [kCapU] member body indices
     double *set_rc;                             // [kCapU] r_crit per set

@@ -94,15 +94,15 @@ __global__ __launch_bounds__(kChunk) void k_momentum(Dev d)
 // ------------------------------------------------------------------------
 // E_Dft(dt): Q_i += dt * P / m0 (Sec. 2, H_Dft), optionally followed by the
 // per-body quantities of the encounter search (Sec. 2.4) at the drifted
-// state: a_i (osculating semi-major axis, r_i when unbound), and the crude
-// sweep terms  ch_i = c_s a_E h_i / 2 (mutual) or c_s a_E h_i a_i (sum),
-// cv_i = c_s |tau| sqrt(2 mu / r_i).  The first workgroup resets the
-// per-step counters.
+// state: a_i (osculating semi-major axis, r_i when unbound), the Hill-radius
+// term ch_i = h_i (mutual) or h_i a_i (sum) and the escape speed
+// cv_i = sqrt(2 mu / r_i).  The first workgroup resets the per-step
+// counters.
 // ------------------------------------------------------------------------
 struct DriftArgs {
     Dev d;
     double dt, G, tau_crude, aE, cs;
-    int prepass, hill_mode, reset;
+    int prepass, hill_mode, reset, count_step;
 };
 
 __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
@@ -121,6 +121,7 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
         d.ctr[C_SUB] = 0;
         d.ctr[C_NU] = 0;
     }
+    if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) d.ctr[C_STEPS] += 1;
     const int t = threadIdx.x;
     if (t >= bc.z) return;
     const int i = bc.y + t;
@@ -139,8 +140,8 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
         const double A = (inva > 0.0) ? 1.0 / inva : r;
         const double ve = sqrt(2.0 * mu / r);
         d.A[i] = A;
-        d.ch[i] = (a.hill_mode == 0) ? 0.5 * a.cs * a.aE * d.h[i] : a.cs * a.aE * d.h[i] * A;
-        d.cv[i] = a.cs * fabs(a.tau_crude) * ve;
+        d.ch[i] = (a.hill_mode == 0) ? d.h[i] : d.h[i] * A;
+        d.cv[i] = ve;
     }
 }
 
@@ -160,13 +161,22 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
 // FP32 pair term (PREC 1): the separation is formed in FP64 and rounded to
 // FP32, the rest of the pair term is FP32 (hardware rsq), sums are FP32
 // within a j-tile and accumulated across tiles in FP64.
+//
+// Crude sweep: per j-tile the maxima of (h or h a, a, ve) bound the exact
+// threshold of every pair of the tile from above, so the pair loop only
+// compares r^2 with one per-i bound (one compare per pair); the few pairs
+// under it take the exact test of the definition.
 // ------------------------------------------------------------------------
 struct KickArgs {
     Dev d;
+    const KickItem *items;   // work items of this kick's launch shape
     double G;
-    long long cap;   // candidate capacity
+    long long cap;     // candidate capacity
     int nitems;
-    int remap;       // XCD-aware workgroup order
+    int remap;         // XCD-aware workgroup order
+    int hill_mode;     // crude test form
+    double aE, cs, tau_abs;
+    double r2seed;     // 1e-200, passed at run time so it stays a register operand
 };
 
 // workgroup b of a grid of g (multiple of 8) runs on XCD b % 8; give each
@@ -177,19 +187,84 @@ __device__ __forceinline__ int xcd_item(int b, int g)
     return (b & 7) * per + (b >> 3);
 }
 
-template <int MODE>
-__device__ __forceinline__ void crude_test(double r2, double hi, double Ai, double vi, double hj,
-                                           double Aj, double vj, int i, int j, const Dev &d,
-                                           long long cap)
+__device__ __forceinline__ double wave_max(double v)
 {
-    double thr;
-    if (MODE == 1)
-        thr = fma(hi + hj, Ai + Aj, vi + vj);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Crude sweep, exact form (Sec. 2.4 reading): evaluated only for the pairs
+// that passed the per-tile bound; same operands and operation order as the
+// definition:  |Q_j-Q_i|^2 < (c_s (R_up + |tau| (ve_i + ve_j)))^2.
+__device__ __forceinline__ void crude_exact(const KickArgs &ka, int i, int j)
+{
+    const Dev &d = ka.d;
+    if (j <= i) return;
+    const double dx = d.x[j] - d.x[i];
+    const double dy = d.y[j] - d.y[i];
+    const double dz = d.z[j] - d.z[i];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    double Rup;
+    if (ka.hill_mode == 0)
+        Rup = ka.aE * (d.h[i] + d.h[j]) * (d.A[i] + d.A[j]) / 2.0;
     else
-        thr = (hi + hj) + (vi + vj);
-    if (MODE != 0 && r2 < thr * thr && j > i) {
-        unsigned long long slot = atomicAdd(&d.ctr[C_CAND], 1ull);
-        if ((long long)slot < cap) d.cand[slot] = make_int2(i, j);
+        Rup = ka.aE * (d.h[i] * d.A[i] + d.h[j] * d.A[j]);
+    const double lim = ka.cs * (Rup + ka.tau_abs * (d.cv[i] + d.cv[j]));
+    if (r2 < lim * lim) {
+        const unsigned long long slot = atomicAdd(&d.ctr[C_CAND], 1ull);
+        if ((long long)slot < ka.cap) d.cand[slot] = make_int2(i, j);
+    }
+}
+
+// FP64 pair term (see the header comment of the kick).  r^2 carries a
+// 1e-200 seed (so the own pair gives 0 * finite = 0 and r^2 >= 1e-184 is
+// unchanged); the correction m y0^3 (1 + 3/2 e + 15/8 e^2) is written as
+// ms0 + 3/2 t + 15/8 t e (t = ms0 e) so that each constant is an
+// instruction literal.
+__device__ __forceinline__ void pair64(const double4 &pj, double xi, double yi, double zi,
+                                       double seed, double &ax, double &ay, double &az, double &r2)
+{
+    const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
+    r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, seed)));
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double y2 = y0 * y0;
+    const double e = fma(-r2, y2, 1.0);
+    const double ms0 = pj.w * (y2 * y0);
+    const double t = ms0 * e;
+    const double ms = fma(t * e, 1.875, fma(t, 1.5, ms0));
+    ax = fma(ms, dx, ax);
+    ay = fma(ms, dy, ay);
+    az = fma(ms, dz, az);
+}
+
+// padding of a partial j-tile: far away (r^2 ~ 3e36, finite in FP32) and massless, so it
+// adds nothing and never passes the crude bound
+constexpr double kFar = 1e18;
+
+// pairs under the tile bound are queued in LDS (lane, i slot, j offset)
+// and given the exact test after the tile, so the pair loop has no call
+constexpr int kCrudeQ = 512;
+
+template <int BS, int IPL, int MODE>
+__device__ __forceinline__ void crude_drain(const KickArgs &ka, const KickItem &it, int jt,
+                                            const int *ii, unsigned *qbuf, unsigned *qn)
+{
+    const unsigned n = *qn;
+    const int tid = threadIdx.x;
+    if (n <= (unsigned)kCrudeQ) {
+        for (unsigned e = tid; e < n; e += BS) {
+            const unsigned v = qbuf[e];
+            const int lt = (int)(v >> 16), u = (int)((v >> 8) & 0xffu), jj = (int)(v & 0xffu);
+            if (lt + u * BS < it.ni) crude_exact(ka, it.i0 + lt + u * BS, jt + jj);
+        }
+    } else {
+        // queue overflow (a dense tile): exact test of every pair of the tile
+        const int jend = min(jt + BS, it.j0 + it.nj);
+#pragma unroll
+        for (int u = 0; u < IPL; ++u)
+            if (tid + u * BS < it.ni)
+                for (int j = jt; j < jend; ++j) crude_exact(ka, ii[u], j);
     }
 }
 
@@ -201,10 +276,13 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
     int b = blockIdx.x;
     if (ka.remap) b = xcd_item(b, gridDim.x);
     if (b >= ka.nitems) return;
-    const KickItem it = d.items[b];
+    const KickItem it = ka.items[b];
+    constexpr int NW = BS / 64;
 
     __shared__ double4 sj[BS];
-    __shared__ double4 sc[MODE ? BS : 1];
+    __shared__ double smax[3][NW];
+    __shared__ unsigned qbuf[MODE ? kCrudeQ : 1];
+    __shared__ unsigned qn;
 
     double xi[IPL], yi[IPL], zi[IPL];
     double ax[IPL], ay[IPL], az[IPL];
@@ -225,62 +303,112 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
         }
         ii[u] = ok ? i : 0x7fffffff;
     }
+    if (MODE && tid == 0) qn = 0u;
     const int jend = it.j0 + it.nj;
     const double G = ka.G;
+    const double seed = ka.r2seed;
+    int qtile = -1;   // tile whose queue is pending
     for (int jt = it.j0; jt < jend; jt += BS) {
         const int j = jt + tid;
         const bool okj = j < jend;
         __syncthreads();
+        if constexpr (MODE != 0) {
+            if (qtile >= 0) {
+                if (qn) crude_drain<BS, IPL, MODE>(ka, it, qtile, ii, qbuf, &qn);
+                __syncthreads();
+                if (tid == 0) qn = 0u;
+                qtile = -1;
+            }
+        }
         sj[tid] = okj ? make_double4(d.x[j], d.y[j], d.z[j], G * d.m[j])
-                      : make_double4(0.0, 0.0, 0.0, 0.0);
-        if (MODE) sc[tid] = okj ? make_double4(d.ch[j], d.A[j], d.cv[j], 0.0)
-                                : make_double4(0.0, 0.0, 0.0, 0.0);
-        __syncthreads();
+                      : make_double4(kFar, kFar, kFar, 0.0);
         const int last_j = min(jt + BS, jend) - 1;
         const bool pred = MODE && (last_j > it.i0);
-        if constexpr (PREC == 0) {
-            if (MODE != 0 && pred) {
+        if (MODE && pred) {
+            // tile maxima of the crude-sweep terms (all non-negative)
+            double t0 = okj ? d.ch[j] : 0.0, t1 = okj ? d.A[j] : 0.0, t2 = okj ? d.cv[j] : 0.0;
+            t0 = wave_max(t0);
+            t1 = wave_max(t1);
+            t2 = wave_max(t2);
+            if ((tid & 63) == 0) {
+                smax[0][tid >> 6] = t0;
+                smax[1][tid >> 6] = t1;
+                smax[2][tid >> 6] = t2;
+            }
+        }
+        __syncthreads();
+        if constexpr (MODE != 0) {
+            if (pred) {
+                double HT = smax[0][0], AT = smax[1][0], VT = smax[2][0];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) {
+                    HT = fmax(HT, smax[0][w]);
+                    AT = fmax(AT, smax[1][w]);
+                    VT = fmax(VT, smax[2][w]);
+                }
+                // per-(i, tile) upper bound of the crude threshold: every
+                // operation is monotone in the j-terms, so th >= the exact
+                // limit of every j in the tile; the factor covers the
+                // different rounding of r^2 in the pair loop
+                double th2[IPL];
+                float fx[IPL], fy[IPL], fz[IPL];
+#pragma unroll
+                for (int u = 0; u < IPL; ++u) {
+                    fx[u] = fy[u] = fz[u] = 0.0f;
+                    double Rb;
+                    if (MODE == 1)
+                        Rb = ka.aE * (hi[u] + HT) * (Ai[u] + AT) / 2.0;
+                    else
+                        Rb = ka.aE * (hi[u] + HT);
+                    const double th = ka.cs * (Rb + ka.tau_abs * (vi[u] + VT));
+                    th2[u] = th * th * 1.000000000001;
+                }
 #pragma unroll 4
                 for (int jj = 0; jj < BS; ++jj) {
                     const double4 pj = sj[jj];
-                    const double4 cj = sc[MODE ? jj : 0];
 #pragma unroll
                     for (int u = 0; u < IPL; ++u) {
-                        const double dx = pj.x - xi[u], dy = pj.y - yi[u], dz = pj.z - zi[u];
-                        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                        const double r2c = fmax(r2, 1e-200);
-                        const double y0 = __builtin_amdgcn_rsq(r2c);
-                        const double y2 = y0 * y0;
-                        const double e = fma(-r2c, y2, 1.0);
-                        const double c = fma(e, 1.875, 1.5);
-                        const double ms0 = pj.w * (y2 * y0);
-                        const double ms = fma(ms0 * e, c, ms0);
-                        ax[u] = fma(ms, dx, ax[u]);
-                        ay[u] = fma(ms, dy, ay[u]);
-                        az[u] = fma(ms, dz, az[u]);
-                        crude_test<MODE>(r2, hi[u], Ai[u], vi[u], cj.x, cj.y, cj.z, ii[u], jt + jj,
-                                         d, ka.cap);
+                        double r2;
+                        if constexpr (PREC == 0) {
+                            pair64(pj, xi[u], yi[u], zi[u], seed, ax[u], ay[u], az[u], r2);
+                        } else {
+                            const double dxd = pj.x - xi[u], dyd = pj.y - yi[u], dzd = pj.z - zi[u];
+                            r2 = fma(dzd, dzd, fma(dyd, dyd, fma(dxd, dxd, seed)));
+                            const float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+                            const float r2f = fmaxf((float)r2, 1e-24f);
+                            const float y0 = __builtin_amdgcn_rsqf(r2f);
+                            const float ms = (float)pj.w * (y0 * y0 * y0);
+                            fx[u] = fmaf(ms, dx, fx[u]);
+                            fy[u] = fmaf(ms, dy, fy[u]);
+                            fz[u] = fmaf(ms, dz, fz[u]);
+                        }
+                        if (r2 < th2[u]) {
+                            const unsigned k = atomicAdd(&qn, 1u);
+                            if (k < (unsigned)kCrudeQ)
+                                qbuf[k] = ((unsigned)tid << 16) | ((unsigned)u << 8) | (unsigned)jj;
+                        }
                     }
                 }
-            } else {
-#pragma unroll 4
-                for (int jj = 0; jj < BS; ++jj) {
-                    const double4 pj = sj[jj];
+                if constexpr (PREC != 0) {
 #pragma unroll
                     for (int u = 0; u < IPL; ++u) {
-                        const double dx = pj.x - xi[u], dy = pj.y - yi[u], dz = pj.z - zi[u];
-                        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                        const double r2c = fmax(r2, 1e-200);
-                        const double y0 = __builtin_amdgcn_rsq(r2c);
-                        const double y2 = y0 * y0;
-                        const double e = fma(-r2c, y2, 1.0);
-                        const double c = fma(e, 1.875, 1.5);
-                        const double ms0 = pj.w * (y2 * y0);
-                        const double ms = fma(ms0 * e, c, ms0);
-                        ax[u] = fma(ms, dx, ax[u]);
-                        ay[u] = fma(ms, dy, ay[u]);
-                        az[u] = fma(ms, dz, az[u]);
+                        ax[u] += (double)fx[u];
+                        ay[u] += (double)fy[u];
+                        az[u] += (double)fz[u];
                     }
+                }
+                qtile = jt;
+                continue;
+            }
+        }
+        if constexpr (PREC == 0) {
+#pragma unroll 4
+            for (int jj = 0; jj < BS; ++jj) {
+                const double4 pj = sj[jj];
+#pragma unroll
+                for (int u = 0; u < IPL; ++u) {
+                    double r2;
+                    pair64(pj, xi[u], yi[u], zi[u], seed, ax[u], ay[u], az[u], r2);
                 }
             }
         } else {
@@ -293,21 +421,15 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
                 const float mj = (float)pj.w;
 #pragma unroll
                 for (int u = 0; u < IPL; ++u) {
-                    const double dxd = pj.x - xi[u], dyd = pj.y - yi[u], dzd = pj.z - zi[u];
-                    const float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
+                    const float dx = (float)(pj.x - xi[u]), dy = (float)(pj.y - yi[u]),
+                                dz = (float)(pj.z - zi[u]);
                     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    const float r2c = fmaxf(r2, 1e-30f);
+                    const float r2c = fmaxf(r2, 1e-24f);
                     const float y0 = __builtin_amdgcn_rsqf(r2c);
                     const float ms = mj * (y0 * y0 * y0);
                     fx[u] = fmaf(ms, dx, fx[u]);
                     fy[u] = fmaf(ms, dy, fy[u]);
                     fz[u] = fmaf(ms, dz, fz[u]);
-                    if (pred) {
-                        const double4 cj = sc[MODE ? jj : 0];
-                        const double r2d = fma(dzd, dzd, fma(dyd, dyd, dxd * dxd));
-                        crude_test<MODE>(r2d, hi[u], Ai[u], vi[u], cj.x, cj.y, cj.z, ii[u],
-                                         jt + jj, d, ka.cap);
-                    }
                 }
             }
 #pragma unroll
@@ -317,6 +439,10 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
                 az[u] += (double)fz[u];
             }
         }
+    }
+    if constexpr (MODE != 0) {
+        __syncthreads();
+        if (qtile >= 0 && qn) crude_drain<BS, IPL, MODE>(ka, it, qtile, ii, qbuf, &qn);
     }
     const int s = it.sys;
     const int ns = d.sys_off[s + 1] - d.sys_off[s];
@@ -333,10 +459,11 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
 }
 
 // sum of the kick partials of body i (local index il of system s)
-__device__ __forceinline__ void sum_partials(const Dev &d, int s, int il, double a[3])
+__device__ __forceinline__ void sum_partials(const Dev &d, const int *sysS, int s, int il,
+                                             double a[3])
 {
     const int ns = d.sys_off[s + 1] - d.sys_off[s];
-    const int S = d.sys_S[s];
+    const int S = sysS[s];
     const double *p = d.acc + d.sys_poff[s] + il;
     double ax = 0.0, ay = 0.0, az = 0.0;
     for (int c = 0; c < S; ++c) {
@@ -515,19 +642,22 @@ __device__ int kepler_advance(double mu, int mode, const float *mlp, double dt, 
 // ------------------------------------------------------------------------
 struct ApplyArgs {
     Dev d;
+    const int4 *chunks; // body chunks of this launch (one per workgroup)
+    const int *sysS;   // j-split of the kick being applied
     double dt_kick, dt_kep, G;
     int do_kick, do_kep, snapshot, kepler_mode, momentum;
 };
 
-__global__ __launch_bounds__(kChunk) void k_apply_kepler(ApplyArgs a)
+template <int BS>
+__global__ __launch_bounds__(BS) void k_apply_kepler(ApplyArgs a)
 {
-    __shared__ double lds[kChunk];
+    __shared__ double lds[BS];
     __shared__ unsigned int hist[kHist];
     __shared__ unsigned int kmax;
     __shared__ unsigned long long ksum;
     __shared__ int bad;
     const Dev &d = a.d;
-    const int4 bc = d.bchunk[blockIdx.x];
+    const int4 bc = a.chunks[blockIdx.x];
     const int s = bc.x;
     const int t = threadIdx.x;
     if (t < kHist) hist[t] = 0;
@@ -544,7 +674,7 @@ __global__ __launch_bounds__(kChunk) void k_apply_kepler(ApplyArgs a)
         double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
         if (a.do_kick) {
             double acc[3];
-            sum_partials(d, s, i - d.sys_off[s], acc);
+            sum_partials(d, a.sysS, s, i - d.sys_off[s], acc);
             vx += a.dt_kick * acc[0];
             vy += a.dt_kick * acc[1];
             vz += a.dt_kick * acc[2];
@@ -582,7 +712,7 @@ __global__ __launch_bounds__(kChunk) void k_apply_kepler(ApplyArgs a)
     }
     if (a.momentum) {
         for (int k = 0; k < 3; ++k) {
-            double sm = block_sum<kChunk>(mom[k], lds);
+            double sm = block_sum<BS>(mom[k], lds);
             if (t == 0) d.pm[3 * blockIdx.x + k] = sm;
         }
     }
@@ -717,18 +847,17 @@ __global__ __launch_bounds__(256) void k_fine_standalone(
 template <typename T>
 __device__ void bitonic_sort_lds(T *v, int n2)
 {
-    // n2 is a power of two; ascending
+    // n2 is a power of two; ascending; one compare-exchange per thread
     for (int k = 2; k <= n2; k <<= 1) {
         for (int jx = k >> 1; jx > 0; jx >>= 1) {
-            for (int i = threadIdx.x; i < n2; i += blockDim.x) {
-                const int l = i ^ jx;
-                if (l > i) {
-                    const T a = v[i], b = v[l];
-                    const bool up = ((i & k) == 0);
-                    if ((a > b) == up) {
-                        v[i] = b;
-                        v[l] = a;
-                    }
+            for (int p = threadIdx.x; p < (n2 >> 1); p += blockDim.x) {
+                const int i = ((p & ~(jx - 1)) << 1) | (p & (jx - 1));
+                const int l = i + jx;
+                const T a = v[i], b = v[l];
+                const bool up = ((i & k) == 0);
+                if ((a > b) == up) {
+                    v[i] = b;
+                    v[l] = a;
                 }
             }
             __syncthreads();
@@ -736,11 +865,24 @@ __device__ void bitonic_sort_lds(T *v, int n2)
     }
 }
 
-// exclusive scan over n <= 2*kCapE flags (in place) by one workgroup;
-// returns the total
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// exclusive scan of v[0..n) in place by one workgroup (thread-contiguous
+// runs, wave scans, one scan of the wave totals); returns the total.
+// tmp needs blockDim/64 + 1 entries.
 __device__ int block_scan_excl(int *v, int n, int *tmp)
 {
     const int T = blockDim.x;
+    const int nw = T >> 6;
     const int per = (n + T - 1) / T;
     const int t = threadIdx.x;
     int s = 0;
@@ -748,19 +890,17 @@ __device__ int block_scan_excl(int *v, int n, int *tmp)
         const int i = t * per + k;
         if (i < n) s += v[i];
     }
-    tmp[t] = s;
+    const int incl = wave_incl_scan(s);
+    if ((t & 63) == 63) tmp[t >> 6] = incl;
     __syncthreads();
-    if (t == 0) {
-        int run = 0;
-        for (int k = 0; k < T; ++k) {
-            const int c = tmp[k];
-            tmp[k] = run;
-            run += c;
-        }
-        tmp[T] = run;
+    if (t < 64) {
+        const int w = (t < nw) ? tmp[t] : 0;
+        const int wi = wave_incl_scan(w);
+        if (t < nw) tmp[t] = wi - w;
+        if (t == nw - 1) tmp[nw] = wi;
     }
     __syncthreads();
-    int run = tmp[t];
+    int run = tmp[t >> 6] + incl - s;
     for (int k = 0; k < per; ++k) {
         const int i = t * per + k;
         if (i < n) {
@@ -769,8 +909,7 @@ __device__ int block_scan_excl(int *v, int n, int *tmp)
             run += c;
         }
     }
-    __syncthreads();
-    const int total = tmp[T];
+    const int total = tmp[nw];
     __syncthreads();
     return total;
 }
@@ -780,15 +919,32 @@ struct SetsArgs {
     double aH;
 };
 
+// binary search of v in the ascending u[0..n)
+__device__ __forceinline__ int lower_rank(const unsigned *u, int n, unsigned v)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (u[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// One workgroup, LDS only (<= kCapE pairs): unique bodies of the encounter
+// pairs (bitonic sort + scan), pairs as rank pairs, labels propagated to the
+// component minimum, members ordered by (component, index) with one more
+// sort, r_crit per set.  Ranks follow body order, so "smallest rank" is
+// "smallest body index".  The pair list itself is left in append order (the
+// ABI returns it sorted on the host).
 __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
 {
     const Dev &d = a.d;
-    __shared__ unsigned long long keys[kCapE];   // 32 KB: sorted pairs
-    __shared__ unsigned int ep[kCapU];           // 32 KB: endpoints -> unique bodies
-    __shared__ unsigned int lab[kCapU];          // 32 KB: component labels (ranks)
-    __shared__ unsigned int rp[kCapE];           // 16 KB: pairs as rank pairs
-    __shared__ int flag[kCapU];                  // 32 KB: scan scratch
-    __shared__ int tmp[kSetsThreads + 1];
+    __shared__ unsigned int ep[kCapU];   // endpoints, later member keys
+    __shared__ unsigned int uq[kCapU];   // unique bodies (ascending)
+    __shared__ unsigned int lab[kCapU];  // component labels (ranks)
+    __shared__ unsigned int rp[kCapE];   // pairs as rank pairs
+    __shared__ int flag[kCapU];          // scan scratch
+    __shared__ int tmp[kSetsThreads / 64 + 1];
     __shared__ int changed;
     const int t = threadIdx.x;
     const unsigned long long cnt = d.ctr[C_ENC];
@@ -802,27 +958,12 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     }
     const int ne = (int)cnt;
     if (ne == 0) return;
-    int n2 = 1;
-    while (n2 < ne) n2 <<= 1;
-    for (int k = t; k < n2; k += blockDim.x) {
-        if (k < ne) {
-            const int2 p = d.enc[k];
-            keys[k] = ((unsigned long long)(unsigned)p.x << 32) | (unsigned)p.y;
-        } else {
-            keys[k] = ~0ull;
-        }
-    }
-    __syncthreads();
-    bitonic_sort_lds(keys, n2);
-    for (int k = t; k < ne; k += blockDim.x)
-        d.enc_sorted[k] = make_int2((int)(keys[k] >> 32), (int)(keys[k] & 0xffffffffu));
-    // unique endpoints
     int m2 = 1;
     while (m2 < 2 * ne) m2 <<= 1;
     for (int k = t; k < m2; k += blockDim.x) {
         if (k < 2 * ne) {
-            const unsigned long long kk = keys[k >> 1];
-            ep[k] = (k & 1) ? (unsigned)(kk & 0xffffffffu) : (unsigned)(kk >> 32);
+            const int2 p = d.enc[k >> 1];
+            ep[k] = (unsigned)((k & 1) ? p.y : p.x);
         } else {
             ep[k] = 0xffffffffu;
         }
@@ -831,37 +972,21 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     bitonic_sort_lds(ep, m2);
     for (int k = t; k < 2 * ne; k += blockDim.x) flag[k] = (k == 0 || ep[k] != ep[k - 1]) ? 1 : 0;
     __syncthreads();
-    // keep a copy of the flags in lab (lab is free until the labelling)
     for (int k = t; k < 2 * ne; k += blockDim.x) lab[k] = (unsigned)flag[k];
     __syncthreads();
     const int nu = block_scan_excl(flag, 2 * ne, tmp);
-    // unique body indices staged through d.set_mem (global), then back to ep
     for (int k = t; k < 2 * ne; k += blockDim.x)
-        if (lab[k]) d.set_mem[flag[k]] = (int)ep[k];
+        if (lab[k]) uq[flag[k]] = ep[k];
     __syncthreads();
-    __threadfence_block();
-    for (int k = t; k < nu; k += blockDim.x) ep[k] = (unsigned)d.set_mem[k];
-    __syncthreads();
-    // rank pairs by binary search in the sorted unique list
     for (int k = t; k < ne; k += blockDim.x) {
-        const unsigned i = (unsigned)(keys[k] >> 32), j = (unsigned)(keys[k] & 0xffffffffu);
-        int lo = 0, hi = nu - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (ep[mid] < i) lo = mid + 1; else hi = mid;
-        }
-        const int ri = lo;
-        lo = 0;
-        hi = nu - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (ep[mid] < j) lo = mid + 1; else hi = mid;
-        }
-        rp[k] = ((unsigned)ri << 16) | (unsigned)lo;
+        const int2 p = d.enc[k];
+        const int ri = lower_rank(uq, nu, (unsigned)p.x);
+        const int rj = lower_rank(uq, nu, (unsigned)p.y);
+        rp[k] = ((unsigned)ri << 16) | (unsigned)rj;
     }
     for (int k = t; k < nu; k += blockDim.x) lab[k] = (unsigned)k;
     __syncthreads();
-    // label propagation to the component minimum
+    // label propagation to the component minimum (with pointer jumping)
     for (int iter = 0; iter < 2 * kCapU; ++iter) {
         if (t == 0) changed = 0;
         __syncthreads();
@@ -876,7 +1001,6 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
             }
         }
         __syncthreads();
-        // pointer jumping
         for (int k = t; k < nu; k += blockDim.x) {
             const unsigned l = lab[k];
             const unsigned ll = lab[l];
@@ -893,36 +1017,51 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     for (int k = t; k < nu; k += blockDim.x) flag[k] = (lab[k] == (unsigned)k) ? 1 : 0;
     __syncthreads();
     const int nsets = block_scan_excl(flag, nu, tmp);
-    // member sort keys (root rank, rank) reuse keys[]
+    // members sorted by (root rank, rank)
     int u2 = 1;
     while (u2 < nu) u2 <<= 1;
-    unsigned int *mk = (unsigned int *)keys;  // kCapU * 4 bytes fit in keys
     for (int k = t; k < u2; k += blockDim.x)
-        mk[k] = (k < nu) ? ((lab[k] << 16) | (unsigned)k) : 0xffffffffu;
+        ep[k] = (k < nu) ? ((lab[k] << 16) | (unsigned)k) : 0xffffffffu;
     __syncthreads();
-    bitonic_sort_lds(mk, u2);
+    bitonic_sort_lds(ep, u2);
+    // member k of the sorted list: body uq[r], set flag[root]; the set index
+    // is kept in lab[k] (lab is free once the keys are built)
     for (int k = t; k < nu; k += blockDim.x) {
-        const unsigned r = mk[k] & 0xffffu;
-        d.set_mem[k] = (int)ep[r];
-        const unsigned root = mk[k] >> 16;
-        const bool first = (k == 0) || ((mk[k - 1] >> 16) != root);
-        if (first) d.set_start[flag[root]] = k;
+        const unsigned r = ep[k] & 0xffffu;
+        d.set_mem[k] = (int)uq[r];
+        const unsigned root = ep[k] >> 16;
+        const bool first = (k == 0) || ((ep[k - 1] >> 16) != root);
+        const int sid = flag[root];
+        if (first) d.set_start[sid] = k;
+        lab[k] = (unsigned)sid;
     }
     if (t == 0) d.set_start[nsets] = nu;
     __syncthreads();
-    __threadfence_block();
-    // r_crit and the largest set
-    for (int sidx = t; sidx < nsets; sidx += blockDim.x) {
-        const int b0 = d.set_start[sidx], b1 = d.set_start[sidx + 1];
-        double hmax = 0.0;
-        for (int k = b0; k < b1; ++k) {
-            const int i = d.set_mem[k];
-            const double rh = d.h[i] * d.A[i];
-            if (rh > hmax) hmax = rh;
-        }
-        d.set_rc[sidx] = a.aH * hmax;
-        atomicMax(&d.ctr[C_MAXSET], (unsigned long long)(b1 - b0));
+    // r_crit = a_H max_{i in S} h_i a_i: one thread per member, max through
+    // LDS atomics on the bit patterns (non-negative doubles order as
+    // integers); flag's storage is reused (nsets <= nu / 2 <= kCapE)
+    unsigned long long *rcb = (unsigned long long *)flag;
+    for (int k = t; k < nsets; k += blockDim.x) rcb[k] = 0ull;
+    __syncthreads();
+    for (int k = t; k < nu; k += blockDim.x) {
+        const int i = (int)uq[ep[k] & 0xffffu];
+        const double rh = d.h[i] * d.A[i];
+        atomicMax(&rcb[lab[k]], (unsigned long long)__double_as_longlong(rh));
     }
+    __syncthreads();
+    unsigned int big = 0;
+    for (int sidx = t; sidx < nsets; sidx += blockDim.x)
+        d.set_rc[sidx] = a.aH * __longlong_as_double((long long)rcb[sidx]);
+    // largest set: from the member positions of the set starts
+    for (int k = t; k < nu; k += blockDim.x) {
+        const bool first = (k == 0) || (lab[k - 1] != lab[k]);
+        if (first) {
+            int e = k + 1;
+            while (e < nu && lab[e] == lab[k]) ++e;
+            if ((unsigned)(e - k) > big) big = (unsigned)(e - k);
+        }
+    }
+    if (big) atomicMax(&d.ctr[C_MAXSET], (unsigned long long)big);
     if (t == 0) {
         d.ctr[C_NSETS] = (unsigned long long)nsets;
         d.ctr[C_NU] = (unsigned long long)nu;
@@ -943,9 +1082,11 @@ __device__ __forceinline__ void transition(double s, double rc, double &K, doubl
     } else {
         const double w = kPi / 2.0;
         const double c = 1.1 / rc;
-        K = sin(w * y);
-        Kp = w * c * cos(w * y);
-        Kpp = -(w * c) * (w * c) * sin(w * y);
+        double sn, cs;
+        sincos(w * y, &sn, &cs);
+        K = sn;
+        Kp = w * c * cs;
+        Kpp = -(w * c) * (w * c) * sn;
     }
 }
 
@@ -955,124 +1096,178 @@ struct HermArgs {
     int max_substeps;
 };
 
+constexpr int kHermLds = 1024;   // members of one set staged in LDS
+
 // member scratch layout: field f of member slot k at hw[f * kCapU + k]
-enum { HX = 0, HU = 3, HA = 6, HJ = 9, HXP = 12, HUP = 15, HA1 = 18, HJ1 = 21, HXN = 24, HUN = 27,
-       HFIELDS = 30 };
+enum { HX = 0, HU = 3, HA = 6, HJ = 9, HXP = 12, HUP = 15, HFIELDS = 18 };
 
 __device__ __forceinline__ double &hw_at(const Dev &d, int f, int k) { return d.hw[f * kCapU + k]; }
 
-// W-weighted in-set acceleration on member slot a (unsoftened, Sec. 2.3
-// steps 5 and 7), positions from field f (or the snapshot when f < 0)
-__device__ void set_pair_acc(const Dev &d, int b0, int n, int a, int f, double G, double rc,
+struct SetLds {
+    double *x, *y, *z, *u, *v, *w, *m;
+};
+
+// sum over the L lanes of an aligned lane group (fixed xor-tree order)
+__device__ __forceinline__ double group_sum(double v, int L)
+{
+    for (int o = L >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// partial W-weighted in-set acceleration on member a from members
+// b = l, l+L, ... (unsoftened; Sec. 2.3 steps 5 and 7)
+__device__ void set_pair_acc(const SetLds &S, int n, int a, int l, int L, double G, double rc,
                              double out[3])
 {
-    const int i = d.set_mem[b0 + a];
-    double xi[3];
-    if (f < 0) { xi[0] = d.x0[i]; xi[1] = d.y0[i]; xi[2] = d.z0[i]; }
-    else { for (int c = 0; c < 3; ++c) xi[c] = hw_at(d, f + c, b0 + a); }
+    const double rc2 = rc * rc;
+    const double xi = S.x[a], yi = S.y[a], zi = S.z[a];
     out[0] = out[1] = out[2] = 0.0;
-    for (int b = 0; b < n; ++b) {
+    for (int b = l; b < n; b += L) {
         if (b == a) continue;
-        const int j = d.set_mem[b0 + b];
-        double dd[3];
-        if (f < 0) { dd[0] = d.x0[j] - xi[0]; dd[1] = d.y0[j] - xi[1]; dd[2] = d.z0[j] - xi[2]; }
-        else { for (int c = 0; c < 3; ++c) dd[c] = hw_at(d, f + c, b0 + b) - xi[c]; }
-        const double s2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] + 0.0 * 0.0;
-        if (s2 == 0.0) continue;
+        const double dd0 = S.x[b] - xi, dd1 = S.y[b] - yi, dd2 = S.z[b] - zi;
+        const double s2 = dd0 * dd0 + dd1 * dd1 + dd2 * dd2;
+        // beyond r_crit K = 1, K' = 0: W = 0, the pair adds exactly zero
+        if (s2 == 0.0 || s2 >= rc2) continue;
         const double s = sqrt(s2);
+        const double is = 1.0 / s;
         double K, Kp, Kpp;
         transition(s, rc, K, Kp, Kpp);
         const double W = 1.0 - K + s * Kp;
-        const double fct = G * d.m[j] * W / (s2 * s);
-        for (int c = 0; c < 3; ++c) out[c] += fct * dd[c];
+        const double fct = G * S.m[b] * W * (is * is * is);
+        out[0] += fct * dd0;
+        out[1] += fct * dd1;
+        out[2] += fct * dd2;
     }
 }
 
-// acceleration and jerk of member slot a of H'_Kep (Sec. 2.2) from fields
-// (fx: positions, fu: velocities)
-__device__ void herm_force(const Dev &d, int b0, int n, int a, int fx, int fu, double G, double mu,
-                           double rc, double eps, double acc[3], double jrk[3])
+// partial pair acceleration and jerk of H'_Kep (Sec. 2.2) on member a from
+// members b = l, l+L, ... at the staged state
+__device__ void herm_pairs(const SetLds &S, int n, int a, int l, int L, double G, double rc,
+                           double eps, double acc[3], double jrk[3])
 {
-    double X[3], U[3];
-    for (int c = 0; c < 3; ++c) {
-        X[c] = hw_at(d, fx + c, b0 + a);
-        U[c] = hw_at(d, fu + c, b0 + a);
+    const double rc2 = rc * rc;
+    const double X0 = S.x[a], X1 = S.y[a], X2 = S.z[a];
+    const double U0 = S.u[a], U1 = S.v[a], U2 = S.w[a];
+    for (int c = 0; c < 3; ++c) acc[c] = jrk[c] = 0.0;
+    for (int b = l; b < n; b += L) {
+        if (b == a) continue;
+        const double dd[3] = {S.x[b] - X0, S.y[b] - X1, S.z[b] - X2};
+        const double w[3] = {S.u[b] - U0, S.v[b] - U1, S.w[b] - U2};
+        const double s2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] + eps * eps;
+        // beyond r_crit W = 0 and K'' = 0: the pair adds exactly zero
+        if (s2 == 0.0 || s2 >= rc2) continue;
+        const double s = sqrt(s2);
+        const double is = 1.0 / s;
+        const double is2 = is * is;
+        double K, Kp, Kpp;
+        transition(s, rc, K, Kp, Kpp);
+        const double W = 1.0 - K + s * Kp;
+        const double gm = G * S.m[b] * (is2 * is);
+        const double gmW = gm * W;
+        const double dw = dd[0] * w[0] + dd[1] * w[1] + dd[2] * w[2];
+        const double c3 = 3.0 * dw * is2;
+        for (int c = 0; c < 3; ++c) {
+            acc[c] += gmW * dd[c];
+            jrk[c] += gm * (dw * dd[c] * Kpp + (w[c] - c3 * dd[c]) * W);
+        }
     }
+}
+
+// central (star) part, added after the pair sums
+__device__ __forceinline__ void herm_central(const double X[3], const double U[3], double mu,
+                                             double acc[3], double jrk[3])
+{
     const double r2 = X[0] * X[0] + X[1] * X[1] + X[2] * X[2];
     const double r = sqrt(r2);
     const double r3 = r2 * r;
     const double xv = X[0] * U[0] + X[1] * U[1] + X[2] * U[2];
     for (int c = 0; c < 3; ++c) {
-        acc[c] = -mu * X[c] / r3;
-        jrk[c] = -mu * (U[c] / r3 - 3.0 * xv * X[c] / (r3 * r2));
-    }
-    for (int b = 0; b < n; ++b) {
-        if (b == a) continue;
-        const int j = d.set_mem[b0 + b];
-        double dd[3], w[3];
-        for (int c = 0; c < 3; ++c) {
-            dd[c] = hw_at(d, fx + c, b0 + b) - X[c];
-            w[c] = hw_at(d, fu + c, b0 + b) - U[c];
-        }
-        const double s2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] + eps * eps;
-        if (s2 == 0.0) continue;
-        const double s = sqrt(s2);
-        double K, Kp, Kpp;
-        transition(s, rc, K, Kp, Kpp);
-        const double W = 1.0 - K + s * Kp;
-        const double gm = G * d.m[j] / (s2 * s);
-        const double dw = dd[0] * w[0] + dd[1] * w[1] + dd[2] * w[2];
-        for (int c = 0; c < 3; ++c) {
-            acc[c] += gm * W * dd[c];
-            jrk[c] += gm * (dw * dd[c] * Kpp + (w[c] - 3.0 * dw * dd[c] / s2) * W);
-        }
+        acc[c] += -mu * X[c] / r3;
+        jrk[c] += -mu * (U[c] / r3 - 3.0 * xv * X[c] / (r3 * r2));
     }
 }
 
-// One workgroup per encounter set (grid-stride over sets): correction at q0
-// (Sec. 2.3 step 5), PEC Hermite over tau with one shared step per set
-// (step 6), correction at q1 (step 7), members written back to the state.
+// One workgroup per encounter set (grid-stride over sets).  The set's
+// positions, velocities and masses are staged in LDS; each member's pair
+// sums are split over L lanes (L = largest power of two with L n <= 256,
+// at most 64) and combined by an xor tree.  Correction at q0 (Sec. 2.3
+// step 5), PEC Hermite over tau with one shared step per set (step 6),
+// correction at q1 (step 7); members written back to the state.
 __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
 {
     const Dev &d = a.d;
+    __shared__ double s_x[kHermLds], s_y[kHermLds], s_z[kHermLds];
+    __shared__ double s_u[kHermLds], s_v[kHermLds], s_w[kHermLds], s_m[kHermLds];
     __shared__ double lds[kHermThreads];
     __shared__ int s_fail;
+    const SetLds S{s_x, s_y, s_z, s_u, s_v, s_w, s_m};
     const int t = threadIdx.x;
     const int nsets = (int)d.ctr[C_NSETS];
     for (int sidx = blockIdx.x; sidx < nsets; sidx += gridDim.x) {
         const int b0 = d.set_start[sidx];
         const int n = d.set_start[sidx + 1] - b0;
         const double rc = d.set_rc[sidx];
-        if (n > kHermMax) {
+        if (n > kHermLds) {
             if (t == 0) latch(d.ctr, S_SET_BIG);
             continue;
         }
+        int L = 1;
+        while (L < 64 && 2 * L * n <= kHermThreads) L <<= 1;
+        const int G = kHermThreads / L;
+        const int g = t / L, l = t % L;
         const double mu = a.G * d.sys_m0[d.body_sys[d.set_mem[b0]]];
         const double half = a.tau / 2.0;
-        // step 5: v0 -= tau/2 * sum W-weighted in-set forces at q0
+        // stage q0, v0 and masses
         for (int k = t; k < n; k += kHermThreads) {
-            double acc[3];
-            set_pair_acc(d, b0, n, k, -1, a.G, rc, acc);
             const int i = d.set_mem[b0 + k];
-            hw_at(d, HX + 0, b0 + k) = d.x0[i];
-            hw_at(d, HX + 1, b0 + k) = d.y0[i];
-            hw_at(d, HX + 2, b0 + k) = d.z0[i];
-            hw_at(d, HU + 0, b0 + k) = d.vx0[i] - half * acc[0];
-            hw_at(d, HU + 1, b0 + k) = d.vy0[i] - half * acc[1];
-            hw_at(d, HU + 2, b0 + k) = d.vz0[i] - half * acc[2];
+            s_x[k] = d.x0[i];
+            s_y[k] = d.y0[i];
+            s_z[k] = d.z0[i];
+            s_m[k] = d.m[i];
+        }
+        __syncthreads();
+        // step 5: v0 -= tau/2 * sum W-weighted in-set forces at q0
+        for (int k = g; k < n; k += G) {
+            double acc[3];
+            set_pair_acc(S, n, k, l, L, a.G, rc, acc);
+            for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+            if (l == 0) {
+                const int i = d.set_mem[b0 + k];
+                hw_at(d, HX + 0, b0 + k) = s_x[k];
+                hw_at(d, HX + 1, b0 + k) = s_y[k];
+                hw_at(d, HX + 2, b0 + k) = s_z[k];
+                const double u0 = d.vx0[i] - half * acc[0];
+                const double u1 = d.vy0[i] - half * acc[1];
+                const double u2 = d.vz0[i] - half * acc[2];
+                hw_at(d, HU + 0, b0 + k) = u0;
+                hw_at(d, HU + 1, b0 + k) = u1;
+                hw_at(d, HU + 2, b0 + k) = u2;
+                s_u[k] = u0;
+                s_v[k] = u1;
+                s_w[k] = u2;
+            }
         }
         __syncthreads();
         // initial force and first step
         double hloc = INFINITY;
-        for (int k = t; k < n; k += kHermThreads) {
+        for (int k = g; k < n; k += G) {
             double acc[3], jr[3];
-            herm_force(d, b0, n, k, HX, HU, a.G, mu, rc, a.epsH, acc, jr);
+            herm_pairs(S, n, k, l, L, a.G, rc, a.epsH, acc, jr);
             for (int c = 0; c < 3; ++c) {
-                hw_at(d, HA + c, b0 + k) = acc[c];
-                hw_at(d, HJ + c, b0 + k) = jr[c];
+                acc[c] = group_sum(acc[c], L);
+                jr[c] = group_sum(jr[c], L);
             }
-            const double hb = a.eta_s * dnorm3(acc[0], acc[1], acc[2]) / dnorm3(jr[0], jr[1], jr[2]);
-            if (hb > 0.0 && hb < hloc) hloc = hb;
+            if (l == 0) {
+                const double X[3] = {s_x[k], s_y[k], s_z[k]}, U[3] = {s_u[k], s_v[k], s_w[k]};
+                herm_central(X, U, mu, acc, jr);
+                for (int c = 0; c < 3; ++c) {
+                    hw_at(d, HA + c, b0 + k) = acc[c];
+                    hw_at(d, HJ + c, b0 + k) = jr[c];
+                }
+                const double hb =
+                    a.eta_s * dnorm3(acc[0], acc[1], acc[2]) / dnorm3(jr[0], jr[1], jr[2]);
+                if (hb > 0.0 && hb < hloc) hloc = hb;
+            }
         }
         double h = block_min<kHermThreads>(hloc, lds);
         const double sgn = a.tau >= 0.0 ? 1.0 : -1.0;
@@ -1092,67 +1287,85 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
                 last = true;
             }
             const double hs = sgn * h;
+            // predict into LDS (read by every member's force) and scratch
             for (int k = t; k < n; k += kHermThreads) {
+                double xp[3], up[3];
                 for (int c = 0; c < 3; ++c) {
                     const double x = hw_at(d, HX + c, b0 + k), u = hw_at(d, HU + c, b0 + k);
                     const double ac = hw_at(d, HA + c, b0 + k), jc = hw_at(d, HJ + c, b0 + k);
-                    hw_at(d, HXP + c, b0 + k) =
-                        x + hs * u + hs * hs * ac / 2.0 + hs * hs * hs * jc / 6.0;
-                    hw_at(d, HUP + c, b0 + k) = u + hs * ac + hs * hs * jc / 2.0;
+                    xp[c] = x + hs * u + hs * hs * ac / 2.0 + hs * hs * hs * jc / 6.0;
+                    up[c] = u + hs * ac + hs * hs * jc / 2.0;
+                    hw_at(d, HXP + c, b0 + k) = xp[c];
+                    hw_at(d, HUP + c, b0 + k) = up[c];
                 }
+                s_x[k] = xp[0]; s_y[k] = xp[1]; s_z[k] = xp[2];
+                s_u[k] = up[0]; s_v[k] = up[1]; s_w[k] = up[2];
             }
             __syncthreads();
             double hn = INFINITY;
-            for (int k = t; k < n; k += kHermThreads) {
+            for (int k = g; k < n; k += G) {
                 double a1[3], j1[3];
-                herm_force(d, b0, n, k, HXP, HUP, a.G, mu, rc, a.epsH, a1, j1);
-                double A2e[3], A3v[3];
+                herm_pairs(S, n, k, l, L, a.G, rc, a.epsH, a1, j1);
                 for (int c = 0; c < 3; ++c) {
-                    const double a0c = hw_at(d, HA + c, b0 + k), j0c = hw_at(d, HJ + c, b0 + k);
-                    const double A2 = (-6.0 * (a0c - a1[c]) - hs * (4.0 * j0c + 2.0 * j1[c])) / (hs * hs);
-                    const double A3 = (12.0 * (a0c - a1[c]) + 6.0 * hs * (j0c + j1[c])) / (hs * hs * hs);
-                    hw_at(d, HA1 + c, b0 + k) = a1[c];
-                    hw_at(d, HJ1 + c, b0 + k) = j1[c];
-                    const double xp = hw_at(d, HXP + c, b0 + k), up = hw_at(d, HUP + c, b0 + k);
-                    // the predicted fields are read by every member's force:
-                    // the corrected state goes to HXN/HUN until the barrier
-                    hw_at(d, HXN + c, b0 + k) =
-                        xp + A2 * hs * hs * hs * hs / 24.0 + A3 * hs * hs * hs * hs * hs / 120.0;
-                    hw_at(d, HUN + c, b0 + k) = up + A2 * hs * hs * hs / 6.0 + A3 * hs * hs * hs * hs / 24.0;
-                    A2e[c] = A2 + hs * A3;
-                    A3v[c] = A3;
+                    a1[c] = group_sum(a1[c], L);
+                    j1[c] = group_sum(j1[c], L);
                 }
-                const double na = dnorm3(a1[0], a1[1], a1[2]), nj = dnorm3(j1[0], j1[1], j1[2]);
-                const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]), n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
-                const double hb = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
-                if (hb > 0.0 && hb < hn) hn = hb;
-            }
-            hn = block_min<kHermThreads>(hn, lds);   // includes a barrier: all forces done
-            for (int k = t; k < n; k += kHermThreads) {
-                for (int c = 0; c < 3; ++c) {
-                    hw_at(d, HX + c, b0 + k) = hw_at(d, HXN + c, b0 + k);
-                    hw_at(d, HU + c, b0 + k) = hw_at(d, HUN + c, b0 + k);
-                    hw_at(d, HA + c, b0 + k) = hw_at(d, HA1 + c, b0 + k);
-                    hw_at(d, HJ + c, b0 + k) = hw_at(d, HJ1 + c, b0 + k);
+                if (l == 0) {
+                    const double X[3] = {s_x[k], s_y[k], s_z[k]}, U[3] = {s_u[k], s_v[k], s_w[k]};
+                    herm_central(X, U, mu, a1, j1);
+                    double A2e[3], A3v[3];
+                    for (int c = 0; c < 3; ++c) {
+                        const double a0c = hw_at(d, HA + c, b0 + k), j0c = hw_at(d, HJ + c, b0 + k);
+                        const double A2 =
+                            (-6.0 * (a0c - a1[c]) - hs * (4.0 * j0c + 2.0 * j1[c])) / (hs * hs);
+                        const double A3 =
+                            (12.0 * (a0c - a1[c]) + 6.0 * hs * (j0c + j1[c])) / (hs * hs * hs);
+                        const double xp = hw_at(d, HXP + c, b0 + k), up = hw_at(d, HUP + c, b0 + k);
+                        // only this lane touches member k's scratch during the
+                        // force loop (the others read the LDS copy)
+                        hw_at(d, HX + c, b0 + k) =
+                            xp + A2 * hs * hs * hs * hs / 24.0 + A3 * hs * hs * hs * hs * hs / 120.0;
+                        hw_at(d, HU + c, b0 + k) =
+                            up + A2 * hs * hs * hs / 6.0 + A3 * hs * hs * hs * hs / 24.0;
+                        hw_at(d, HA + c, b0 + k) = a1[c];
+                        hw_at(d, HJ + c, b0 + k) = j1[c];
+                        A2e[c] = A2 + hs * A3;
+                        A3v[c] = A3;
+                    }
+                    const double na = dnorm3(a1[0], a1[1], a1[2]), nj = dnorm3(j1[0], j1[1], j1[2]);
+                    const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]);
+                    const double n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
+                    const double hb = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
+                    if (hb > 0.0 && hb < hn) hn = hb;
                 }
             }
-            __syncthreads();
+            hn = block_min<kHermThreads>(hn, lds);   // barriers: forces and scratch done
             tt += h;
             ++nsub;
             h = hn;
         }
         __syncthreads();
-        // step 7: v1 -= tau/2 * sum W-weighted in-set forces at q1; write back
+        // step 7: stage the final positions, v1 -= tau/2 * W-weighted
+        // in-set forces at q1, write back
         for (int k = t; k < n; k += kHermThreads) {
+            s_x[k] = hw_at(d, HX + 0, b0 + k);
+            s_y[k] = hw_at(d, HX + 1, b0 + k);
+            s_z[k] = hw_at(d, HX + 2, b0 + k);
+        }
+        __syncthreads();
+        for (int k = g; k < n; k += G) {
             double acc[3];
-            set_pair_acc(d, b0, n, k, HX, a.G, rc, acc);
-            const int i = d.set_mem[b0 + k];
-            d.x[i] = hw_at(d, HX + 0, b0 + k);
-            d.y[i] = hw_at(d, HX + 1, b0 + k);
-            d.z[i] = hw_at(d, HX + 2, b0 + k);
-            d.vx[i] = hw_at(d, HU + 0, b0 + k) - half * acc[0];
-            d.vy[i] = hw_at(d, HU + 1, b0 + k) - half * acc[1];
-            d.vz[i] = hw_at(d, HU + 2, b0 + k) - half * acc[2];
+            set_pair_acc(S, n, k, l, L, a.G, rc, acc);
+            for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+            if (l == 0) {
+                const int i = d.set_mem[b0 + k];
+                d.x[i] = s_x[k];
+                d.y[i] = s_y[k];
+                d.z[i] = s_z[k];
+                d.vx[i] = hw_at(d, HU + 0, b0 + k) - half * acc[0];
+                d.vy[i] = hw_at(d, HU + 1, b0 + k) - half * acc[1];
+                d.vz[i] = hw_at(d, HU + 2, b0 + k) - half * acc[2];
+            }
         }
         if (t == 0) {
             atomicAdd(&d.ctr[C_SUB], (unsigned long long)nsub);
@@ -1231,7 +1444,5 @@ __global__ __launch_bounds__(256) void k_energy_final(EnergyArgs a)
         d.E[s] = kin + (px * px + py * py + pz * pz) / (2.0 * m0) - pot0 - a.G * pp;
 }
 
-// steps counter (one thread)
-__global__ void k_count_step(Dev d) { d.ctr[C_STEPS] += 1; }
 
 }  // namespace qsym

@@ -99,8 +99,9 @@ SIGNATURES = {
     "qsym_fine_test": (C.c_int, [C.POINTER(Params), C.c_double, C.c_double, C.c_int64] +
                        [C.c_void_p] * 7 + [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p]),
-    "qsym_set_kick_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_int32]),
-    "qsym_get_kick_shape": (C.c_int, [C.c_void_p, _ip, _ip, _lp, _ip]),
+    "qsym_set_kick_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int64,
+                                      C.c_int32]),
+    "qsym_get_kick_shape": (C.c_int, [C.c_void_p, C.c_int32, _ip, _ip, _lp, _ip]),
     "qsym_autotune": (C.c_int, [C.c_void_p, C.c_double, _dp]),
     "qsym_profile": (C.c_int, [C.c_void_p, C.c_int32]),
 }
@@ -146,7 +147,11 @@ class Context:
     paper_1007_3458_amd.inputs.System); bodies are concatenated in order.
     """
 
-    def __init__(self, systems, params: Params | None = None, device="cuda:0", **kw):
+    def __init__(self, systems, params: Params | None = None, device="cuda:0", shapes="table",
+                 **kw):
+        """shapes="table" starts from the tuned kick shapes recorded for this
+        workload signature (paper_1007_3458_amd/tuned_shapes.json) when there
+        is an entry; None keeps the library defaults."""
         torch = _torch()
         if not isinstance(systems, (list, tuple)):
             systems = [systems]
@@ -178,6 +183,15 @@ class Context:
         q = np.concatenate([np.asarray(s.q).reshape(-1, 3) for s in systems])
         v = np.concatenate([np.asarray(s.v).reshape(-1, 3) for s in systems])
         self.set_state(m, hh, q, v)
+        self.tuned = None
+        if shapes == "table":
+            from . import tune
+            e = tune.lookup(sizes, self.params.precision, self.params.hill_mode)
+            if e:
+                for w, key in ((0, "plain"), (1, "crude")):
+                    sh = e[key]
+                    self.set_kick_shape(sh["ipl"], sh["block"], sh["jchunk"], sh["remap"], which=w)
+                self.tuned = e
 
     # ---------------------------------------------------------- helpers
     def _check(self, rc, ctx):
@@ -260,19 +274,22 @@ class Context:
         self._c(lib().qsym_apply_kepler(self.ctx, float(dt)))
 
     # -------------------------------------------------------- tuning
-    def set_kick_shape(self, ipl, block, jchunk, remap=1):
-        self._c(lib().qsym_set_kick_shape(self.ctx, ipl, block, jchunk, remap))
+    def set_kick_shape(self, ipl, block, jchunk, remap=1, which=-1):
+        """which: 0 plain kick, 1 kick with the crude sweep, -1 both."""
+        self._c(lib().qsym_set_kick_shape(self.ctx, which, ipl, block, jchunk, remap))
 
-    def kick_shape(self):
+    def kick_shape(self, which=1):
         a, b, r = C.c_int32(), C.c_int32(), C.c_int32()
         j = C.c_int64()
-        self._c(lib().qsym_get_kick_shape(self.ctx, C.byref(a), C.byref(b), C.byref(j), C.byref(r)))
+        self._c(lib().qsym_get_kick_shape(self.ctx, which, C.byref(a), C.byref(b), C.byref(j),
+                                          C.byref(r)))
         return dict(ipl=a.value, block=b.value, jchunk=j.value, remap=r.value)
 
     def autotune(self, tau):
-        us = C.c_double()
-        self._c(lib().qsym_autotune(self.ctx, float(tau), C.byref(us)))
-        return us.value
+        """Tune both kick shapes; returns (plain_us, crude_us)."""
+        us = (C.c_double * 2)()
+        self._c(lib().qsym_autotune(self.ctx, float(tau), us))
+        return us[0], us[1]
 
     def profile(self, enable=True):
         self._c(lib().qsym_profile(self.ctx, 1 if enable else 0))

@@ -85,13 +85,10 @@ def test_crude_candidates_match(Q, orc, name):
     got = {tuple(x) for x in ctx.candidates()}
     A, ve = orc.prepass(1.0, s.q, s.v)
     ref = {tuple(x) for x in orc.crude(p, tau, s.q, s.h, A, ve)}
-    # any disagreement must sit on the threshold (different rounding order)
-    for (i, j) in got ^ ref:
-        r2 = np.sum((s.q[j] - s.q[i]) ** 2)
-        R = 3.0 * (s.h[i] + s.h[j]) * (A[i] + A[j]) / 2
-        lim = 1.1 * (R + tau * (ve[i] + ve[j]))
-        assert abs(r2 - lim * lim) <= 1e-12 * lim * lim, (i, j)
-    assert len(got ^ ref) == 0 or len(ref) > 0
+    # identical inputs: the pairs under the tile bound take the exact test of
+    # the definition with the oracle's operands and order -> identical sets
+    assert got == ref
+    assert len(ref) > 0
     ctx.close()
 
 
@@ -285,7 +282,7 @@ def test_autotune_keeps_results(Q, orc):
     s.v[:] = 0.0
     ctx = Q.Context(s)
     us = ctx.autotune(0.05)
-    assert us > 0
+    assert min(us) > 0
     ctx.apply_kick(1.0)
     _, v1 = ctx.get_state()
     assert per_body_rel(v1 - s.v, orc.accel(s.G, s.m, s.q)) < 1e-13
