@@ -8,10 +8,14 @@ whole hybrid step: drift, kick with the fused crude sweep, Kepler, fine
 sweep, sets, corrections + Hermite, second kick, drift.
 
 Prints one JSON line.  `value` is pair-interactions per second (two all-pairs
-kicks per step, N(N-1) ordered pairs each) over the timed steps, inputs
-resident in HBM.  The timed steps run with HIP events around every kernel
-(no graph) so the kick kernel's average duration comes from the same region;
-graph-replay throughput is reported beside it.
+kicks per step, N(N-1) ordered pairs each per system) over the timed steps,
+inputs resident in HBM.  The timed steps run with HIP events around every
+kernel (no graph) so the kick kernel's average duration comes from the same
+region; graph-replay throughput is reported beside it.
+
+Other workloads: --workload disk128k (131076 bodies; with --precision 1 the
+FP32 pair-term form, compared with the FP64 path on the same initial
+conditions), --workload batch (512 independent systems of 64..4096 bodies).
 """
 from __future__ import annotations
 
@@ -22,6 +26,8 @@ import os
 import platform
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -37,11 +43,11 @@ def workload(name):
     if name == "disk16k":
         return [inputs.disk16k()], "4 planets + 16384 planetesimals (m=1e-8, a~U[15,40], e~Rayleigh(0.05), i~Rayleigh(0.025)), tau=0.05, aE=3 mutual Hill radii, encounters on"
     if name == "disk128k":
-        return [inputs.disk128k()], "4 planets + 131072 planetesimals (m=2e-9), tau=0.05, aE=3 mutual Hill radii, encounters on"
+        return [inputs.disk128k()], "4 planets + 131072 planetesimals (m=2e-9, a~U[15,40], e~Rayleigh(0.05), i~Rayleigh(0.025)), tau=0.05, aE=3 mutual Hill radii, encounters on"
     if name == "small":
         return [inputs.small()], "4 planets + 100 planetesimals, tau=0.05"
     if name == "batch":
-        return inputs.batch(), "512 systems, N~logU[64,4096]: 1 Jupiter-mass planet + planetesimals (m=1e-8, a~U[3,10]), tau=0.05"
+        return inputs.batch(), "512 systems, N~logU[64,4096]: 1 Jupiter-mass planet at 5.2 + planetesimals (m=1e-8, a~U[3,10]), tau=0.05, encounters on"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -71,7 +77,7 @@ def cpu_baseline(systems, tau, seconds):
     import oracle
     oracle.build()
     p = oracle.make_params()
-    s = systems[0]
+    s = max(systems, key=lambda x: x.n)
     q, v = s.q, s.v
     t0 = time.perf_counter()
     q, v, _ = oracle.step(p, tau, s.m, s.h, q, v)
@@ -93,15 +99,74 @@ def cpu_baseline(systems, tau, seconds):
         pass
     return {"value": 2.0 * n * (n - 1) * k / dt, "unit": "pair-interactions/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{k} whole hybrid steps of the first system ({n} bodies) after 1 untimed step",
+            "sample": f"{k} whole hybrid steps of the largest system ({n} bodies) after 1 untimed step",
             "steps_per_s": k / dt, "cpu": model}
+
+
+def make_context(systems, precision, tau, force_tune):
+    from paper_1007_3458_amd import qsym
+    ctx = qsym.Context(systems, precision=precision)
+    tune_us = None
+    if force_tune or ctx.tuned is None:
+        tune_us = ctx.autotune(tau)
+    src = "autotuned now" if tune_us is not None else "tuned table"
+    shape = {"plain": ctx.kick_shape(0), "crude": ctx.kick_shape(1), "source": src,
+             "autotune_us": tune_us}
+    return ctx, shape
+
+
+def timed_run(ctx, tau, steps, warmup, graph_pass):
+    """Warm-up, then `steps` profiled steps (HIP events per kernel); returns
+    a dict of timings, energies and counters."""
+    import torch
+    from paper_1007_3458_amd import qsym
+    ctx.step(tau, warmup)
+    ctx.sync()
+    E0 = ctx.energy()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(tau, steps)
+    ctx.sync()
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    st = ctx.stats()
+    ctx.profile(False)
+    kern = {}
+    for k, name in enumerate(qsym.PHASES):
+        if st["phase_calls"][k]:
+            kern[name] = st["phase_us"][k] / st["phase_calls"][k]
+    E1 = ctx.energy()
+    graph_sps = None
+    if graph_pass:
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        ctx.step(tau, steps)
+        ctx.sync()
+        torch.cuda.synchronize()
+        graph_sps = steps / (time.perf_counter() - g0)
+    st2 = ctx.stats()
+    return {"T": T, "kern": kern, "E0": E0, "E1": E1, "graph_sps": graph_sps, "st": st, "st2": st2}
+
+
+def kick_accels(ctx, systems):
+    """Accelerations of the initial state through the library's kick
+    (velocities zeroed so that v = a exactly), state restored afterwards."""
+    m = np.concatenate([s.m for s in systems]); h = np.concatenate([s.h for s in systems])
+    q = np.concatenate([s.q for s in systems])
+    ctx.set_state(m, h, q, np.zeros_like(q))
+    ctx.apply_kick(1.0)
+    _, a = ctx.get_state()
+    v = np.concatenate([s.v for s in systems])
+    ctx.set_state(m, h, q, v)
+    return a
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="disk16k", choices=["disk16k", "disk128k", "small", "batch"])
     ap.add_argument("--precision", type=int, default=0, choices=[0, 1])
     ap.add_argument("--tau", type=float, default=0.05)
@@ -110,63 +175,56 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="tune the kick shapes now instead of using the tuned table")
     ap.add_argument("--no-graph-pass", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="precision 1: skip the FP64 run on the same initial conditions")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build runs one process on one MI355X "
               "(the multi-GPU design is described, not built)", file=sys.stderr)
         sys.exit(2)
+    defaults = {"disk16k": (200, 20), "disk128k": (100, 5), "small": (1000, 50), "batch": (100, 10)}
+    steps = args.steps if args.steps is not None else defaults[args.workload][0]
+    warmup = args.warmup if args.warmup is not None else defaults[args.workload][1]
 
     import torch
-
-    from paper_1007_3458_amd import qsym
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     systems, desc = workload(args.workload)
     ntot = sum(s.n for s in systems)
-    pairs_per_step = sum(2.0 * s.n * (s.n - 1) for s in systems)
-    ctx = qsym.Context(systems, precision=args.precision)
-    tune_us = None
-    if args.autotune or ctx.tuned is None:
-        tune_us = ctx.autotune(args.tau)
-    shape_source = "autotuned now" if tune_us is not None else "tuned table"
-    shape = {"plain": ctx.kick_shape(0), "crude": ctx.kick_shape(1)}
-    ctx.step(args.tau, args.warmup)
-    ctx.sync()
-    E0 = ctx.energy()
-
-    # timed region: eager launches with HIP events around each kernel
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(args.tau, args.steps)
-    ctx.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = ctx.stats()
-    ctx.profile(False)
-    T = t1 - t0
-    value = pairs_per_step * args.steps / T
-    kern = {}
-    for k, name in enumerate(qsym.PHASES):
-        if st["phase_calls"][k]:
-            kern[name] = st["phase_us"][k] / st["phase_calls"][k]
-
-    graph_sps = None
-    if not args.no_graph_pass:
-        torch.cuda.synchronize()
-        g0 = time.perf_counter()
-        ctx.step(args.tau, args.steps)
-        ctx.sync()
-        torch.cuda.synchronize()
-        graph_sps = args.steps / (time.perf_counter() - g0)
-    E1 = ctx.energy()
-    st2 = ctx.stats()
-    energy_err = float(max(abs(E1[k] / E0[k] - 1.0) for k in range(len(E0))))
+    npairs = sum(float(s.n) * (s.n - 1) for s in systems)
+    ctx, shape = make_context(systems, args.precision, args.tau, args.autotune)
+    extra = {}
+    if args.precision == 1 and not args.no_compare:
+        # accuracy of the FP32 pair terms against the FP64 kick (which is
+        # itself checked against the oracle to 1e-13 by the test suite)
+        ctx64, shape64 = make_context(systems, 0, args.tau, args.autotune)
+        a32 = kick_accels(ctx, systems)
+        a64 = kick_accels(ctx64, systems)
+        rel = np.linalg.norm(a32 - a64, axis=1) / np.maximum(np.linalg.norm(a64, axis=1), 1e-300)
+        r64 = timed_run(ctx64, args.tau, steps, warmup, False)
+        e64 = float(max(abs(r64["E1"][k] / r64["E0"][k] - 1.0) for k in range(len(systems))))
+        extra["precision_report"] = {
+            "accel_rel_err_max": float(rel.max()), "accel_rel_err_rms": float(np.sqrt(np.mean(rel ** 2))),
+            "reference": "FP64 kick of the same library on the same state",
+            "fp64_value": 2.0 * npairs * steps / r64["T"],
+            "fp64_kick_crude_us": r64["kern"].get("kick+crude"), "fp64_kick_us": r64["kern"].get("kick2"),
+            "fp64_energy_error": e64, "fp64_kick_shape": shape64}
+        ctx64.close()
+    r = timed_run(ctx, args.tau, steps, warmup, not args.no_graph_pass)
+    T = r["T"]
+    value = 2.0 * npairs * steps / T
+    kern = r["kern"]
+    energy_err = float(max(abs(r["E1"][k] / r["E0"][k] - 1.0) for k in range(len(systems))))
+    if "precision_report" in extra:
+        pr = extra["precision_report"]
+        pr["energy_error"] = energy_err
+        pr["energy_error_ratio_vs_fp64"] = energy_err / pr["fp64_energy_error"] if pr["fp64_energy_error"] else None
+        pr["speedup_vs_fp64"] = value / pr["fp64_value"]
 
     # roofline of the dominant kernel: the kick with the fused crude sweep
     t_kick = kern.get("kick+crude")
-    flops = sum(s.n * (s.n - 1) * FLOP_PAIR + s.n * (s.n - 1) / 2 * FLOP_CRUDE for s in systems)
+    flops = npairs * FLOP_PAIR + npairs / 2 * FLOP_CRUDE
     peak = FP64_PEAK_TFLOPS if args.precision == 0 else FP32_PEAK_TFLOPS
     achieved = flops / (t_kick * 1e-6) / 1e12 if t_kick else None
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -174,32 +232,33 @@ def main():
             "traffic": measured_traffic(args.workload, args.precision),
             "kernel": "k_kick (E_Int + fused crude sweep)",
             "flop_per_launch": flops, "avg_launch_us": t_kick,
-            "pairs_per_s_kernel": (sum(s.n * (s.n - 1) for s in systems) / (t_kick * 1e-6)) if t_kick else None}
+            "pairs_per_s_kernel": (npairs / (t_kick * 1e-6)) if t_kick else None}
     out = {
         "metric": "pair-interactions/s and steps/s vs plain FP64 path at matched energy error",
         "value": value,
         "unit": "pair-interactions/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1000.0 * T / args.steps,
-        "steps_per_s": args.steps / T,
-        "steps_per_s_graph": graph_sps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1000.0 * T / steps,
+        "steps_per_s": steps / T,
+        "steps_per_s_graph": r["graph_sps"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == 0 else "f32 pair terms, f64 elsewhere",
+        "dtype": "f64" if args.precision == 0 else "f32 m/r^3 on f64 separations, f64 elsewhere",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n_bodies": ntot, "n_systems": len(systems),
-                   "tau": args.tau, "precision": args.precision, "kick_shape": shape,
-                   "kick_shape_source": shape_source, "autotune_kick_us": tune_us},
+                   "tau": args.tau, "precision": args.precision, "kick_shape": shape},
         "energy_error": energy_err,
-        "encounters_last_step": st["n_encounters"],
-        "encounters_total": st2["total_encounters"],
-        "hermite_substeps_total": st2["total_substeps"],
+        "encounters_last_step": r["st"]["n_encounters"],
+        "encounters_total": r["st2"]["total_encounters"],
+        "hermite_substeps_total": r["st2"]["total_substeps"],
+        "kepler_iters_total": r["st2"]["kepler_iters"],
         "kernel_avg_us": kern,
         "roofline": roof,
     }
+    out.update(extra)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(systems, args.tau, args.cpu_seconds)
     out["host"] = platform.node()

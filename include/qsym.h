@@ -66,8 +66,9 @@ typedef struct qsym_params {
     int32_t hill_mode;   /* 0: a_E x mutual Hill radius; 1: a_E x sum of radii   */
     int32_t kepler_mode; /* 0: Laguerre from x = r0 (Appendix A); 1: Newton from
                             sqrt(mu) dt / r0; 2: Newton from the learned guess   */
-    int32_t precision;   /* 0: FP64 pair terms; 1: FP32 pair terms on FP64
-                            separations with FP64 tile accumulation            */
+    int32_t precision;   /* 0: FP64 pair terms; 1: m r^-3 in FP32 on FP64
+                            separations, accumulated in FP64 (Sec. 2 remarks
+                            on single-precision forces)                        */
     int32_t max_substeps;/* Hermite substep cap per set per step (>= 1)           */
     int64_t pair_capacity; /* crude-candidate capacity; 0 selects 8*ntot + 1024  */
 } qsym_params;
@@ -138,6 +139,8 @@ int qsym_encounters(qsym_ctx *ctx, int32_t *pairs, int64_t cap, int64_t *n_pairs
 int qsym_candidates(qsym_ctx *ctx, int32_t *pairs, int64_t cap, int64_t *n);
 
 int qsym_stats(qsym_ctx *ctx, qsym_stats_t *out);
+/* Message of the last failure of ctx; with ctx = NULL, of the last failure
+ * on this thread that had no context (qsym_create, qsym_workspace_bytes). */
 const char *qsym_last_error(const qsym_ctx *ctx);
 
 /* Operator-level entry points running the step's own kernels on the

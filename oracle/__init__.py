@@ -77,6 +77,7 @@ def lib():
             "orc_prepass": (None, [i64, d, _dp, _dp, _dp, _dp]),
             "orc_accel": (None, [i64, d, _dp, _dp, _dp]),
             "orc_kick": (None, [i64, d, _dp, _dp, _dp, d]),
+            "orc_accel_rows": (None, [i64, d, _dp, _dp, i64, C.POINTER(C.c_int64), _dp]),
             "orc_crude": (i64, [i64, pp, d, _dp, _dp, _dp, _dp, _ip, i64]),
             "orc_fine_pair": (C.c_int, [pp, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, i64, i64,
                                         _dp, _dp, _dp]),
@@ -157,6 +158,16 @@ def accel(G, m, q):
     q = _f64(q, (-1, 3)); m = _f64(m)
     a = np.empty_like(q)
     lib().orc_accel(q.shape[0], G, _d(m), _d(q), _d(a))
+    return a
+
+
+def accel_rows(G, m, q, rows):
+    """Accelerations of the bodies listed in rows (over all j)."""
+    q = _f64(q, (-1, 3)); m = _f64(m)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    a = np.empty((rows.shape[0], 3))
+    lib().orc_accel_rows(q.shape[0], G, _d(m), _d(q), rows.shape[0],
+                         rows.ctypes.data_as(C.POINTER(C.c_int64)), _d(a))
     return a
 
 

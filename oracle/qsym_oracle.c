@@ -297,6 +297,34 @@ void orc_accel(int64_t n, double G, const double *m, const double *q, double *a)
     }
 }
 
+/* The same acceleration for a subset of bodies (rows), e.g. a sample of a
+ * large system. */
+void orc_accel_rows(int64_t n, double G, const double *m, const double *q, int64_t nrows,
+                    const int64_t *rows, double *a)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows[r];
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = q[3 * j] - q[3 * i];
+            double dy = q[3 * j + 1] - q[3 * i + 1];
+            double dz = q[3 * j + 2] - q[3 * i + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0) continue;
+            double rr = sqrt(r2);
+            double s = G * m[j] / (r2 * rr);
+            ax += s * dx;
+            ay += s * dy;
+            az += s * dz;
+        }
+        a[3 * r] = ax;
+        a[3 * r + 1] = ay;
+        a[3 * r + 2] = az;
+    }
+}
+
 /* E_Int(dt): v_i += dt * a_i */
 void orc_kick(int64_t n, double G, const double *m, const double *q, double *v, double dt)
 {

@@ -36,7 +36,7 @@ struct Layout {
     size_t off_state = 0, off_snap = 0, off_aux = 0, off_acc = 0, off_pm = 0, off_bsys = 0;
     size_t off_sysoff = 0, off_sysm0 = 0, off_sysS = 0, off_syspoff = 0, off_sysc0 = 0;
     size_t off_bchunk = 0, off_kchunk = 0, off_items = 0, off_eitems = 0, off_syse0 = 0, off_cand = 0;
-    size_t off_enc = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0;
+    size_t off_enc = 0, off_syseoff = 0, off_sysecnt = 0, off_setcount = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0;
     size_t off_hw = 0, off_ctr = 0, off_epart = 0, off_E = 0, off_mlp = 0;
     size_t total = 0;
     long long np = 0;          // padded body count
@@ -46,11 +46,13 @@ struct Layout {
     long long max_items = 0;   // kick items of the finest allowed shape
     long long n_eitems = 0;
     long long cap = 0;         // candidate capacity
+    long long ecap = 0;        // encounter-pair slots (sum of per-system capacities)
+    long long memcap = 0;      // set-member slots
     long long jchunk_min = 128;
 };
 
 struct Tables {
-    std::vector<int> sys_off, sys_S, sys_c0, sys_e0;
+    std::vector<int> sys_off, sys_S, sys_c0, sys_e0, sys_eoff;
     std::vector<long long> sys_poff;
     std::vector<int4> bchunk, kchunk;
     std::vector<KickItem> eitems;
@@ -58,6 +60,13 @@ struct Tables {
 };
 
 int nsys_bodies(const std::vector<long long> &off, int s) { return (int)(off[s + 1] - off[s]); }
+
+// encounter pairs one system may append per step (its segment)
+long long sys_enc_cap(long long n)
+{
+    if (n <= 0) return 0;
+    return std::min<long long>(std::max<long long>(2 * n, 64), kCapE);
+}
 
 long long jchunk_min_for(const std::vector<long long> &off)
 {
@@ -94,6 +103,10 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     L.max_items = std::max<long long>(L.max_items, 1) + 8;
     L.n_eitems = std::max<long long>(L.n_eitems, 1);
     L.cap = p.pair_capacity > 0 ? p.pair_capacity : 8 * ntot + 1024;
+    L.ecap = 0;
+    for (int s = 0; s < nsys; ++s) L.ecap += sys_enc_cap(off[s + 1] - off[s]);
+    L.ecap = std::max<long long>(L.ecap, 1);
+    L.memcap = 2 * L.ecap;
     size_t o = 0;
     auto take = [&](size_t &field, size_t bytes) {
         o = align_up(o, 256);
@@ -118,11 +131,14 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_eitems, (size_t)L.n_eitems * sizeof(KickItem));
     take(L.off_syse0, (size_t)(nsys + 1) * sizeof(int));
     take(L.off_cand, (size_t)L.cap * sizeof(int2));
-    take(L.off_enc, (size_t)kCapE * sizeof(int2));
-    take(L.off_setstart, (size_t)(kCapU + 1) * sizeof(int));
-    take(L.off_setmem, (size_t)kCapU * sizeof(int));
-    take(L.off_setrc, (size_t)kCapU * D);
-    take(L.off_hw, (size_t)HFIELDS * kCapU * D);
+    take(L.off_enc, (size_t)L.ecap * sizeof(int2));
+    take(L.off_syseoff, (size_t)(nsys + 1) * sizeof(int));
+    take(L.off_sysecnt, (size_t)std::max(nsys, 1) * sizeof(int));
+    take(L.off_setstart, (size_t)L.ecap * sizeof(int));
+    take(L.off_setcount, (size_t)L.ecap * sizeof(int));
+    take(L.off_setmem, (size_t)L.memcap * sizeof(int));
+    take(L.off_setrc, (size_t)L.ecap * D);
+    take(L.off_hw, (size_t)HFIELDS * L.memcap * D);
     take(L.off_ctr, (size_t)C_COUNT * sizeof(unsigned long long));
     take(L.off_epart, (size_t)L.n_eitems * D);
     take(L.off_E, (size_t)std::max(nsys, 1) * D);
@@ -170,6 +186,10 @@ Dev bind(char *base, const Layout &L)
     d.sys_e0 = (int *)(base + L.off_syse0);
     d.cand = (int2 *)(base + L.off_cand);
     d.enc = (int2 *)(base + L.off_enc);
+    d.sys_eoff = (int *)(base + L.off_syseoff);
+    d.sys_ecnt = (int *)(base + L.off_sysecnt);
+    d.set_count = (int *)(base + L.off_setcount);
+    d.memcap = (int)L.memcap;
     d.set_start = (int *)(base + L.off_setstart);
     d.set_mem = (int *)(base + L.off_setmem);
     d.set_rc = (double *)(base + L.off_setrc);
@@ -218,9 +238,13 @@ struct qsym_ctx {
 
 namespace {
 
+// message of the last failure that had no context to hold it (creation)
+thread_local std::string g_noctx_err;
+
 int fail(qsym_ctx *c, int code, const std::string &msg)
 {
     if (c) c->err = msg;
+    else g_noctx_err = msg;
     return code;
 }
 
@@ -260,6 +284,7 @@ void build_tables(qsym_ctx *c)
     T.sys_poff.assign(nsys, 0);
     T.sys_c0.assign(nsys + 1, 0);
     T.sys_e0.assign(nsys + 1, 0);
+    T.sys_eoff.assign(nsys + 1, 0);
     T.bchunk.clear();
     T.kchunk.clear();
     T.eitems.clear();
@@ -285,6 +310,8 @@ void build_tables(qsym_ctx *c)
         for (long long i = c->off[s]; i < c->off[s + 1]; ++i) T.body_sys[i] = s;
     }
     T.sys_off[nsys] = (int)c->off[nsys];
+    for (int s = 0; s < nsys; ++s)
+        T.sys_eoff[s + 1] = T.sys_eoff[s] + (int)sys_enc_cap(c->off[s + 1] - c->off[s]);
     T.sys_c0[nsys] = (int)T.bchunk.size();
     T.sys_e0[nsys] = (int)T.eitems.size();
     if (T.bchunk.empty()) T.bchunk.push_back(make_int4(0, 0, 0, 0));
@@ -496,7 +523,7 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
     {
         Timer tm(c, P_SETS);
         SetsArgs sa{c->d, c->p.aH};
-        hipLaunchKernelGGL(k_sets, dim3(1), dim3(kSetsThreads), 0, st, sa);
+        hipLaunchKernelGGL(k_sets, dim3(c->nsys), dim3(kSetsThreads), 0, st, sa);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // 5-7: corrections and Hermite per set
@@ -596,19 +623,24 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
     c->base = (char *)workspace;
     c->d = bind(c->base, c->L);
     c->ustream = (hipStream_t)stream;
-    auto bail = [&](int code) {
-        if (c->stream) hipStreamDestroy(c->stream);
+    auto bail = [&](int code, const char *what) {
+        const hipError_t e = hipGetLastError();
+        g_noctx_err = std::string("qsym_create: ") + what + ": " + hipGetErrorString(e);
+        if (c->stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return code;
     };
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(QSYM_EHIP);
-    if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess) return bail(QSYM_EHIP);
-    if (hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) return bail(QSYM_EHIP);
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(QSYM_EHIP, "hipStreamCreateWithFlags");
+    if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess)
+        return bail(QSYM_EHIP, "hipEventCreateWithFlags");
+    if (hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+        return bail(QSYM_EHIP, "hipEventCreateWithFlags");
     build_tables(c);
     enter(c);
     hipStream_t st = c->stream;
     // zero the whole workspace once (outside any graph)
-    if (hipMemsetAsync(c->base, 0, c->L.total, st) != hipSuccess) return bail(QSYM_EHIP);
+    if (hipMemsetAsync(c->base, 0, c->L.total, st) != hipSuccess) return bail(QSYM_EHIP, "hipMemsetAsync");
     const Tables &T = c->T;
     bool ok = true;
     ok &= hipMemcpyAsync(c->d.sys_off, T.sys_off.data(), sizeof(int) * T.sys_off.size(),
@@ -621,6 +653,8 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.sys_e0, T.sys_e0.data(), sizeof(int) * T.sys_e0.size(),
                          hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.sys_eoff, T.sys_eoff.data(), sizeof(int) * T.sys_eoff.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.bchunk, T.bchunk.data(), sizeof(int4) * T.bchunk.size(),
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.kchunk, T.kchunk.data(), sizeof(int4) * T.kchunk.size(),
@@ -630,7 +664,7 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
     ok &= hipMemcpyAsync(c->d.body_sys, T.body_sys.data(), sizeof(int) * T.body_sys.size(),
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipStreamSynchronize(st) == hipSuccess;
-    if (!ok) return bail(QSYM_EHIP);
+    if (!ok) return bail(QSYM_EHIP, "table upload");
     // default kick shapes (the autotuner or a tuned table replaces them):
     // block 128, one i per lane, j-split so that the grid has >= 4096
     // workgroups where the size allows
@@ -652,7 +686,10 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
         sh.jchunk = std::max<long long>(jc, c->L.jchunk_min);
         sh.jchunk = (sh.jchunk + 127) / 128 * 128;
     }
-    if (upload_shape(c, 0) != QSYM_OK || upload_shape(c, 1) != QSYM_OK) return bail(QSYM_EINVAL);
+    if (upload_shape(c, 0) != QSYM_OK || upload_shape(c, 1) != QSYM_OK) {
+        g_noctx_err = c->err;
+        return bail(QSYM_EINVAL, "kick shape upload");
+    }
     leave(c);
     *out = c;
     return QSYM_OK;
@@ -782,18 +819,24 @@ int qsym_encounters(qsym_ctx *c, int32_t *pairs, int64_t cap, int64_t *n_pairs, 
     if (rc) return rc;
     const long long ne = (long long)h[C_ENC];
     *n_pairs = ne;
-    const long long held = std::min<long long>(ne, kCapE);
-    const long long k = std::min<long long>(held, cap);
     hipStream_t st = c->stream;
-    if (k > 0) {
-        // the device keeps the append order; the canonical (i < j,
-        // lexicographic) order is produced here
-        std::vector<int2> raw((size_t)held);
-        HIPCHK(c, hipMemcpyAsync(raw.data(), c->d.enc, sizeof(int2) * held, hipMemcpyDeviceToHost, st));
+    if (cap > 0 && ne > 0) {
+        // the device keeps per-system segments in append order; the
+        // canonical (i < j, lexicographic) order is produced here
+        std::vector<int> cnt(c->nsys);
+        std::vector<int2> seg((size_t)c->L.ecap);
+        HIPCHK(c, hipMemcpyAsync(cnt.data(), c->d.sys_ecnt, sizeof(int) * c->nsys, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(seg.data(), c->d.enc, sizeof(int2) * c->L.ecap, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipStreamSynchronize(st));
+        std::vector<int2> raw;
+        for (int s = 0; s < c->nsys; ++s) {
+            const int held = std::min(cnt[s], c->T.sys_eoff[s + 1] - c->T.sys_eoff[s]);
+            for (int k = 0; k < held; ++k) raw.push_back(seg[(size_t)c->T.sys_eoff[s] + k]);
+        }
         std::sort(raw.begin(), raw.end(), [](const int2 &a, const int2 &b) {
             return a.x != b.x ? a.x < b.x : a.y < b.y;
         });
+        const long long k = std::min<long long>((long long)raw.size(), cap);
         for (long long q = 0; q < k; ++q) {
             pairs[2 * q] = raw[q].x;
             pairs[2 * q + 1] = raw[q].y;
@@ -802,14 +845,21 @@ int qsym_encounters(qsym_ctx *c, int32_t *pairs, int64_t cap, int64_t *n_pairs, 
     if (set_id) {
         for (long long i = 0; i < c->ntot; ++i) set_id[i] = -1;
         const long long ns = (long long)h[C_NSETS], nu = (long long)h[C_NU];
-        if (ns > 0 && ne <= kCapE) {
-            std::vector<int> start(ns + 1), mem(nu);
-            HIPCHK(c, hipMemcpyAsync(start.data(), c->d.set_start, sizeof(int) * (ns + 1),
-                                     hipMemcpyDeviceToHost, st));
+        if (ns > 0 && !(h[C_STATUS] & S_ENC_OVF)) {
+            std::vector<int> start(ns), count(ns), mem(nu);
+            HIPCHK(c, hipMemcpyAsync(start.data(), c->d.set_start, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipMemcpyAsync(count.data(), c->d.set_count, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipMemcpyAsync(mem.data(), c->d.set_mem, sizeof(int) * nu, hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));
-            for (long long s = 0; s < ns; ++s)
-                for (int b = start[s]; b < start[s + 1]; ++b) set_id[mem[b]] = (int32_t)s;
+            // sets are numbered by their smallest member (members ascend)
+            std::vector<long long> order(ns);
+            for (long long s = 0; s < ns; ++s) order[s] = s;
+            std::sort(order.begin(), order.end(),
+                      [&](long long a, long long b) { return mem[start[a]] < mem[start[b]]; });
+            for (long long r = 0; r < ns; ++r) {
+                const long long s = order[r];
+                for (int b = start[s]; b < start[s] + count[s]; ++b) set_id[mem[b]] = (int32_t)r;
+            }
         }
     }
     HIPCHK(c, hipStreamSynchronize(st));
@@ -864,7 +914,7 @@ int qsym_stats(qsym_ctx *c, qsym_stats_t *out)
     return QSYM_OK;
 }
 
-const char *qsym_last_error(const qsym_ctx *c) { return c ? c->err.c_str() : "null context"; }
+const char *qsym_last_error(const qsym_ctx *c) { return c ? c->err.c_str() : g_noctx_err.c_str(); }
 
 int qsym_apply_drift(qsym_ctx *c, double dt)
 {

@@ -8,8 +8,8 @@ namespace qsym {
 
 constexpr int kChunk = 256;        // bodies per workgroup of the O(N) kernels
 constexpr int kChunkK = 64;        // bodies per workgroup of the Kepler pass
-constexpr int kCapE = 4096;        // encounter pairs per step handled on chip
-constexpr int kCapU = 2 * kCapE;   // bodies taking part in encounters
+constexpr int kCapE = 4096;        // encounter pairs of one system per step (on chip)
+constexpr int kCapU = 2 * kCapE;   // bodies of one system taking part in encounters
 constexpr int kHist = 32;          // Kepler iteration histogram bins
 constexpr int kSMax = 64;          // largest j-split of one system
 constexpr int kSetsThreads = 256;  // workgroup of the set-partition kernel
@@ -69,10 +69,14 @@ struct Dev {
     KickItem *eitems;                           // energy work items
     int *sys_e0;                                // [nsys+1] first energy item
     int2 *cand;                                 // crude candidates
-    int2 *enc;                                  // encounter pairs (append order)
-    int *set_start;                             // [kCapU+1]
-    int *set_mem;                               // [kCapU] member body indices
-    double *set_rc;                             // [kCapU] r_crit per set
+    int2 *enc;                                  // encounter pairs, per-system segments
+    int *sys_eoff;                              // [nsys+1] segment offsets (capacities)
+    int *sys_ecnt;                              // [nsys] pairs appended this step
+    int *set_start;                             // [setcap] first member slot of each set
+    int *set_count;                             // [setcap] members of each set
+    int *set_mem;                               // [memcap] member body indices
+    double *set_rc;                             // [setcap] r_crit per set
+    int memcap;                                 // member slots (Hermite scratch stride)
     double *hw;                                 // Hermite member scratch
     unsigned long long *ctr;                    // counters and status
     double *epart;                              // energy partials per item

@@ -122,6 +122,7 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
         d.ctr[C_NU] = 0;
     }
     if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) d.ctr[C_STEPS] += 1;
+    if (a.reset && threadIdx.x == 0 && (int)blockIdx.x == d.sys_c0[s]) d.sys_ecnt[s] = 0;
     const int t = threadIdx.x;
     if (t >= bc.z) return;
     const int i = bc.y + t;
@@ -158,9 +159,7 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
 // exact to FP64 rounding since |e| < 2^-22.  r^2 is floored at 1e-200 so a
 // body's own pair (and coincident bodies) contributes exactly zero.
 //
-// FP32 pair term (PREC 1): the separation is formed in FP64 and rounded to
-// FP32, the rest of the pair term is FP32 (hardware rsq), sums are FP32
-// within a j-tile and accumulated across tiles in FP64.
+// FP32 pair term (PREC 1): see pair32.
 //
 // Crude sweep: per j-tile the maxima of (h or h a, a, ve) bound the exact
 // threshold of every pair of the tile from above, so the pair loop only
@@ -233,6 +232,24 @@ __device__ __forceinline__ void pair64(const double4 &pj, double xi, double yi, 
     const double ms0 = pj.w * (y2 * y0);
     const double t = ms0 * e;
     const double ms = fma(t * e, 1.875, fma(t, 1.5, ms0));
+    ax = fma(ms, dx, ax);
+    ay = fma(ms, dy, ay);
+    az = fma(ms, dz, az);
+}
+
+// FP32 pair term on an FP64 separation: the differences and r^2 stay FP64
+// (an FP64 add or fma costs the same issue slot as an FP32 one on this
+// chip, and r^2 in FP64 needs one conversion instead of three), only
+// m r^-3 is formed in FP32 from the hardware rsq (no refinement), and the
+// sum is accumulated in FP64.  The 1e-24 seed keeps the own pair finite
+// (r^-3 = 1e36 < FLT_MAX) and changes no physical pair.
+__device__ __forceinline__ void pair32(const double4 &pj, float mj, double xi, double yi, double zi,
+                                       double &ax, double &ay, double &az, double &r2)
+{
+    const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
+    r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, 1e-24)));
+    const float y = __builtin_amdgcn_rsqf((float)r2);
+    const double ms = (double)(mj * (y * y * y));
     ax = fma(ms, dx, ax);
     ay = fma(ms, dy, ay);
     az = fma(ms, dz, az);
@@ -324,6 +341,9 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
                       : make_double4(kFar, kFar, kFar, 0.0);
         const int last_j = min(jt + BS, jend) - 1;
         const bool pred = MODE && (last_j > it.i0);
+        // j-slots of this tile, rounded up to the unroll factor (the
+        // padding slots are massless and far away)
+        const int ntj = (last_j - jt + 1 + 3) & ~3;
         if (MODE && pred) {
             // tile maxima of the crude-sweep terms (all non-negative)
             double t0 = okj ? d.ch[j] : 0.0, t1 = okj ? d.A[j] : 0.0, t2 = okj ? d.cv[j] : 0.0;
@@ -351,10 +371,8 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
                 // limit of every j in the tile; the factor covers the
                 // different rounding of r^2 in the pair loop
                 double th2[IPL];
-                float fx[IPL], fy[IPL], fz[IPL];
 #pragma unroll
                 for (int u = 0; u < IPL; ++u) {
-                    fx[u] = fy[u] = fz[u] = 0.0f;
                     double Rb;
                     if (MODE == 1)
                         Rb = ka.aE * (hi[u] + HT) * (Ai[u] + AT) / 2.0;
@@ -364,37 +382,21 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
                     th2[u] = th * th * 1.000000000001;
                 }
 #pragma unroll 4
-                for (int jj = 0; jj < BS; ++jj) {
+                for (int jj = 0; jj < ntj; ++jj) {
                     const double4 pj = sj[jj];
+                    const float mjf = (float)pj.w;
 #pragma unroll
                     for (int u = 0; u < IPL; ++u) {
                         double r2;
-                        if constexpr (PREC == 0) {
+                        if constexpr (PREC == 0)
                             pair64(pj, xi[u], yi[u], zi[u], seed, ax[u], ay[u], az[u], r2);
-                        } else {
-                            const double dxd = pj.x - xi[u], dyd = pj.y - yi[u], dzd = pj.z - zi[u];
-                            r2 = fma(dzd, dzd, fma(dyd, dyd, fma(dxd, dxd, seed)));
-                            const float dx = (float)dxd, dy = (float)dyd, dz = (float)dzd;
-                            const float r2f = fmaxf((float)r2, 1e-24f);
-                            const float y0 = __builtin_amdgcn_rsqf(r2f);
-                            const float ms = (float)pj.w * (y0 * y0 * y0);
-                            fx[u] = fmaf(ms, dx, fx[u]);
-                            fy[u] = fmaf(ms, dy, fy[u]);
-                            fz[u] = fmaf(ms, dz, fz[u]);
-                        }
+                        else
+                            pair32(pj, mjf, xi[u], yi[u], zi[u], ax[u], ay[u], az[u], r2);
                         if (r2 < th2[u]) {
                             const unsigned k = atomicAdd(&qn, 1u);
                             if (k < (unsigned)kCrudeQ)
                                 qbuf[k] = ((unsigned)tid << 16) | ((unsigned)u << 8) | (unsigned)jj;
                         }
-                    }
-                }
-                if constexpr (PREC != 0) {
-#pragma unroll
-                    for (int u = 0; u < IPL; ++u) {
-                        ax[u] += (double)fx[u];
-                        ay[u] += (double)fy[u];
-                        az[u] += (double)fz[u];
                     }
                 }
                 qtile = jt;
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
         }
         if constexpr (PREC == 0) {
 #pragma unroll 4
-            for (int jj = 0; jj < BS; ++jj) {
+            for (int jj = 0; jj < ntj; ++jj) {
                 const double4 pj = sj[jj];
 #pragma unroll
                 for (int u = 0; u < IPL; ++u) {
@@ -412,31 +414,15 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
                 }
             }
         } else {
-            float fx[IPL], fy[IPL], fz[IPL];
-#pragma unroll
-            for (int u = 0; u < IPL; ++u) fx[u] = fy[u] = fz[u] = 0.0f;
 #pragma unroll 4
-            for (int jj = 0; jj < BS; ++jj) {
+            for (int jj = 0; jj < ntj; ++jj) {
                 const double4 pj = sj[jj];
-                const float mj = (float)pj.w;
+                const float mjf = (float)pj.w;
 #pragma unroll
                 for (int u = 0; u < IPL; ++u) {
-                    const float dx = (float)(pj.x - xi[u]), dy = (float)(pj.y - yi[u]),
-                                dz = (float)(pj.z - zi[u]);
-                    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    const float r2c = fmaxf(r2, 1e-24f);
-                    const float y0 = __builtin_amdgcn_rsqf(r2c);
-                    const float ms = mj * (y0 * y0 * y0);
-                    fx[u] = fmaf(ms, dx, fx[u]);
-                    fy[u] = fmaf(ms, dy, fy[u]);
-                    fz[u] = fmaf(ms, dz, fz[u]);
+                    double r2;
+                    pair32(pj, mjf, xi[u], yi[u], zi[u], ax[u], ay[u], az[u], r2);
                 }
-            }
-#pragma unroll
-            for (int u = 0; u < IPL; ++u) {
-                ax[u] += (double)fx[u];
-                ay[u] += (double)fy[u];
-                az[u] += (double)fz[u];
             }
         }
     }
@@ -809,8 +795,10 @@ __global__ __launch_bounds__(256) void k_fine(FineArgs a)
         const int f = fine_pair(a.hill_mode, a.aE, d.sys_m0[d.body_sys[i]], a.tau, d.m[i], d.m[j],
                                 d.h[i], d.h[j], d.A[i], d.A[j], a0, b0, a1, b1, lhs, rhs);
         if (f) {
-            const unsigned long long slot = atomicAdd(&d.ctr[C_ENC], 1ull);
-            if (slot < (unsigned long long)kCapE) d.enc[slot] = make_int2(i, j);
+            atomicAdd(&d.ctr[C_ENC], 1ull);
+            const int s = d.body_sys[i];
+            const int slot = atomicAdd(&d.sys_ecnt[s], 1);
+            if (slot < d.sys_eoff[s + 1] - d.sys_eoff[s]) d.enc[d.sys_eoff[s] + slot] = make_int2(i, j);
         }
     }
 }
@@ -946,23 +934,22 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     __shared__ int flag[kCapU];          // scan scratch
     __shared__ int tmp[kSetsThreads / 64 + 1];
     __shared__ int changed;
+    __shared__ int base_set, base_mem;
     const int t = threadIdx.x;
-    const unsigned long long cnt = d.ctr[C_ENC];
-    if (cnt > (unsigned long long)kCapE) {
-        if (t == 0) {
-            latch(d.ctr, S_ENC_OVF);
-            d.ctr[C_NSETS] = 0;
-            atomicAdd(&d.ctr[C_TENC], cnt);
-        }
+    const int sys = blockIdx.x;
+    const int cnt = d.sys_ecnt[sys];
+    const int2 *enc = d.enc + d.sys_eoff[sys];
+    if (cnt > d.sys_eoff[sys + 1] - d.sys_eoff[sys] || cnt > kCapE) {
+        if (t == 0) latch(d.ctr, S_ENC_OVF);
         return;
     }
-    const int ne = (int)cnt;
+    const int ne = cnt;
     if (ne == 0) return;
     int m2 = 1;
     while (m2 < 2 * ne) m2 <<= 1;
     for (int k = t; k < m2; k += blockDim.x) {
         if (k < 2 * ne) {
-            const int2 p = d.enc[k >> 1];
+            const int2 p = enc[k >> 1];
             ep[k] = (unsigned)((k & 1) ? p.y : p.x);
         } else {
             ep[k] = 0xffffffffu;
@@ -979,7 +966,7 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
         if (lab[k]) uq[flag[k]] = ep[k];
     __syncthreads();
     for (int k = t; k < ne; k += blockDim.x) {
-        const int2 p = d.enc[k];
+        const int2 p = enc[k];
         const int ri = lower_rank(uq, nu, (unsigned)p.x);
         const int rj = lower_rank(uq, nu, (unsigned)p.y);
         rp[k] = ((unsigned)ri << 16) | (unsigned)rj;
@@ -1024,18 +1011,24 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
         ep[k] = (k < nu) ? ((lab[k] << 16) | (unsigned)k) : 0xffffffffu;
     __syncthreads();
     bitonic_sort_lds(ep, u2);
-    // member k of the sorted list: body uq[r], set flag[root]; the set index
-    // is kept in lab[k] (lab is free once the keys are built)
+    // global slots of this system's sets and members
+    if (t == 0) {
+        base_set = (int)atomicAdd(&d.ctr[C_NSETS], (unsigned long long)nsets);
+        base_mem = (int)atomicAdd(&d.ctr[C_NU], (unsigned long long)nu);
+    }
+    __syncthreads();
+    const int bs = base_set, bm = base_mem;
+    // member k of the sorted list: body uq[r], local set flag[root]; the
+    // local set index is kept in lab[k] (lab is free once the keys are built)
     for (int k = t; k < nu; k += blockDim.x) {
         const unsigned r = ep[k] & 0xffffu;
-        d.set_mem[k] = (int)uq[r];
+        d.set_mem[bm + k] = (int)uq[r];
         const unsigned root = ep[k] >> 16;
         const bool first = (k == 0) || ((ep[k - 1] >> 16) != root);
         const int sid = flag[root];
-        if (first) d.set_start[sid] = k;
+        if (first) d.set_start[bs + sid] = bm + k;
         lab[k] = (unsigned)sid;
     }
-    if (t == 0) d.set_start[nsets] = nu;
     __syncthreads();
     // r_crit = a_H max_{i in S} h_i a_i: one thread per member, max through
     // LDS atomics on the bit patterns (non-negative doubles order as
@@ -1049,24 +1042,21 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
         atomicMax(&rcb[lab[k]], (unsigned long long)__double_as_longlong(rh));
     }
     __syncthreads();
-    unsigned int big = 0;
     for (int sidx = t; sidx < nsets; sidx += blockDim.x)
-        d.set_rc[sidx] = a.aH * __longlong_as_double((long long)rcb[sidx]);
-    // largest set: from the member positions of the set starts
+        d.set_rc[bs + sidx] = a.aH * __longlong_as_double((long long)rcb[sidx]);
+    // set sizes (and the largest)
+    unsigned int big = 0;
     for (int k = t; k < nu; k += blockDim.x) {
         const bool first = (k == 0) || (lab[k - 1] != lab[k]);
         if (first) {
             int e = k + 1;
             while (e < nu && lab[e] == lab[k]) ++e;
+            d.set_count[bs + (int)lab[k]] = e - k;
             if ((unsigned)(e - k) > big) big = (unsigned)(e - k);
         }
     }
     if (big) atomicMax(&d.ctr[C_MAXSET], (unsigned long long)big);
-    if (t == 0) {
-        d.ctr[C_NSETS] = (unsigned long long)nsets;
-        d.ctr[C_NU] = (unsigned long long)nu;
-        atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
-    }
+    if (t == 0) atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
 }
 
 // ------------------------------------------------------------------------
@@ -1098,10 +1088,14 @@ struct HermArgs {
 
 constexpr int kHermLds = 1024;   // members of one set staged in LDS
 
-// member scratch layout: field f of member slot k at hw[f * kCapU + k]
-enum { HX = 0, HU = 3, HA = 6, HJ = 9, HXP = 12, HUP = 15, HFIELDS = 18 };
+// member scratch layout: field f of member slot k at hw[f * memcap + k]
+// HS..HS+6: staging of sets too large for LDS (x y z u v w m)
+enum { HX = 0, HU = 3, HA = 6, HJ = 9, HXP = 12, HUP = 15, HS = 18, HFIELDS = 25 };
 
-__device__ __forceinline__ double &hw_at(const Dev &d, int f, int k) { return d.hw[f * kCapU + k]; }
+__device__ __forceinline__ double &hw_at(const Dev &d, int f, int k)
+{
+    return d.hw[(long long)f * d.memcap + k];
+}
 
 struct SetLds {
     double *x, *y, *z, *u, *v, *w, *m;
@@ -1188,7 +1182,8 @@ __device__ __forceinline__ void herm_central(const double X[3], const double U[3
 }
 
 // One workgroup per encounter set (grid-stride over sets).  The set's
-// positions, velocities and masses are staged in LDS; each member's pair
+// positions, velocities and masses are staged in LDS (in the global member
+// scratch for sets of more than kHermLds members); each member's pair
 // sums are split over L lanes (L = largest power of two with L n <= 256,
 // at most 64) and combined by an xor tree.  Correction at q0 (Sec. 2.3
 // step 5), PEC Hermite over tau with one shared step per set (step 6),
@@ -1200,17 +1195,20 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
     __shared__ double s_u[kHermLds], s_v[kHermLds], s_w[kHermLds], s_m[kHermLds];
     __shared__ double lds[kHermThreads];
     __shared__ int s_fail;
-    const SetLds S{s_x, s_y, s_z, s_u, s_v, s_w, s_m};
     const int t = threadIdx.x;
     const int nsets = (int)d.ctr[C_NSETS];
     for (int sidx = blockIdx.x; sidx < nsets; sidx += gridDim.x) {
         const int b0 = d.set_start[sidx];
-        const int n = d.set_start[sidx + 1] - b0;
+        const int n = d.set_count[sidx];
         const double rc = d.set_rc[sidx];
-        if (n > kHermLds) {
-            if (t == 0) latch(d.ctr, S_SET_BIG);
-            continue;
-        }
+        // sets beyond the LDS capacity stage through the member scratch in
+        // global memory (same code, slower loads)
+        const bool big = n > kHermLds;
+        double *gs = d.hw + (long long)HS * d.memcap + b0;
+        const long long fs = d.memcap;
+        const SetLds S = big ? SetLds{gs, gs + fs, gs + 2 * fs, gs + 3 * fs, gs + 4 * fs, gs + 5 * fs,
+                                      gs + 6 * fs}
+                             : SetLds{s_x, s_y, s_z, s_u, s_v, s_w, s_m};
         int L = 1;
         while (L < 64 && 2 * L * n <= kHermThreads) L <<= 1;
         const int G = kHermThreads / L;
@@ -1220,10 +1218,10 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
         // stage q0, v0 and masses
         for (int k = t; k < n; k += kHermThreads) {
             const int i = d.set_mem[b0 + k];
-            s_x[k] = d.x0[i];
-            s_y[k] = d.y0[i];
-            s_z[k] = d.z0[i];
-            s_m[k] = d.m[i];
+            S.x[k] = d.x0[i];
+            S.y[k] = d.y0[i];
+            S.z[k] = d.z0[i];
+            S.m[k] = d.m[i];
         }
         __syncthreads();
         // step 5: v0 -= tau/2 * sum W-weighted in-set forces at q0
@@ -1233,18 +1231,18 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
             for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
             if (l == 0) {
                 const int i = d.set_mem[b0 + k];
-                hw_at(d, HX + 0, b0 + k) = s_x[k];
-                hw_at(d, HX + 1, b0 + k) = s_y[k];
-                hw_at(d, HX + 2, b0 + k) = s_z[k];
+                hw_at(d, HX + 0, b0 + k) = S.x[k];
+                hw_at(d, HX + 1, b0 + k) = S.y[k];
+                hw_at(d, HX + 2, b0 + k) = S.z[k];
                 const double u0 = d.vx0[i] - half * acc[0];
                 const double u1 = d.vy0[i] - half * acc[1];
                 const double u2 = d.vz0[i] - half * acc[2];
                 hw_at(d, HU + 0, b0 + k) = u0;
                 hw_at(d, HU + 1, b0 + k) = u1;
                 hw_at(d, HU + 2, b0 + k) = u2;
-                s_u[k] = u0;
-                s_v[k] = u1;
-                s_w[k] = u2;
+                S.u[k] = u0;
+                S.v[k] = u1;
+                S.w[k] = u2;
             }
         }
         __syncthreads();
@@ -1258,7 +1256,7 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
                 jr[c] = group_sum(jr[c], L);
             }
             if (l == 0) {
-                const double X[3] = {s_x[k], s_y[k], s_z[k]}, U[3] = {s_u[k], s_v[k], s_w[k]};
+                const double X[3] = {S.x[k], S.y[k], S.z[k]}, U[3] = {S.u[k], S.v[k], S.w[k]};
                 herm_central(X, U, mu, acc, jr);
                 for (int c = 0; c < 3; ++c) {
                     hw_at(d, HA + c, b0 + k) = acc[c];
@@ -1298,8 +1296,8 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
                     hw_at(d, HXP + c, b0 + k) = xp[c];
                     hw_at(d, HUP + c, b0 + k) = up[c];
                 }
-                s_x[k] = xp[0]; s_y[k] = xp[1]; s_z[k] = xp[2];
-                s_u[k] = up[0]; s_v[k] = up[1]; s_w[k] = up[2];
+                S.x[k] = xp[0]; S.y[k] = xp[1]; S.z[k] = xp[2];
+                S.u[k] = up[0]; S.v[k] = up[1]; S.w[k] = up[2];
             }
             __syncthreads();
             double hn = INFINITY;
@@ -1311,7 +1309,7 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
                     j1[c] = group_sum(j1[c], L);
                 }
                 if (l == 0) {
-                    const double X[3] = {s_x[k], s_y[k], s_z[k]}, U[3] = {s_u[k], s_v[k], s_w[k]};
+                    const double X[3] = {S.x[k], S.y[k], S.z[k]}, U[3] = {S.u[k], S.v[k], S.w[k]};
                     herm_central(X, U, mu, a1, j1);
                     double A2e[3], A3v[3];
                     for (int c = 0; c < 3; ++c) {
@@ -1348,9 +1346,9 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
         // step 7: stage the final positions, v1 -= tau/2 * W-weighted
         // in-set forces at q1, write back
         for (int k = t; k < n; k += kHermThreads) {
-            s_x[k] = hw_at(d, HX + 0, b0 + k);
-            s_y[k] = hw_at(d, HX + 1, b0 + k);
-            s_z[k] = hw_at(d, HX + 2, b0 + k);
+            S.x[k] = hw_at(d, HX + 0, b0 + k);
+            S.y[k] = hw_at(d, HX + 1, b0 + k);
+            S.z[k] = hw_at(d, HX + 2, b0 + k);
         }
         __syncthreads();
         for (int k = g; k < n; k += G) {
@@ -1359,9 +1357,9 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
             for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
             if (l == 0) {
                 const int i = d.set_mem[b0 + k];
-                d.x[i] = s_x[k];
-                d.y[i] = s_y[k];
-                d.z[i] = s_z[k];
+                d.x[i] = S.x[k];
+                d.y[i] = S.y[k];
+                d.z[i] = S.z[k];
                 d.vx[i] = hw_at(d, HU + 0, b0 + k) - half * acc[0];
                 d.vy[i] = hw_at(d, HU + 1, b0 + k) - half * acc[1];
                 d.vz[i] = hw_at(d, HU + 2, b0 + k) - half * acc[2];

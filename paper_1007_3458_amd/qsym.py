@@ -108,9 +108,14 @@ SIGNATURES = {
 
 
 def lib():
-    """Load libqsym.so (raises if it has not been built)."""
+    """Load libqsym.so (raises if it has not been built).
+
+    torch is imported first: torch carries its own HIP runtime with the same
+    soname as the system one, and the process must use a single runtime (the
+    one torch allocates device memory and streams with)."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (loads torch's HIP runtime before ours binds to it)
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
         L = C.CDLL(LIB_PATH)
@@ -176,7 +181,7 @@ class Context:
                            self.m0.ctypes.data_as(_dp), C.c_void_p(self._ws_ptr),
                            self.ws_bytes, C.c_void_p(self.stream.cuda_stream), C.byref(h))
         if rc != 0:
-            raise QsymError(rc, "qsym_create failed")
+            raise QsymError(rc, lib().qsym_last_error(None).decode())
         self.ctx = h
         m = np.concatenate([s.m for s in systems]).astype(np.float64)
         hh = np.concatenate([s.h for s in systems]).astype(np.float64)
@@ -196,8 +201,7 @@ class Context:
     # ---------------------------------------------------------- helpers
     def _check(self, rc, ctx):
         if rc != 0:
-            msg = lib().qsym_last_error(ctx).decode() if ctx is not None else ""
-            raise QsymError(rc, msg)
+            raise QsymError(rc, lib().qsym_last_error(ctx).decode())
 
     def _c(self, rc):
         self._check(rc, self.ctx)

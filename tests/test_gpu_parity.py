@@ -315,3 +315,57 @@ def test_edge_sizes(Q, orc):
             q, v, _ = orc.step(orc.make_params(), 0.05, s.m, s.h, q, v)
         assert per_body_rel(qg, q) < 1e-12 and per_body_rel(vg, v) < 1e-12
         ctx.close()
+
+
+def test_fp32_form_accuracy_and_step(Q, orc):
+    """Precision form: m r^-3 in FP32 on FP64 separations, FP64 sums.  Per-body
+    acceleration error against the oracle at the FP32 level; the whole step
+    stays close to the oracle step and keeps the encounter list."""
+    s = inputs.scaled_disk(4096, seed=14)
+    say("fp32 form")
+    s0 = s.copy()
+    s0.v[:] = 0.0
+    ctx = Q.Context(s0, precision=1)
+    ctx.set_kick_shape(2, 256, 512, 1)
+    ctx.apply_kick(1.0)
+    _, a = ctx.get_state()
+    ao = orc.accel(s.G, s.m, s.q)
+    rel = np.linalg.norm(a - ao, axis=1) / np.linalg.norm(ao, axis=1)
+    print("fp32 form accel rel err max %.3e rms %.3e" % (rel.max(), np.sqrt(np.mean(rel ** 2))))
+    assert rel.max() < 2e-6 and np.sqrt(np.mean(rel ** 2)) < 3e-7
+    ctx.close()
+    ctx = Q.Context(s, precision=1)
+    ctx.step(0.05, 1)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    pg, _ = ctx.encounters()
+    qo, vo, r = orc.step(orc.make_params(), 0.05, s.m, s.h, s.q, s.v)
+    assert per_body_rel(qg, qo) < 1e-9 and per_body_rel(vg, vo) < 1e-7
+    ctx.close()
+
+
+def test_set_larger_than_lds_stage(Q, orc):
+    """A body on a nearly parabolic orbit has a huge osculating semi-major
+    axis, hence a huge Hill radius: every body joins its encounter set.  A set
+    of more than 1024 members is integrated from the global staging path."""
+    base = inputs.make_disk("wide", 21, 1300, 1e-9, 4.5, 6.0, "uniform", "uniform", 0.05, 0.01,
+                            planets=False)
+    rng = np.random.Generator(np.random.PCG64(3))
+    r = np.array([5.0, 0.1, 0.0])
+    vesc = np.sqrt(2.0 / np.linalg.norm(r))
+    v = np.array([0.0, 0.99995 * vesc, 0.0])
+    m = np.concatenate([base.m, [1e-6]])
+    q = np.vstack([base.q, r])
+    vv = np.vstack([base.v, v])
+    s = inputs.System("bigset", 1.0, 1.0, m, q, vv)
+    say("big set", s.n)
+    ctx = Q.Context(s)
+    ctx.step(0.05, 1)
+    ctx.sync()
+    st = ctx.stats()
+    assert st["max_set"] > 1024
+    qg, vg = ctx.get_state()
+    qo, vo, res = orc.step(orc.make_params(), 0.05, s.m, s.h, s.q, s.v)
+    assert res.stats["max_set"] == st["max_set"]
+    assert per_body_rel(qg, qo) < 1e-12 and per_body_rel(vg, vo) < 1e-12
+    ctx.close()

@@ -134,3 +134,9 @@ def test_prepass_semimajor_axis_and_escape_speed(orc):
     vh = np.array([[0, 2.0, 0]])
     A2, _ = orc.prepass(mu, qh, vh)
     assert A2[0] == 1.0
+
+
+def test_accel_rows_equals_full_accel(orc):
+    m, q, v = _rand_system(40, 6)
+    rows = np.array([0, 7, 39, 7], np.int64)
+    assert np.array_equal(orc.accel_rows(1.0, m, q, rows), orc.accel(1.0, m, q)[rows])
