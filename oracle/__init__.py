@@ -1,4 +1,5 @@
-"""ctypes front-end of the FP64 CPU oracle (``qsym_oracle.c``).
+"""ctypes front-end of the FP64 CPU oracle (``qsym_oracle.c`` and
+``kepler_guess_oracle.c``).
 
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
 CPU-baseline leg call it; the HIP product path never does.  Arrays are
@@ -13,7 +14,7 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "qsym_oracle.c")
+SRCS = [os.path.join(HERE, "qsym_oracle.c"), os.path.join(HERE, "kepler_guess_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 _dp = C.POINTER(C.c_double)
@@ -50,10 +51,12 @@ def make_params(**kw) -> Params:
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    stale = not os.path.exists(LIB) or any(
+        os.path.getmtime(LIB) < os.path.getmtime(src) for src in SRCS)
+    if force or stale:
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
-                               "-fno-fast-math", "-fopenmp", "-o", tmp, SRC, "-lm"])
+                               "-fno-fast-math", "-fopenmp", "-o", tmp, *SRCS, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -92,6 +95,15 @@ def lib():
             "orc_angmom": (None, [i64, _dp, _dp, _dp, _dp]),
             "orc_step": (C.c_int, [i64, pp, d, _dp, _dp, _dp, _dp, i64, _ip, i64, _ip,
                                    C.POINTER(Stats)]),
+            "orc_guess_features": (C.c_int, [d, _dp, _dp, d, _dp, _dp, _dp]),
+            "orc_guess_net": (d, [_dp, _dp, _dp, _dp]),
+            "orc_guess": (d, [_dp, d, _dp, _dp, d]),
+            "orc_guess_target": (d, [d, _dp, _dp, d, d]),
+            "orc_guess_dataset": (None, [i64, d, _dp, _dp, _dp, _dp, _dp, _dp]),
+            "orc_guess_scalers": (None, [i64, _dp, _dp, _dp]),
+            "orc_guess_loss_grad": (d, [_dp, i64, _dp, _dp, _dp]),
+            "orc_adam": (None, [i64, _dp, _dp, _dp, _dp, i64, d, d, d, d]),
+            "orc_kepler_roots": (i64, [i64, d, _dp, _dp, _dp, i32, _dp, _dp, _ip]),
             "orc_num_threads": (C.c_int, []),
             "orc_set_threads": (None, [C.c_int]),
         }
@@ -280,3 +292,82 @@ def num_threads() -> int:
 
 def set_threads(k: int) -> None:
     lib().orc_set_threads(int(k))
+
+
+# ---------------------------------------------------------------------------
+# learned starting value of the Kepler solve (kepler_guess_oracle.c)
+# ---------------------------------------------------------------------------
+GUESS_NPARAM = 1249
+GUESS_NWEIGHTS = 1259   # parameters + 10 scalers
+
+
+def guess_features(mu, x0, v0, dt):
+    """(f[4], x_p, T) of one body, or None for dt == 0."""
+    x0 = _f64(x0, (3,)); v0 = _f64(v0, (3,))
+    f = np.zeros(4); xp = C.c_double(); T = C.c_double()
+    if lib().orc_guess_features(mu, _d(x0), _d(v0), dt, _d(f), C.byref(xp), C.byref(T)):
+        return None
+    return f, xp.value, T.value
+
+
+def guess_net(w, inp):
+    """Network output and hidden activations on standardised inputs."""
+    w = _f64(w); inp = _f64(inp, (4,))
+    h1 = np.zeros(32); h2 = np.zeros(32)
+    o = lib().orc_guess_net(_d(w), _d(inp), _d(h1), _d(h2))
+    return o, h1, h2
+
+
+def guess(w, mu, x0, v0, dt):
+    w = _f64(w); x0 = _f64(x0, (3,)); v0 = _f64(v0, (3,))
+    assert w.size == GUESS_NWEIGHTS
+    return lib().orc_guess(_d(w), mu, _d(x0), _d(v0), dt)
+
+
+def guess_target(mu, x0, v0, dt, x):
+    x0 = _f64(x0, (3,)); v0 = _f64(v0, (3,))
+    return lib().orc_guess_target(mu, _d(x0), _d(v0), dt, x)
+
+
+def guess_dataset(mu, q, v, dt, x):
+    """Raw features (n, 4) and targets (n,) of solved bodies."""
+    q = _f64(q, (-1, 3)); v = _f64(v, (-1, 3)); n = q.shape[0]
+    dt = _f64(np.broadcast_to(np.asarray(dt, np.float64), (n,))); x = _f64(x)
+    f = np.zeros((n, 4)); y = np.zeros(n)
+    lib().orc_guess_dataset(n, mu, _d(q), _d(v), _d(dt), _d(x), _d(f), _d(y))
+    return f, y
+
+
+def guess_scalers(f, y):
+    f = _f64(f, (-1, 4)); y = _f64(y)
+    sc = np.zeros(10)
+    lib().orc_guess_scalers(f.shape[0], _d(f), _d(y), _d(sc))
+    return sc
+
+
+def guess_loss_grad(w, f, y, want_grad=True):
+    w = _f64(w); f = _f64(f, (-1, 4)); y = _f64(y)
+    assert w.size == GUESS_NWEIGHTS
+    g = np.zeros(GUESS_NPARAM) if want_grad else None
+    loss = lib().orc_guess_loss_grad(_d(w), f.shape[0], _d(f), _d(y),
+                                     _d(g) if want_grad else None)
+    return (loss, g) if want_grad else loss
+
+
+def adam(w, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update in place on float64 arrays w, m, v."""
+    for a in (w, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    lib().orc_adam(g.size, _d(w), _d(g), _d(m), _d(v), int(t), lr, b1, b2, eps)
+
+
+def kepler_roots(mu, q, v, dt, mode=0, x_start=None):
+    """Universal anomalies of n bodies (per-body dt); returns x, iters, fails."""
+    q = _f64(q, (-1, 3)); v = _f64(v, (-1, 3)); n = q.shape[0]
+    dt = _f64(np.broadcast_to(np.asarray(dt, np.float64), (n,)))
+    xs = None if x_start is None else _f64(x_start)
+    x = np.zeros(n); it = np.zeros(n, np.int32)
+    fails = lib().orc_kepler_roots(n, mu, _d(q), _d(v), _d(dt), mode,
+                                   None if xs is None else _d(xs), _d(x), _i(it))
+    return x, it, int(fails)

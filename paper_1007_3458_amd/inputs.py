@@ -23,6 +23,13 @@ stand in for it:
   seed 4_000_000 + k.
 * ``kepler_test`` massless bodies (a ~ U[0.5, 50], e ~ U[0, 0.9],
   i ~ U[0, 0.1]); seed 6.
+* ``kepler_train`` training solves for the learned Kepler starting value:
+  a ~ U[0.5, 50], e ~ U[0, 0.9], isotropic orientation, steps
+  dt ~ log-U[0.005, 0.5]; seed 5.
+* ``learned_workload`` 1,048,576 ``kepler_test`` bodies (seed 6) after a
+  65,536-planetesimal disk with the 4 planets (disk16k distributions, seed 6).
+* ``guess_init`` Glorot-uniform starting weights of the 4-32-32-1 network,
+  zero biases, rounded to float32; seed 7.
 
 Positions are heliocentric; velocities are barycentric, i.e. the heliocentric
 velocity minus sum_j m_j u_j / (m0 + sum_j m_j) (the democratic-heliocentric
@@ -212,3 +219,48 @@ def kepler_test(n: int, seed: int = 6, a_lo=0.5, a_hi=50.0, e_hi=0.9, i_hi=0.1,
 def random_unit(rng, n):
     x = rng.normal(size=(n, 3))
     return x / np.linalg.norm(x, axis=1, keepdims=True)
+
+
+def kepler_train(n: int = 1_000_000, seed: int = 5, a_lo=0.5, a_hi=50.0, e_hi=0.9,
+                 dt_lo=0.005, dt_hi=0.5, mu: float = 1.0):
+    """Bound orbits with isotropic orientation and log-uniform steps:
+    returns q (n, 3), u (n, 3), dt (n,)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.uniform(a_lo, a_hi, n)
+    e = rng.uniform(0.0, e_hi, n)
+    inc = np.arccos(rng.uniform(-1.0, 1.0, n))
+    ang = rng.uniform(0.0, 2 * np.pi, (3, n))
+    q, u = elements_to_cartesian(mu, a, e, inc, ang[0], ang[1], ang[2])
+    dt = np.exp(rng.uniform(np.log(dt_lo), np.log(dt_hi), n))
+    return q, u, dt
+
+
+def learned_workload(n_test: int = 1_048_576, n_disk: int = 65_536, seed: int = 6) -> System:
+    """Massless test bodies behind a planetesimal disk with four planets."""
+    disk = make_disk("disk64k", seed, n_disk, 1e-8, 15.0, 40.0, "rayleigh", "rayleigh",
+                     0.05, 0.025)
+    tp = kepler_test(n_test, seed)
+    m = np.concatenate([disk.m, tp.m])
+    q = np.concatenate([disk.q, tp.q])
+    u = np.concatenate([disk.v, tp.v])
+    return System("learned", disk.G, disk.m0, m, q, u)
+
+
+# (size, fan_in, fan_out) of W1, b1, W2, b2, W3, b3; fan_in 0 marks a bias
+GUESS_BLOCKS = ((128, 4, 32), (32, 0, 0), (1024, 32, 32), (32, 0, 0), (32, 32, 1), (1, 0, 0))
+
+
+def guess_init(seed: int = 7) -> np.ndarray:
+    """1249 starting parameters (W1, b1, W2, b2, W3, b3 in that order, weight
+    matrices row-major with one row per output unit), float32-exact."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for size, fan_in, fan_out in GUESS_BLOCKS:
+        if fan_in:
+            lim = np.sqrt(6.0 / (fan_in + fan_out))
+            parts.append(rng.uniform(-lim, lim, size))
+        else:
+            parts.append(np.zeros(size))
+    w = np.concatenate(parts).astype(np.float32).astype(np.float64)
+    assert w.size == 1249
+    return w
