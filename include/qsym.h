@@ -187,6 +187,81 @@ int qsym_autotune(qsym_ctx *ctx, double tau, double *us);
  * 6 second kick, 7 kick apply + momentum, 8 final drift, 9 energy. */
 int qsym_profile(qsym_ctx *ctx, int32_t enable);
 
+/* ------------------------------------------------------------------------
+ * Learned starting value of the Kepler solve (kepler_mode 2).  Not in the
+ * paper, which iterates from a fixed start (Appendix A).  With r0 = |x0|,
+ * s = sign(dt), T = sqrt(mu)|dt|/r0^1.5, alpha = 2/r0 - v0^2/mu:
+ *   features f = (ln r0, s x0.v0/sqrt(mu r0), alpha r0, ln T)
+ *   start    x = (sqrt(mu) dt/r0) exp(T (o s_y + m_y))
+ * where o is a 4-32-32-1 tanh network on (f_k - m_k)/s_k.  Weights are
+ * QSYM_GUESS_WEIGHTS floats: W1[32][4] (row = first-layer unit) at 0,
+ * b1 at 128, W2[32][32] (row = second-layer unit) at 160, b2 at 1184,
+ * W3 at 1216, b3 at 1248, then m_0..m_3, s_0..s_3, m_y, s_y.
+ * Newton from the start stops at |dx| <= 1e-14 |x|.  A start whose ratio to
+ * the first-order guess sqrt(mu) dt / r0 is not within [r0/r_max, r0/q]
+ * (apocentre r_max, infinite for e >= 1; pericentre q), where the root's
+ * ratio always lies, is replaced by the first-order guess, and Newton that
+ * reaches its cap restarts as Laguerre from the first-order guess, so bad
+ * weights cost iterations, never the result.
+ * ------------------------------------------------------------------------ */
+#define QSYM_GUESS_PARAMS 1249
+#define QSYM_GUESS_WEIGHTS 1259
+
+/* Weights of the learned start used by kepler_mode 2 (copied; where =
+ * QSYM_HOST or QSYM_DEVICE).  qsym_step and qsym_apply_kepler fail with
+ * QSYM_EINVAL in kepler_mode 2 until weights are set. */
+int qsym_set_guess(qsym_ctx *ctx, const float *weights, int32_t where);
+
+/* Stand-alone Kepler roots (Appendix A) of n bodies, each with its own
+ * step: state is device SoA [6][n] (x, y, z, vx, vy, vz), dt device [n],
+ * mode as kepler_mode (weights: device QSYM_GUESS_WEIGHTS floats, needed
+ * for mode 2 only), x_out device [n] receives the universal anomaly, iters
+ * (device [n], may be NULL) the iteration count, negated when every start
+ * reached the cap.  Enqueued on `stream`, not synchronised. */
+int qsym_kepler_solve(double mu, int64_t n, const double *state, const double *dt, int32_t mode,
+                      const float *weights, double *x_out, int32_t *iters, void *stream);
+/* The learned start alone (x_out device [n]; 0 for a zero step, not
+ * finite when the network or the features are unusable). */
+int qsym_kepler_guess(double mu, int64_t n, const double *state, const double *dt,
+                      const float *weights, double *x_out, void *stream);
+
+/* Training of the learned start on the GPU.  Samples are device FP32
+ * column-major: rows 0..3 of feat hold f, row 4 the target
+ * y = ln(x / x_p) / T of a solved root x, rows ld floats apart.  The loss of
+ * n samples is (1/n) sum (o - (y - m_y)/s_y)^2.  A trainer owns its device
+ * scratch (allocated at creation) and the Adam moments; it runs on
+ * `stream`.  max_batch bounds n of qsym_guess_grad and the batch of
+ * qsym_guess_train. */
+typedef struct qsym_guess_trainer qsym_guess_trainer;
+int qsym_guess_trainer_create(int64_t max_batch, void *stream, qsym_guess_trainer **out);
+void qsym_guess_trainer_destroy(qsym_guess_trainer *tr);
+const char *qsym_guess_trainer_error(const qsym_guess_trainer *tr);
+/* zero the Adam moments and the step count */
+int qsym_guess_reset(qsym_guess_trainer *tr);
+/* features and targets (x_root device [n], may be NULL: targets 0) of n
+ * bodies; QSYM_EINVAL when a sample has a zero step or a non-finite
+ * feature or target.  Synchronises the stream. */
+int qsym_guess_prepare(qsym_guess_trainer *tr, double mu, int64_t n, const double *state,
+                       const double *dt, const double *x_root, float *feat, int64_t ld);
+/* means and population deviations of the 5 rows into weights[1249..1258]
+ * (a zero deviation becomes 1) */
+int qsym_guess_fit_scalers(qsym_guess_trainer *tr, const float *feat, int64_t ld, int64_t n,
+                           float *weights);
+/* dL/dw (device [1249]) of n samples; loss (host, may be NULL) receives L
+ * and then the stream is synchronised. */
+int qsym_guess_grad(qsym_guess_trainer *tr, const float *weights, const float *feat, int64_t ld,
+                    int64_t n, float *grad, double *loss);
+/* one Adam update (Kingma & Ba 2015, Alg. 1) of weights[0..1248] from grad */
+int qsym_guess_adam(qsym_guess_trainer *tr, float *weights, const float *grad, double lr,
+                    double b1, double b2, double eps);
+/* epochs of mini-batch Adam (b1 0.9, b2 0.999, eps 1e-8) over the samples
+ * in order, batches of `batch`, learning rate decayed from lr to lr_final
+ * on a half cosine over the epochs; curve (host [epochs], may be NULL)
+ * receives each epoch's mean loss.  Synchronises the stream. */
+int qsym_guess_train(qsym_guess_trainer *tr, float *weights, const float *feat, int64_t ld,
+                     int64_t n, int64_t batch, int32_t epochs, double lr, double lr_final,
+                     double *curve);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,7 @@ def lib():
             "orc_stumpff": (None, [d, _dp, _dp]),
             "orc_kepler_body": (C.c_int, [d, _dp, _dp, d, i32, _dp, _dp, _ip]),
             "orc_kepler_root": (C.c_int, [d, _dp, _dp, d, i32, d, i32, _dp, _ip]),
+            "orc_start_admissible": (C.c_int, [d, _dp, _dp, d, d]),
             "orc_kepler_all": (i64, [i64, d, _dp, _dp, d, i32, _dp, _dp, _ip]),
             "orc_drift": (None, [i64, d, _dp, _dp, _dp, d]),
             "orc_prepass": (None, [i64, d, _dp, _dp, _dp, _dp]),
@@ -142,6 +143,11 @@ def kepler(mu, q, v, dt, mode=0):
     q1 = np.empty_like(q); v1 = np.empty_like(v); it = np.zeros(n, np.int32)
     fails = lib().orc_kepler_all(n, mu, _d(q), _d(v), dt, mode, _d(q1), _d(v1), _i(it))
     return q1, v1, it, int(fails)
+
+
+def start_admissible(mu, x0, v0, dt, xs):
+    x0 = _f64(x0, (3,)); v0 = _f64(v0, (3,))
+    return bool(lib().orc_start_admissible(mu, _d(x0), _d(v0), dt, xs))
 
 
 def kepler_root(mu, x0, v0, dt, mode=0, x_start=None):

@@ -185,11 +185,40 @@ static int orc_kepler_iterate(double smu, double r0, double rv, double alpha, do
  *         hit the cap), so on reaching the cap it restarts once from the
  *         first-order guess sqrt(mu) dt / r0 (a reading, see the tests).
  * mode 1: Newton from the first-order guess sqrt(mu) dt / r0.
- * mode 2: Newton from x_start (a proposed guess, e.g. a learned one),
- *         starting from the first-order guess when x_start is not finite.
+ * mode 2: Newton from x_start (a proposed guess, e.g. a learned one) when
+ *         it is admissible (orc_start_admissible), else from the
+ *         first-order guess.
  * Modes 1 and 2 fall back to Laguerre from the first-order guess when
  * Newton reaches the cap (possible over many revolutions).
  * Returns 0 on convergence, 1 if the iteration cap was hit. */
+/* Admissible starting values.  Along the orbit dx/dt = sqrt(mu)/r, so the
+ * root over a step dt is x = sqrt(mu) dt <1/r> and its ratio to the
+ * first-order guess sqrt(mu) dt / r0 lies between r0/r_max and r0/q, with q
+ * the pericentre distance and r_max the apocentre (unbounded for e >= 1):
+ * q = h^2 / (mu (1 + e)), r_max = h^2 / (mu (1 - e)), h = |x0 x v0|,
+ * e^2 = 1 - alpha h^2 / mu.  A proposed start outside that range (or not
+ * finite, or of the wrong sign) cannot be close to the root and is not
+ * used; far outside it, the Stumpff functions of a huge argument can even
+ * make Newton stop at a wrong value. */
+int orc_start_admissible(double mu, const double *x0, const double *v0, double dt, double xs)
+{
+    if (!isfinite(xs) || dt == 0.0) return 0;
+    double r0 = sqrt(x0[0] * x0[0] + x0[1] * x0[1] + x0[2] * x0[2]);
+    double vv = v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2];
+    double alpha = 2.0 / r0 - vv / mu;
+    double hx = x0[1] * v0[2] - x0[2] * v0[1];
+    double hy = x0[2] * v0[0] - x0[0] * v0[2];
+    double hz = x0[0] * v0[1] - x0[1] * v0[0];
+    double h2 = hx * hx + hy * hy + hz * hz;
+    double e2 = 1.0 - alpha * h2 / mu;
+    double e = e2 > 0.0 ? sqrt(e2) : 0.0;
+    double rho = xs / (sqrt(mu) * dt / r0);
+    if (!(rho > 0.0)) return 0;
+    if (h2 > 0.0 && rho > r0 * mu * (1.0 + e) / h2) return 0;
+    if (alpha > 0.0 && e < 1.0 && h2 > 0.0 && rho < r0 * mu * (1.0 - e) / h2) return 0;
+    return 1;
+}
+
 int orc_kepler_root(double mu, const double *x0, const double *v0, double dt,
                     int32_t mode, double x_start, int32_t use_start, double *x_out,
                     int32_t *iters)
@@ -212,7 +241,8 @@ int orc_kepler_root(double mu, const double *x0, const double *v0, double dt,
             ok = orc_kepler_iterate(smu, r0, rv, alpha, dt, 1, &x, &count);
         }
     } else {
-        x = (mode == 2 && use_start && isfinite(x_start)) ? x_start : guess;
+        x = (mode == 2 && use_start && orc_start_admissible(mu, x0, v0, dt, x_start)) ? x_start
+                                                                                       : guess;
         ok = orc_kepler_iterate(smu, r0, rv, alpha, dt, 0, &x, &count);
         if (!ok) {
             x = guess;

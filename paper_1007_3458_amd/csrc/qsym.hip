@@ -37,7 +37,7 @@ struct Layout {
     size_t off_sysoff = 0, off_sysm0 = 0, off_sysS = 0, off_syspoff = 0, off_sysc0 = 0;
     size_t off_bchunk = 0, off_kchunk = 0, off_items = 0, off_eitems = 0, off_syse0 = 0, off_cand = 0;
     size_t off_enc = 0, off_syseoff = 0, off_sysecnt = 0, off_setcount = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0;
-    size_t off_hw = 0, off_ctr = 0, off_epart = 0, off_E = 0, off_mlp = 0;
+    size_t off_hw = 0, off_ctr = 0, off_epart = 0, off_E = 0, off_guess = 0;
     size_t total = 0;
     long long np = 0;          // padded body count
     long long acc_len = 0;     // doubles of kick partials
@@ -142,7 +142,7 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_ctr, (size_t)C_COUNT * sizeof(unsigned long long));
     take(L.off_epart, (size_t)L.n_eitems * D);
     take(L.off_E, (size_t)std::max(nsys, 1) * D);
-    take(L.off_mlp, (size_t)(kMlpParams + 16) * sizeof(float));
+    take(L.off_guess, (size_t)(kGuessWeights + 5) * sizeof(float));
     L.total = align_up(o, 256);
     return L;
 }
@@ -197,7 +197,7 @@ Dev bind(char *base, const Layout &L)
     d.ctr = (unsigned long long *)(base + L.off_ctr);
     d.epart = (double *)(base + L.off_epart);
     d.E = (double *)(base + L.off_E);
-    d.mlp = (float *)(base + L.off_mlp);
+    d.guess = (float *)(base + L.off_guess);
     return d;
 }
 
@@ -231,7 +231,7 @@ struct qsym_ctx {
     size_t pool_used = 0;
     double phase_us[kPhases] = {};
     long long phase_calls[kPhases] = {};
-    bool mlp_loaded = false;
+    bool guess_loaded = false;
     double tau_crude = 0.0;  // |tau| of the crude sweep being enqueued
     std::string err;
 };
@@ -756,6 +756,8 @@ int qsym_get_state(qsym_ctx *c, double *q, double *v, int32_t where)
 int qsym_step(qsym_ctx *c, double tau, int64_t nsteps)
 {
     if (!c || nsteps < 0 || !std::isfinite(tau)) return fail(c, QSYM_EINVAL, "step: bad argument");
+    if (c->p.kepler_mode == 2 && !c->guess_loaded)
+        return fail(c, QSYM_EINVAL, "kepler_mode 2 needs weights (qsym_set_guess)");
     if (nsteps == 0 || c->ntot == 0) return QSYM_OK;
     enter(c);
     if (c->profile) {
@@ -782,6 +784,20 @@ int qsym_step(qsym_ctx *c, double tau, int64_t nsteps)
     }
     for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
     leave(c);
+    return QSYM_OK;
+}
+
+int qsym_set_guess(qsym_ctx *c, const float *weights, int32_t where)
+{
+    if (!c || !weights || (where != QSYM_HOST && where != QSYM_DEVICE))
+        return fail(c, QSYM_EINVAL, "set_guess: bad argument");
+    enter(c);
+    HIPCHK(c, hipMemcpyAsync(c->d.guess, weights, sizeof(float) * kGuessWeights,
+                             where == QSYM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    leave(c);
+    c->guess_loaded = true;
     return QSYM_OK;
 }
 
@@ -941,6 +957,8 @@ int qsym_apply_kick(qsym_ctx *c, double dt, double crude_tau)
 int qsym_apply_kepler(qsym_ctx *c, double dt)
 {
     if (!c) return QSYM_EINVAL;
+    if (c->p.kepler_mode == 2 && !c->guess_loaded)
+        return fail(c, QSYM_EINVAL, "kepler_mode 2 needs weights (qsym_set_guess)");
     enter(c);
     HIPCHK(c, run_apply(c, 0.0, dt, 0, 1, 0, 1, c->stream, P_APPLY1, 0));
     leave(c);

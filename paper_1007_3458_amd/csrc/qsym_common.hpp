@@ -14,7 +14,6 @@ constexpr int kHist = 32;          // Kepler iteration histogram bins
 constexpr int kSMax = 64;          // largest j-split of one system
 constexpr int kSetsThreads = 256;  // workgroup of the set-partition kernel
 constexpr int kHermThreads = 512;  // workgroup of the Hermite kernel
-constexpr int kMlpParams = 1249;   // 4->32->32->1 network
 constexpr double kPi = 3.14159265358979323846;
 
 // counters / status word in device memory (unsigned 64-bit for atomics)
@@ -81,7 +80,7 @@ struct Dev {
     unsigned long long *ctr;                    // counters and status
     double *epart;                              // energy partials per item
     double *E;                                  // energies per system
-    float *mlp;                                 // learned-guess weights + scalers
+    float *guess;                               // learned Kepler start: weights + scalers
 };
 
 }  // namespace qsym

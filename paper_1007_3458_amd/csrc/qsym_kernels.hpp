@@ -7,6 +7,7 @@
 // test, r_crit) use plain IEEE +, -, *, /, sqrt in a fixed order.
 #pragma once
 #include "qsym_common.hpp"
+#include "qsym_kepler.hpp"
 
 namespace qsym {
 
@@ -463,165 +464,6 @@ __device__ __forceinline__ void sum_partials(const Dev &d, const int *sysS, int 
 }
 
 // ------------------------------------------------------------------------
-// Appendix A: Stumpff functions and the universal-variable Kepler advance
-// ------------------------------------------------------------------------
-__device__ __forceinline__ void stumpff(double y, double &C, double &S)
-{
-    if (fabs(y) < 1.0) {
-        // C = sum_k (-y)^k/(2k+2)!, S = sum_k (-y)^k/(2k+3)!, Horner, k <= 13
-        constexpr double c[14] = {
-            1.0 / 2.0, 1.0 / 24.0, 1.0 / 720.0, 1.0 / 40320.0, 1.0 / 3628800.0,
-            1.0 / 479001600.0, 1.0 / 87178291200.0, 1.0 / 20922789888000.0,
-            1.0 / 6402373705728000.0, 1.0 / 2432902008176640000.0,
-            1.0 / 1.1240007277776077e21, 1.0 / 6.204484017332394e23,
-            1.0 / 4.0329146112660565e26, 1.0 / 3.0488834461171387e29};
-        constexpr double s[14] = {
-            1.0 / 6.0, 1.0 / 120.0, 1.0 / 5040.0, 1.0 / 362880.0, 1.0 / 39916800.0,
-            1.0 / 6227020800.0, 1.0 / 1307674368000.0, 1.0 / 355687428096000.0,
-            1.0 / 121645100408832000.0, 1.0 / 5.109094217170944e19,
-            1.0 / 2.585201673888498e22, 1.0 / 1.5511210043330986e25,
-            1.0 / 1.0888869450418352e28, 1.0 / 8.841761993739702e30};
-        const double w = -y;
-        double cc = c[13], ss = s[13];
-#pragma unroll
-        for (int k = 12; k >= 0; --k) {
-            cc = c[k] + w * cc;
-            ss = s[k] + w * ss;
-        }
-        C = cc;
-        S = ss;
-    } else if (y > 0.0) {
-        const double sy = sqrt(y);
-        C = (1.0 - cos(sy)) / y;
-        S = (sy - sin(sy)) / (y * sy);
-    } else {
-        const double sy = sqrt(-y);
-        C = (cosh(sy) - 1.0) / (-y);
-        S = (sinh(sy) - sy) / ((-y) * sy);
-    }
-}
-
-constexpr int kKeplerCap = 30;
-constexpr double kKeplerTol = 1e-14;
-
-// iterate to |dx| <= 1e-14 |x| (Laguerre n = 5, or Newton); returns 1 when
-// converged, adds the iterations to *count
-__device__ int kepler_iterate(double smu, double r0, double rv, double alpha, double dt,
-                              int laguerre, double &x, int &count)
-{
-    const double b = 1.0 - r0 * alpha;
-    for (int it = 1; it <= kKeplerCap; ++it) {
-        const double z = alpha * x * x;
-        double C, S;
-        stumpff(z, C, S);
-        const double F = rv * x * x * C / smu + b * x * x * x * S + r0 * x - smu * dt;
-        const double Fp = rv * x * (1.0 - z * S) / smu + b * x * x * C + r0;
-        double dx;
-        if (laguerre) {
-            const double Fpp = rv * (1.0 - z * C) / smu + b * x * (1.0 - z * S);
-            const double nl = 5.0;
-            const double rad =
-                sqrt(fabs((nl - 1.0) * (nl - 1.0) * Fp * Fp - nl * (nl - 1.0) * F * Fpp));
-            dx = nl * F / (Fp + (Fp >= 0.0 ? rad : -rad));
-        } else {
-            dx = F / Fp;
-        }
-        x = x - dx;
-        if (fabs(dx) <= kKeplerTol * fabs(x)) {
-            count += it;
-            return 1;
-        }
-    }
-    count += kKeplerCap;
-    return 0;
-}
-
-// learned first guess of the universal anomaly (form c): features
-// (|r0|, r0.v0, alpha, dt) standardised, 4->32->32->1 tanh network in FP32,
-// target standardised; weights laid out W1[32][4] b1[32] W2[32][32] b2[32]
-// W3[32] b3, then 10 scalers (feature means[4], scales[4], target mean,
-// target scale).
-__device__ float mlp_guess(const float *w, float f0, float f1, float f2, float f3)
-{
-    const float *W1 = w, *b1 = w + 128, *W2 = w + 160, *b2 = w + 1184, *W3 = w + 1216;
-    const float b3 = w[1248];
-    const float *sc = w + kMlpParams;
-    const float in[4] = {(f0 - sc[0]) / sc[4], (f1 - sc[1]) / sc[5], (f2 - sc[2]) / sc[6],
-                         (f3 - sc[3]) / sc[7]};
-    float h1[32];
-#pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        float a = b1[k];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) a = fmaf(W1[4 * k + c], in[c], a);
-        h1[k] = tanhf(a);
-    }
-    float out = b3;
-#pragma unroll 4
-    for (int k = 0; k < 32; ++k) {
-        float a = b2[k];
-#pragma unroll
-        for (int c = 0; c < 32; ++c) a = fmaf(W2[32 * k + c], h1[c], a);
-        out = fmaf(W3[k], tanhf(a), out);
-    }
-    return out * sc[9] + sc[8];
-}
-
-// Advance one body by dt about mu (Appendix A); returns iterations, sets
-// *fail when every start reached the cap.
-__device__ int kepler_advance(double mu, int mode, const float *mlp, double dt, double &x,
-                              double &y, double &z, double &vx, double &vy, double &vz, int &fail)
-{
-    fail = 0;
-    if (dt == 0.0) return 0;
-    const double r0 = sqrt(x * x + y * y + z * z);
-    const double vv = vx * vx + vy * vy + vz * vz;
-    const double rv = x * vx + y * vy + z * vz;
-    const double smu = sqrt(mu);
-    const double alpha = 2.0 / r0 - vv / mu;
-    const double guess = smu * dt / r0;
-    int count = 0, ok;
-    double xu;
-    if (mode == 0) {
-        xu = r0;
-        ok = kepler_iterate(smu, r0, rv, alpha, dt, 1, xu, count);
-        if (!ok) {
-            xu = guess;
-            ok = kepler_iterate(smu, r0, rv, alpha, dt, 1, xu, count);
-        }
-    } else {
-        xu = guess;
-        if (mode == 2) {
-            const double g = (double)mlp_guess(mlp, (float)r0, (float)rv, (float)alpha, (float)dt);
-            if (isfinite(g)) xu = g;
-        }
-        ok = kepler_iterate(smu, r0, rv, alpha, dt, 0, xu, count);
-        if (!ok) {
-            xu = guess;
-            ok = kepler_iterate(smu, r0, rv, alpha, dt, 1, xu, count);
-        }
-    }
-    fail = !ok;
-    const double zz = alpha * xu * xu;
-    double C, S;
-    stumpff(zz, C, S);
-    const double f = 1.0 - xu * xu * C / r0;
-    const double g = dt - xu * xu * xu * S / smu;
-    const double nx = f * x + g * vx, ny = f * y + g * vy, nz = f * z + g * vz;
-    const double r = sqrt(nx * nx + ny * ny + nz * nz);
-    const double fd = smu * xu * (zz * S - 1.0) / (r * r0);
-    const double gd = 1.0 - xu * xu * C / r;
-    const double nvx = fd * x + gd * vx, nvy = fd * y + gd * vy, nvz = fd * z + gd * vz;
-    x = nx;
-    y = ny;
-    z = nz;
-    vx = nvx;
-    vy = nvy;
-    vz = nvz;
-    return count;
-}
-
-// ------------------------------------------------------------------------
 // First kick applied (v += dt a), state snapshot (q0, v0), then E_Kep(tau)
 // of every body (Sec. 2.3 steps 2-3).  mode < 0 skips the kick part,
 // kick_only skips the Kepler part (operator-level entry points).
@@ -675,7 +517,7 @@ __global__ __launch_bounds__(BS) void k_apply_kepler(ApplyArgs a)
         }
         if (a.do_kep) {
             int fail;
-            const int it = kepler_advance(a.G * d.sys_m0[s], a.kepler_mode, d.mlp, a.dt_kep, x, y,
+            const int it = kepler_advance(a.G * d.sys_m0[s], a.kepler_mode, d.guess, a.dt_kep, x, y,
                                           z, vx, vy, vz, fail);
             atomicAdd(&hist[it < kHist ? it : kHist - 1], 1u);
             atomicMax(&kmax, (unsigned)it);

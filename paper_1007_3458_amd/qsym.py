@@ -104,7 +104,29 @@ SIGNATURES = {
     "qsym_get_kick_shape": (C.c_int, [C.c_void_p, C.c_int32, _ip, _ip, _lp, _ip]),
     "qsym_autotune": (C.c_int, [C.c_void_p, C.c_double, _dp]),
     "qsym_profile": (C.c_int, [C.c_void_p, C.c_int32]),
+    "qsym_set_guess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "qsym_kepler_solve": (C.c_int, [C.c_double, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "qsym_kepler_guess": (C.c_int, [C.c_double, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]),
+    "qsym_guess_trainer_create": (C.c_int, [C.c_int64, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "qsym_guess_trainer_destroy": (None, [C.c_void_p]),
+    "qsym_guess_trainer_error": (C.c_char_p, [C.c_void_p]),
+    "qsym_guess_reset": (C.c_int, [C.c_void_p]),
+    "qsym_guess_prepare": (C.c_int, [C.c_void_p, C.c_double, C.c_int64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_int64]),
+    "qsym_guess_fit_scalers": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                         C.c_void_p]),
+    "qsym_guess_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                  C.c_void_p, _dp]),
+    "qsym_guess_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                  C.c_double, C.c_double]),
+    "qsym_guess_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                   C.c_int64, C.c_int32, C.c_double, C.c_double, _dp]),
 }
+
+GUESS_PARAMS = 1249
+GUESS_WEIGHTS = 1259
 
 
 def lib():
@@ -298,6 +320,22 @@ class Context:
     def profile(self, enable=True):
         self._c(lib().qsym_profile(self.ctx, 1 if enable else 0))
 
+    def set_guess(self, weights):
+        """Weights of the learned Kepler start (kepler_mode 2): a host array
+        or a device tensor of GUESS_WEIGHTS float32 values."""
+        torch = _torch()
+        if isinstance(weights, torch.Tensor):
+            if weights.dtype != torch.float32 or weights.numel() != GUESS_WEIGHTS or \
+                    not weights.is_cuda or not weights.is_contiguous():
+                raise ValueError("weights: contiguous float32 device tensor of 1259 values")
+            torch.cuda.current_stream(weights.device).synchronize()
+            self._c(lib().qsym_set_guess(self.ctx, C.c_void_p(weights.data_ptr()), QSYM_DEVICE))
+        else:
+            w = np.ascontiguousarray(weights, dtype=np.float32).ravel()
+            if w.size != GUESS_WEIGHTS:
+                raise ValueError("weights must hold 1259 values")
+            self._c(lib().qsym_set_guess(self.ctx, C.c_void_p(w.ctypes.data), QSYM_HOST))
+
 
 def fine_test(params: Params, m0, tau, m, h, A, q0, v0, q1, v1, pairs, device="cuda:0"):
     """Standalone fine sweep (Sec. 2.4) on the GPU; returns flags, lhs, rhs."""
@@ -333,3 +371,159 @@ def fine_test(params: Params, m0, tau, m, h, A, q0, v0, q1, v1, pairs, device="c
     if rc != 0:
         raise QsymError(rc, "qsym_fine_test failed")
     return (flags.cpu().numpy()[:k].astype(bool), lhs.cpu().numpy()[:k], rhs.cpu().numpy()[:k])
+
+
+# ---------------------------------------------------------------------------
+# stand-alone Kepler solves and the learned start
+# ---------------------------------------------------------------------------
+def state_tensor(q, v, device="cuda:0"):
+    """(n, 3) positions and velocities -> device float64 SoA [6][n]."""
+    torch = _torch()
+    q = np.asarray(q, dtype=np.float64).reshape(-1, 3)
+    v = np.asarray(v, dtype=np.float64).reshape(-1, 3)
+    if q.shape != v.shape:
+        raise ValueError("q and v must have the same shape")
+    return torch.from_numpy(np.ascontiguousarray(np.concatenate([q.T, v.T]))).to(device)
+
+
+def _dev_f64(a, n, device):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        if a.dtype != torch.float64 or a.numel() != n or not a.is_cuda or not a.is_contiguous():
+            raise ValueError("expected a contiguous float64 device tensor of n values")
+        return a
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), (n,)))
+    return torch.from_numpy(a).to(device)
+
+
+def _weights_dev(w, device):
+    torch = _torch()
+    if isinstance(w, torch.Tensor):
+        if w.dtype != torch.float32 or w.numel() != GUESS_WEIGHTS or not w.is_cuda \
+                or not w.is_contiguous():
+            raise ValueError("weights: contiguous float32 device tensor of 1259 values")
+        return w
+    w = np.ascontiguousarray(w, dtype=np.float32).ravel()
+    if w.size != GUESS_WEIGHTS:
+        raise ValueError("weights must hold 1259 values")
+    return torch.from_numpy(w).to(device)
+
+
+def kepler_solve(mu, state, dt, mode=0, weights=None, device="cuda:0"):
+    """Universal anomalies (Appendix A) of the bodies of a device SoA state
+    [6][n] with per-body steps; returns device tensors (x, iters), iters < 0
+    where every start reached the iteration cap."""
+    torch = _torch()
+    n = state.shape[1]
+    if state.dtype != torch.float64 or state.shape[0] != 6 or not state.is_contiguous():
+        raise ValueError("state: contiguous float64 device tensor [6][n]")
+    dt_t = _dev_f64(dt, n, state.device)
+    w = _weights_dev(weights, state.device) if weights is not None else None
+    if mode == 2 and w is None:
+        raise ValueError("mode 2 needs weights")
+    x = torch.empty(max(n, 1), dtype=torch.float64, device=state.device)
+    it = torch.empty(max(n, 1), dtype=torch.int32, device=state.device)
+    st = torch.cuda.current_stream(state.device)
+    rc = lib().qsym_kepler_solve(float(mu), n, C.c_void_p(state.data_ptr()),
+                                 C.c_void_p(dt_t.data_ptr()), int(mode),
+                                 C.c_void_p(w.data_ptr() if w is not None else 0),
+                                 C.c_void_p(x.data_ptr()), C.c_void_p(it.data_ptr()),
+                                 C.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise QsymError(rc, "qsym_kepler_solve failed")
+    return x[:n], it[:n]
+
+
+def kepler_guess(mu, state, dt, weights, device="cuda:0"):
+    """The learned start alone (device tensor [n])."""
+    torch = _torch()
+    n = state.shape[1]
+    dt_t = _dev_f64(dt, n, state.device)
+    w = _weights_dev(weights, state.device)
+    x = torch.empty(max(n, 1), dtype=torch.float64, device=state.device)
+    st = torch.cuda.current_stream(state.device)
+    rc = lib().qsym_kepler_guess(float(mu), n, C.c_void_p(state.data_ptr()),
+                                 C.c_void_p(dt_t.data_ptr()), C.c_void_p(w.data_ptr()),
+                                 C.c_void_p(x.data_ptr()), C.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise QsymError(rc, "qsym_kepler_guess failed")
+    return x[:n]
+
+
+class GuessTrainer:
+    """Device-side training of the learned Kepler start (forward, backward
+    and Adam kernels of the library) on torch's current stream."""
+
+    def __init__(self, max_batch: int, device="cuda:0"):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.tr = C.c_void_p()
+        rc = lib().qsym_guess_trainer_create(int(max_batch), C.c_void_p(self.stream.cuda_stream),
+                                             C.byref(self.tr))
+        if rc != 0:
+            raise QsymError(rc, "qsym_guess_trainer_create failed")
+        self.max_batch = int(max_batch)
+
+    def _c(self, rc, what):
+        if rc != 0:
+            msg = lib().qsym_guess_trainer_error(self.tr)
+            raise QsymError(rc, f"{what}: " + (msg.decode() if msg else ""))
+
+    def close(self):
+        if self.tr:
+            lib().qsym_guess_trainer_destroy(self.tr)
+            self.tr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prepare(self, mu, state, dt, x_root=None):
+        """Features and targets [5][n] (device float32) of solved bodies."""
+        torch = _torch()
+        n = state.shape[1]
+        dt_t = _dev_f64(dt, n, state.device)
+        xr = _dev_f64(x_root, n, state.device) if x_root is not None else None
+        feat = torch.empty((5, max(n, 1)), dtype=torch.float32, device=state.device)
+        self._c(lib().qsym_guess_prepare(self.tr, float(mu), n, C.c_void_p(state.data_ptr()),
+                                         C.c_void_p(dt_t.data_ptr()),
+                                         C.c_void_p(xr.data_ptr() if xr is not None else 0),
+                                         C.c_void_p(feat.data_ptr()), feat.shape[1]),
+                "guess_prepare")
+        return feat
+
+    def fit_scalers(self, feat, weights, n=None):
+        n = feat.shape[1] if n is None else n
+        self._c(lib().qsym_guess_fit_scalers(self.tr, C.c_void_p(feat.data_ptr()), feat.shape[1],
+                                             n, C.c_void_p(weights.data_ptr())), "fit_scalers")
+
+    def grad(self, weights, feat, n=None, offset=0):
+        """(dL/dw device [1249], L) over samples [offset, offset + n)."""
+        torch = _torch()
+        n = feat.shape[1] - offset if n is None else n
+        g = torch.empty(GUESS_PARAMS, dtype=torch.float32, device=self.device)
+        loss = C.c_double()
+        self._c(lib().qsym_guess_grad(self.tr, C.c_void_p(weights.data_ptr()),
+                                      C.c_void_p(feat.data_ptr() + 4 * offset), feat.shape[1], n,
+                                      C.c_void_p(g.data_ptr()), C.byref(loss)), "guess_grad")
+        return g, loss.value
+
+    def adam(self, weights, grad, lr, b1=0.9, b2=0.999, eps=1e-8):
+        self._c(lib().qsym_guess_adam(self.tr, C.c_void_p(weights.data_ptr()),
+                                      C.c_void_p(grad.data_ptr()), lr, b1, b2, eps), "guess_adam")
+
+    def reset(self):
+        self._c(lib().qsym_guess_reset(self.tr), "guess_reset")
+
+    def train(self, weights, feat, batch, epochs, lr, lr_final=0.0, n=None):
+        """Mini-batch Adam over the samples; returns each epoch's mean loss."""
+        n = feat.shape[1] if n is None else n
+        curve = np.zeros(epochs)
+        self._c(lib().qsym_guess_train(self.tr, C.c_void_p(weights.data_ptr()),
+                                       C.c_void_p(feat.data_ptr()), feat.shape[1], n, int(batch),
+                                       int(epochs), float(lr), float(lr_final),
+                                       curve.ctypes.data_as(_dp)), "guess_train")
+        return curve

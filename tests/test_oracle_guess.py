@@ -191,3 +191,64 @@ def test_training_lowers_loss():
     w[:NP] = wp
     l1 = oracle.guess_loss_grad(w, f, y, want_grad=False)
     assert l1 < 0.01 * l0
+
+
+def _orbits(n, seed):
+    """Bound orbits (e in [0.05, 0.95]) and unbound ones (1.05 to 2 times the
+    escape speed) with positive and negative steps up to half a period."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    q, u, dt = inputs.kepler_train(n, seed, e_hi=0.95)
+    out = []
+    for i in range(n):
+        out.append((q[i], u[i], dt[i] * (1 if i % 2 else -1)))
+        r = rng.normal(size=3)
+        r *= rng.uniform(0.5, 20) / np.linalg.norm(r)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        vesc = np.sqrt(2.0 / np.linalg.norm(r))
+        out.append((r, d * vesc * rng.uniform(1.05, 2.0), rng.uniform(0.01, 2.0)))
+    return out
+
+
+def test_root_ratio_lies_in_admissible_range():
+    """x / (sqrt(mu) dt / r0) = r0 <1/r> lies in [r0/r_max, r0/q]: every
+    converged root is an admissible start; scaled, negated or non-finite
+    values are not."""
+    for q0, u0, h in _orbits(200, 71):
+        f, xp, T = oracle.guess_features(1.0, q0, u0, h)
+        if abs(f[2] - 2.0) < 1e-3:    # nearly at rest: h -> 0, the range is unbounded
+            continue
+        x, it, fail = oracle.kepler_root(1.0, q0, u0, h, 0)
+        assert fail == 0
+        if abs(x / xp - 1.0) > 1e-9:
+            assert oracle.start_admissible(1.0, q0, u0, h, x)
+        assert not oracle.start_admissible(1.0, q0, u0, h, 1e6 * x)
+        assert not oracle.start_admissible(1.0, q0, u0, h, -x)
+        assert not oracle.start_admissible(1.0, q0, u0, h, float("nan"))
+
+
+def test_universal_anomaly_is_time_integral_of_inverse_radius():
+    """dx/dt = sqrt(mu)/r (the relation behind the admissible range):
+    Simpson's rule over exact Kepler positions reproduces the root."""
+    for q0, u0, h in _orbits(4, 73)[:6]:
+        ts = np.linspace(0.0, h, 2001)
+        inv_r = []
+        for t in ts:
+            q1, _, _, fails = oracle.kepler(1.0, q0[None], u0[None], t)
+            assert fails == 0
+            inv_r.append(1.0 / np.linalg.norm(q1[0]))
+        inv_r = np.array(inv_r)
+        dtq = ts[1] - ts[0]
+        simpson = dtq / 3 * (inv_r[0] + inv_r[-1] + 4 * inv_r[1:-1:2].sum() + 2 * inv_r[2:-1:2].sum())
+        x, _, _ = oracle.kepler_root(1.0, q0, u0, h, 0)
+        assert simpson == pytest.approx(x, rel=1e-8)
+
+
+def test_inadmissible_start_falls_back_to_first_order_guess():
+    """A wild start (here 1e30 times the root) gives the same root as the
+    first-order guess, in the same number of iterations."""
+    q, u, dt = inputs.kepler_train(200, 79)
+    x1, it1, _ = oracle.kepler_roots(1.0, q, u, dt, 1)
+    x2, it2, f2 = oracle.kepler_roots(1.0, q, u, dt, 2, 1e30 * x1)
+    assert f2 == 0
+    assert np.array_equal(x1, x2) and np.array_equal(it1, it2)
