@@ -15,7 +15,11 @@ region; graph-replay throughput is reported beside it.
 
 Other workloads: --workload disk128k (131076 bodies; with --precision 1 the
 FP32 pair-term form, compared with the FP64 path on the same initial
-conditions), --workload batch (512 independent systems of 64..4096 bodies).
+conditions), --workload batch (512 independent systems of 64..4096 bodies),
+--workload learned (the learned Kepler start: trained here on the GPU from
+1e6 library solves, then the Kepler solve of 1,048,576 test bodies + a
+65,540-body disk timed from each start, and whole steps of the disk with
+the learned start against the first-order start).
 """
 from __future__ import annotations
 
@@ -48,6 +52,8 @@ def workload(name):
         return [inputs.small()], "4 planets + 100 planetesimals, tau=0.05"
     if name == "batch":
         return inputs.batch(), "512 systems, N~logU[64,4096]: 1 Jupiter-mass planet at 5.2 + planetesimals (m=1e-8, a~U[3,10]), tau=0.05, encounters on"
+    if name == "learned":
+        return [inputs.learned_workload(n_test=0)], "4 planets + 65536 planetesimals (m=1e-8, disk16k distributions, seed 6), tau=0.05, Kepler solve from the learned start (kepler_mode 2)"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -103,9 +109,9 @@ def cpu_baseline(systems, tau, seconds):
             "steps_per_s": k / dt, "cpu": model}
 
 
-def make_context(systems, precision, tau, force_tune):
+def make_context(systems, precision, tau, force_tune, kepler_mode=0, guess=None):
     from paper_1007_3458_amd import qsym
-    ctx = qsym.Context(systems, precision=precision)
+    ctx = qsym.Context(systems, precision=precision, kepler_mode=kepler_mode, guess=guess)
     tune_us = None
     if force_tune or ctx.tuned is None:
         tune_us = ctx.autotune(tau)
@@ -162,12 +168,71 @@ def kick_accels(ctx, systems):
     return a
 
 
+def _time_launches(fn, reps):
+    """Average device time of `fn` (launches on torch's current stream)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        out = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps, out
+
+
+def learned_report(reps=20):
+    """Train the learned start on the GPU (1e6 library Laguerre solves), then
+    time the Kepler solve of the 1,048,576 test bodies + 65,540-body disk
+    from each start; returns (weights, report)."""
+    import torch
+    from paper_1007_3458_amd import inputs, learned_guess, qsym
+    R = learned_guess.RECIPE
+    q, v, dt = inputs.kepler_train(R["n"], R["seed"])
+    w, curve, info = learned_guess.train(q, v, dt, batch=R["batch"], epochs=R["epochs"],
+                                         lr=R["lr"], lr_final=R["lr_final"],
+                                         init_seed=R["init_seed"])
+    s = inputs.learned_workload()
+    st = qsym.state_tensor(s.q, s.v)
+    n = st.shape[1]
+    dtt = torch.full((n,), 0.05, dtype=torch.float64, device=st.device)
+    modes = {}
+    roots = {}
+    for mode, name in ((0, "laguerre_from_r0"), (1, "newton_first_order"), (2, "newton_learned")):
+        us, (x, it) = _time_launches(
+            lambda: qsym.kepler_solve(1.0, st, dtt, mode, w if mode == 2 else None), reps)
+        itn = it.cpu().numpy()
+        roots[mode] = x.cpu().numpy()
+        nw = n // 64 * 64
+        modes[name] = {"kernel_us": us, "solves_per_s": n / (us * 1e-6),
+                       "iters_mean": float(itn.mean()), "iters_max": int(np.abs(itn).max()),
+                       "wave_max_mean": float(np.abs(itn[:nw]).reshape(-1, 64).max(1).mean()),
+                       "capped": int((itn < 0).sum())}
+    us_g, _ = _time_launches(lambda: qsym.kepler_guess(1.0, st, dtt, w), reps)
+    ref = roots[1]
+    deltas = {name: float(np.max(np.abs(roots[m] - ref) / np.abs(ref)))
+              for m, name in ((0, "laguerre_vs_newton"), (2, "learned_vs_newton"))}
+    return w, {
+        "kepler_bodies": n, "dt": 0.05,
+        "kepler_test": "1048576 massless bodies a~U[0.5,50], e~U[0,0.9], i~U[0,0.1] (seed 6) "
+                       "after 4 planets + 65536 planetesimals",
+        "modes": modes, "guess_only_us": us_g, "root_rel_delta_max": deltas,
+        "training": {"samples": info["n"], "labels": info["labels"], "epochs": R["epochs"],
+                     "batch": R["batch"], "lr": [R["lr"], R["lr_final"]],
+                     "train_s": info["train_s"], "loss_first_epoch": float(curve[0]),
+                     "loss_last_epoch": float(curve[-1]),
+                     "curve": [float(c) for c in curve]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="disk16k", choices=["disk16k", "disk128k", "small", "batch"])
+    ap.add_argument("--workload", default="disk16k", choices=["disk16k", "disk128k", "small", "batch", "learned"])
     ap.add_argument("--precision", type=int, default=0, choices=[0, 1])
     ap.add_argument("--tau", type=float, default=0.05)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -177,13 +242,27 @@ def main():
     ap.add_argument("--no-graph-pass", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="precision 1: skip the FP64 run on the same initial conditions")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 3 plain device-to-device copies of MIB MiB (the reference "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        nb = args.calibrate_copy << 20
+        a = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nb, "copy_bytes_written": nb, "copies": 3}))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build runs one process on one MI355X "
               "(the multi-GPU design is described, not built)", file=sys.stderr)
         sys.exit(2)
-    defaults = {"disk16k": (200, 20), "disk128k": (100, 5), "small": (1000, 50), "batch": (100, 10)}
+    defaults = {"disk16k": (200, 20), "disk128k": (100, 5), "small": (1000, 50), "batch": (100, 10),
+                "learned": (50, 5)}
     steps = args.steps if args.steps is not None else defaults[args.workload][0]
     warmup = args.warmup if args.warmup is not None else defaults[args.workload][1]
 
@@ -193,8 +272,22 @@ def main():
     systems, desc = workload(args.workload)
     ntot = sum(s.n for s in systems)
     npairs = sum(float(s.n) * (s.n - 1) for s in systems)
-    ctx, shape = make_context(systems, args.precision, args.tau, args.autotune)
     extra = {}
+    kepler_mode, guess = 0, None
+    if args.workload == "learned":
+        guess, extra["learned_report"] = learned_report()
+        kepler_mode = 2
+    ctx, shape = make_context(systems, args.precision, args.tau, args.autotune, kepler_mode, guess)
+    if args.workload == "learned" and not args.no_compare:
+        # the same disk from the first-order Newton start
+        ctx1, _ = make_context(systems, args.precision, args.tau, False, 1)
+        r1 = timed_run(ctx1, args.tau, steps, warmup, not args.no_graph_pass)
+        q1, _ = ctx1.get_state()
+        extra["learned_report"]["step_first_order"] = {
+            "value": 2.0 * npairs * steps / r1["T"], "apply+kepler_us": r1["kern"].get("apply+kepler"),
+            "energy_error": float(abs(r1["E1"][0] / r1["E0"][0] - 1.0)),
+            "kepler_iters_total": r1["st"]["kepler_iters"]}
+        ctx1.close()
     if args.precision == 1 and not args.no_compare:
         # accuracy of the FP32 pair terms against the FP64 kick (which is
         # itself checked against the oracle to 1e-13 by the test suite)
@@ -221,6 +314,14 @@ def main():
         pr["energy_error"] = energy_err
         pr["energy_error_ratio_vs_fp64"] = energy_err / pr["fp64_energy_error"] if pr["fp64_energy_error"] else None
         pr["speedup_vs_fp64"] = value / pr["fp64_value"]
+    if "learned_report" in extra and "step_first_order" in extra["learned_report"]:
+        lr_ = extra["learned_report"]
+        q2, _ = ctx.get_state()
+        lr_["step_learned"] = {"value": value, "apply+kepler_us": kern.get("apply+kepler"),
+                               "energy_error": energy_err,
+                               "kepler_iters_total": r["st"]["kepler_iters"]}
+        lr_["step_position_rel_delta_max"] = float(np.max(
+            np.linalg.norm(q2 - q1, axis=1) / np.linalg.norm(q1, axis=1)))
 
     # roofline of the dominant kernel: the kick with the fused crude sweep
     t_kick = kern.get("kick+crude")
@@ -249,7 +350,8 @@ def main():
         "dtype": "f64" if args.precision == 0 else "f32 m/r^3 on f64 separations, f64 elsewhere",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n_bodies": ntot, "n_systems": len(systems),
-                   "tau": args.tau, "precision": args.precision, "kick_shape": shape},
+                   "tau": args.tau, "precision": args.precision, "kepler_mode": kepler_mode,
+                   "kick_shape": shape},
         "energy_error": energy_err,
         "encounters_last_step": r["st"]["n_encounters"],
         "encounters_total": r["st2"]["total_encounters"],

@@ -89,7 +89,7 @@ def _solve_eccentric_anomaly(M: np.ndarray, e: np.ndarray) -> np.ndarray:
     for _ in range(60):
         d = (E - e * np.sin(E) - M) / (1.0 - e * np.cos(E))
         E = E - d
-        if np.max(np.abs(d)) < 1e-15:
+        if d.size == 0 or np.max(np.abs(d)) < 1e-15:
             break
     return E
 

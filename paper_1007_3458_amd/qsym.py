@@ -175,10 +175,12 @@ class Context:
     """
 
     def __init__(self, systems, params: Params | None = None, device="cuda:0", shapes="table",
-                 **kw):
+                 guess="packaged", **kw):
         """shapes="table" starts from the tuned kick shapes recorded for this
         workload signature (paper_1007_3458_amd/tuned_shapes.json) when there
-        is an entry; None keeps the library defaults."""
+        is an entry; None keeps the library defaults.  guess="packaged" loads
+        the packaged learned-start weights when kepler_mode is 2 (None
+        leaves them unset; an array sets those)."""
         torch = _torch()
         if not isinstance(systems, (list, tuple)):
             systems = [systems]
@@ -219,6 +221,11 @@ class Context:
                     sh = e[key]
                     self.set_kick_shape(sh["ipl"], sh["block"], sh["jchunk"], sh["remap"], which=w)
                 self.tuned = e
+        if self.params.kepler_mode == 2 and guess is not None:
+            if isinstance(guess, str) and guess == "packaged":
+                from . import learned_guess
+                guess = learned_guess.load()
+            self.set_guess(guess)
 
     # ---------------------------------------------------------- helpers
     def _check(self, rc, ctx):

@@ -239,9 +239,7 @@ def test_step_with_learned_start_matches_first_order_start(Q, trained):
     s = inputs.small()
     out = {}
     for mode in (1, 2):
-        ctx = Q.Context([s], Q.make_params(kepler_mode=mode))
-        if mode == 2:
-            ctx.set_guess(w)
+        ctx = Q.Context([s], Q.make_params(kepler_mode=mode), guess=w if mode == 2 else None)
         say(f"20 steps kepler_mode {mode}")
         ctx.step(0.05, 20)
         out[mode] = ctx.get_state()
@@ -253,9 +251,11 @@ def test_step_with_learned_start_matches_first_order_start(Q, trained):
 def test_mode2_needs_weights_and_survives_garbage(Q):
     import torch
     s = inputs.small()
-    ctx = Q.Context([s], Q.make_params(kepler_mode=2))
+    ctx = Q.Context([s], Q.make_params(kepler_mode=2), guess=None)
     with pytest.raises(Q.QsymError):
         ctx.step(0.05, 1)
+    ctx.set_guess(np.full(NW, np.nan, np.float32))   # unusable start: first-order guess
+    ctx.step(0.05, 1)
     ctx.close()
     q, u, dt = _train_set(4099, 59, negative=True)
     st = Q.state_tensor(q, u)
@@ -274,3 +274,19 @@ def test_mode2_needs_weights_and_survives_garbage(Q):
         assert np.max(np.abs(a - b) / np.abs(a)) <= 1e-14
         if name == "nan":   # not-finite start -> first-order guess: identical
             assert np.array_equal(a, b) and torch.equal(it1, it2)
+
+
+def test_packaged_weights_gain(Q):
+    """The packaged weights (trained on 1e6 library solves) gain over the
+    first-order start on the test orbits."""
+    import torch
+    from paper_1007_3458_amd import learned_guess
+    w = learned_guess.load()
+    s = inputs.kepler_test(1 << 15, seed=83)
+    st = Q.state_tensor(s.q, s.v)
+    _, it1 = Q.kepler_solve(1.0, st, 0.05, 1)
+    _, it2 = Q.kepler_solve(1.0, st, 0.05, 2, w)
+    torch.cuda.synchronize()
+    a, b = it1.cpu().numpy(), it2.cpu().numpy()
+    say(f"packaged weights: mean {a.mean():.3f} -> {b.mean():.3f}")
+    assert np.all(b > 0) and b.mean() < 0.9 * a.mean()
