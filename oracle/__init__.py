@@ -105,6 +105,7 @@ def lib():
             "orc_guess_loss_grad": (d, [_dp, i64, _dp, _dp, _dp]),
             "orc_adam": (None, [i64, _dp, _dp, _dp, _dp, i64, d, d, d, d]),
             "orc_kepler_roots": (i64, [i64, d, _dp, _dp, _dp, i32, _dp, _dp, _ip]),
+            "orc_step_swapped": (i64, [i64, pp, d, _dp, _dp, _dp, C.POINTER(C.c_int64)]),
             "orc_num_threads": (C.c_int, []),
             "orc_set_threads": (None, [C.c_int]),
         }
@@ -290,6 +291,18 @@ def step(params: Params, tau, m, h, q, v, cand_cap=None, enc_cap=None):
                         _i(pairs), enc_cap, _i(label), C.byref(st))
     ne = min(st.n_encounters, enc_cap)
     return q, v, StepResult(rc, pairs[:ne].copy(), label[:n].copy(), st.as_dict())
+
+
+def step_swapped(params: Params, tau, m, q, v, nsteps=1):
+    """nsteps encounter-free steps with E_Kep and E_Int swapped; returns
+    (q, v, kepler_fails, kepler_iters)."""
+    q = _f64(q, (-1, 3)).copy(); v = _f64(v, (-1, 3)).copy()
+    m = _f64(m)
+    fails, iters = 0, C.c_int64(0)
+    for _ in range(nsteps):
+        fails += lib().orc_step_swapped(q.shape[0], C.byref(params), tau, _d(m), _d(q), _d(v),
+                                        C.byref(iters))
+    return q, v, int(fails), int(iters.value)
 
 
 def num_threads() -> int:

@@ -933,6 +933,36 @@ int orc_step(int64_t n, const orc_params *p, double tau, const double *m, const 
     return rc;
 }
 
+/* ------------------------------------------------------------------ */
+/* Step without the close-encounter search (Sec. 2, after the second-   */
+/* order composition): with no search the Keplerian and interaction     */
+/* operators trade places, so one O(N^2) evaluation serves a step:      */
+/*   E_Dft(tau/2) E_Kep(tau/2) E_Int(tau) E_Kep(tau/2) E_Dft(tau/2)     */
+/* (the paper states the swap without writing the product out; this is */
+/* the symmetric second-order arrangement of the same three operators). */
+/* Returns the number of Kepler solves that hit the cap; iteration      */
+/* counts summed into *kepler_iters when not NULL.                      */
+/* ------------------------------------------------------------------ */
+int64_t orc_step_swapped(int64_t n, const orc_params *p, double tau, const double *m, double *q,
+                         double *v, int64_t *kepler_iters)
+{
+    double mu = p->G * p->m0;
+    double *qt = malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double *vt = malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    int32_t *it = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t fails = 0, iters = 0;
+    orc_drift(n, p->m0, m, v, q, tau / 2.0);
+    fails += orc_kepler_all(n, mu, q, v, tau / 2.0, p->kepler_mode, qt, vt, it);
+    for (int64_t i = 0; i < n; ++i) iters += it[i];
+    orc_kick(n, p->G, m, qt, vt, tau);
+    fails += orc_kepler_all(n, mu, qt, vt, tau / 2.0, p->kepler_mode, q, v, it);
+    for (int64_t i = 0; i < n; ++i) iters += it[i];
+    orc_drift(n, p->m0, m, v, q, tau / 2.0);
+    if (kepler_iters) *kepler_iters += iters;
+    free(qt); free(vt); free(it);
+    return fails;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
