@@ -78,20 +78,28 @@ def measured_traffic(name, prec):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(systems, tau, seconds):
+def cpu_baseline(systems, tau, seconds, swapped=False):
     """The oracle (as it stands) on the host cores, a bounded sample of steps."""
     import oracle
     oracle.build()
     p = oracle.make_params()
     s = max(systems, key=lambda x: x.n)
+
+    def one(q, v):
+        if swapped:
+            q, v, _, _ = oracle.step_swapped(p, tau, s.m, q, v)
+            return q, v
+        q, v, _ = oracle.step(p, tau, s.m, s.h, q, v)
+        return q, v
+
     q, v = s.q, s.v
     t0 = time.perf_counter()
-    q, v, _ = oracle.step(p, tau, s.m, s.h, q, v)
-    one = time.perf_counter() - t0
-    k = max(1, min(200, int(seconds / max(one, 1e-6))))
+    q, v = one(q, v)
+    first = time.perf_counter() - t0
+    k = max(1, min(200, int(seconds / max(first, 1e-6))))
     t0 = time.perf_counter()
     for _ in range(k):
-        q, v, _ = oracle.step(p, tau, s.m, s.h, q, v)
+        q, v = one(q, v)
     dt = time.perf_counter() - t0
     n = s.n
     model = ""
@@ -104,18 +112,20 @@ def cpu_baseline(systems, tau, seconds):
     except OSError:
         pass
     cores = oracle.num_threads()
-    out = {"value": 2.0 * n * (n - 1) * k / dt, "unit": "pair-interactions/s",
+    kicks = 1.0 if swapped else 2.0
+    kind = "swapped encounter-free" if swapped else "whole hybrid"
+    out = {"value": kicks * n * (n - 1) * k / dt, "unit": "pair-interactions/s",
            "cores": cores, "kind": "oracle",
-           "sample": f"{k} whole hybrid steps of the largest system ({n} bodies) after 1 untimed step",
+           "sample": f"{k} {kind} steps of the largest system ({n} bodies) after 1 untimed step",
            "steps_per_s": k / dt, "cpu": model}
     # one thread, one step, when that fits the same time budget
     if dt / k * cores <= seconds:
         oracle.set_threads(1)
         t0 = time.perf_counter()
-        q, v, _ = oracle.step(p, tau, s.m, s.h, q, v)
+        q, v = one(q, v)
         d1 = time.perf_counter() - t0
         oracle.set_threads(cores)
-        out["single_thread"] = {"value": 2.0 * n * (n - 1) / d1, "steps": 1}
+        out["single_thread"] = {"value": kicks * n * (n - 1) / d1, "steps": 1}
     return out
 
 
@@ -131,13 +141,14 @@ def make_context(systems, precision, tau, force_tune, kepler_mode=0, guess=None)
     return ctx, shape
 
 
-def timed_run(ctx, tau, steps, warmup, graph_pass, checkpoints=10):
+def timed_run(ctx, tau, steps, warmup, graph_pass, checkpoints=10, swapped=False):
     """Warm-up, then `steps` profiled steps (HIP events per kernel) in
     `checkpoints` segments with the energy evaluated between them (outside
     the timed time); returns timings, energies and counters."""
     import torch
     from paper_1007_3458_amd import qsym
-    ctx.step(tau, warmup)
+    stepper = ctx.step_swapped if swapped else ctx.step
+    stepper(tau, warmup)
     ctx.sync()
     E0 = ctx.energy()
     ctx.profile(True)
@@ -147,7 +158,7 @@ def timed_run(ctx, tau, steps, warmup, graph_pass, checkpoints=10):
         k = min(seg, steps - done)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx.step(tau, k)
+        stepper(tau, k)
         ctx.sync()
         torch.cuda.synchronize()
         T += time.perf_counter() - t0
@@ -165,7 +176,7 @@ def timed_run(ctx, tau, steps, warmup, graph_pass, checkpoints=10):
     if graph_pass:
         torch.cuda.synchronize()
         g0 = time.perf_counter()
-        ctx.step(tau, steps)
+        stepper(tau, steps)
         ctx.sync()
         torch.cuda.synchronize()
         graph_sps = steps / (time.perf_counter() - g0)
@@ -263,6 +274,8 @@ def main():
     ap.add_argument("--no-graph-pass", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="precision 1: skip the FP64 run on the same initial conditions")
+    ap.add_argument("--swapped", action="store_true",
+                    help="encounter-free steps with E_Kep and E_Int swapped (one kick per step)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device-to-device copies of MIB MiB (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -291,6 +304,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     systems, desc = workload(args.workload)
+    if args.swapped:
+        desc = desc.replace("encounters on", "encounter-free step with E_Kep and E_Int swapped")
     ntot = sum(s.n for s in systems)
     npairs = sum(float(s.n) * (s.n - 1) for s in systems)
     extra = {}
@@ -324,9 +339,10 @@ def main():
             "fp64_value": 2.0 * npairs * steps / r64["T"],
             "fp64_kick_crude_us": r64["kern"].get("kick+crude"), "fp64_kick_us": r64["kern"].get("kick2"),
             "fp64_energy_error": e64, "fp64_kick_shape": shape64}
-    r = timed_run(ctx, args.tau, steps, warmup, not args.no_graph_pass)
+    r = timed_run(ctx, args.tau, steps, warmup, not args.no_graph_pass, swapped=args.swapped)
     T = r["T"]
-    value = 2.0 * npairs * steps / T
+    kicks_per_step = 1.0 if args.swapped else 2.0
+    value = kicks_per_step * npairs * steps / T
     kern = r["kern"]
     energy_err = float(np.max(r["dEmax"]))
     if "precision_report" in extra:
@@ -349,14 +365,15 @@ def main():
             np.linalg.norm(q2 - q1, axis=1) / np.linalg.norm(q1, axis=1)))
 
     # roofline of the dominant kernel: the kick with the fused crude sweep
-    t_kick = kern.get("kick+crude")
-    flops = npairs * FLOP_PAIR + npairs / 2 * FLOP_CRUDE
+    # (the plain kick for the swapped step)
+    t_kick = kern.get("kick2") if args.swapped else kern.get("kick+crude")
+    flops = npairs * FLOP_PAIR + (0 if args.swapped else npairs / 2 * FLOP_CRUDE)
     peak = FP64_PEAK_TFLOPS if args.precision == 0 else FP32_PEAK_TFLOPS
     achieved = flops / (t_kick * 1e-6) / 1e12 if t_kick else None
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": (achieved / peak) if achieved else None,
             "traffic": measured_traffic(args.workload, args.precision),
-            "kernel": "k_kick (E_Int + fused crude sweep)",
+            "kernel": "k_kick (E_Int)" if args.swapped else "k_kick (E_Int + fused crude sweep)",
             "flop_per_launch": flops, "avg_launch_us": t_kick,
             "pairs_per_s_kernel": (npairs / (t_kick * 1e-6)) if t_kick else None}
     out = {
@@ -376,6 +393,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n_bodies": ntot, "n_systems": len(systems),
                    "tau": args.tau, "precision": args.precision, "kepler_mode": kepler_mode,
+                   "step": "swapped E_Kep/E_Int, no encounter search" if args.swapped else "hybrid",
                    "kick_shape": shape},
         "energy_error": energy_err,
         "encounters_last_step": r["st"]["n_encounters"],
@@ -388,7 +406,7 @@ def main():
     }
     out.update(extra)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(systems, args.tau, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(systems, args.tau, args.cpu_seconds, args.swapped)
     out["host"] = platform.node()
     ctx.close()
     print(json.dumps(out), flush=True)

@@ -118,6 +118,15 @@ int qsym_get_state(qsym_ctx *ctx, double *q, double *v, int32_t where);
  * for a given tau captures one step into a HIP graph that is replayed
  * nsteps times.  A negative tau integrates backwards (used with a_E = 0). */
 int qsym_step(qsym_ctx *ctx, double tau, int64_t nsteps);
+/* nsteps encounter-free steps with the Keplerian and interaction operators
+ * swapped (Sec. 2, after the second-order composition: without the
+ * encounter search they may trade places):
+ *   E_Dft(tau/2) E_Kep(tau/2) E_Int(tau) E_Kep(tau/2) E_Dft(tau/2),
+ * one all-pairs evaluation per step instead of two.  No sweeps, sets or
+ * Hermite: close encounters are not treated, so use it only where none
+ * occur.  Same queuing and error behaviour as qsym_step; the encounter
+ * statistics of qsym_stats read 0 after it. */
+int qsym_step_swapped(qsym_ctx *ctx, double tau, int64_t nsteps);
 
 /* Wait for the context's work; return the latched device status as a code. */
 int qsym_sync(qsym_ctx *ctx);

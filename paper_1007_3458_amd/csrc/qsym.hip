@@ -219,10 +219,13 @@ struct qsym_ctx {
     int nitems[2] = {0, 0};
     int grid_kick[2] = {0, 0};
     Tables T;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    double gtau = 0.0;
-    bool gvalid = false;
+    // captured steps: [0] the hybrid step, [1] the encounter-free swapped step
+    struct StepGraph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        double tau = 0.0;
+        bool valid = false;
+    } g[2];
     bool profile = false;
     // profiling: event pairs recorded around launches without waiting; the
     // pending pairs are read (and the events recycled) at the next flush
@@ -366,7 +369,7 @@ int upload_shape(qsym_ctx *c, int which)
     HIPCHK(c, hipMemcpyAsync(c->d.sys_S + (size_t)which * c->nsys, sysS.data(), sizeof(int) * c->nsys,
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->gvalid = false;
+    c->g[0].valid = c->g[1].valid = false;
     return QSYM_OK;
 }
 
@@ -581,6 +584,59 @@ int sync_status(qsym_ctx *c)
     return status_code(c, h[C_STATUS]);
 }
 
+// Encounter-free step with the Keplerian and interaction operators swapped
+// (Sec. 2, after the composition): E_Dft(tau/2) E_Kep(tau/2) E_Int(tau)
+// E_Kep(tau/2) E_Dft(tau/2); one all-pairs kick per step.  The kick and the
+// second Kepler half-step share one pass over the bodies.
+hipError_t enqueue_swapped(qsym_ctx *c, double tau, hipStream_t st)
+{
+    hipError_t e;
+    const double half = tau / 2.0;
+    if ((e = run_drift(c, half, 0, 0.0, 1, st, P_DRIFT)) != hipSuccess) return e;
+    if ((e = run_apply(c, 0.0, half, 0, 1, 0, 0, st, P_APPLY1, 0)) != hipSuccess) return e;
+    if ((e = run_kick(c, 0, 0.0, st, P_KICK2)) != hipSuccess) return e;
+    if ((e = run_apply(c, tau, half, 1, 1, 0, 1, st, P_APPLY2, 0)) != hipSuccess) return e;
+    return run_drift(c, half, 0, 0.0, 0, st, P_DRIFT2, 1);
+}
+
+// nsteps steps of one kind (0 hybrid, 1 swapped): eager launches in
+// profiling mode, else one captured step replayed
+int run_steps(qsym_ctx *c, double tau, int64_t nsteps, int kind)
+{
+    if (!c || nsteps < 0 || !std::isfinite(tau)) return fail(c, QSYM_EINVAL, "step: bad argument");
+    if (c->p.kepler_mode == 2 && !c->guess_loaded)
+        return fail(c, QSYM_EINVAL, "kepler_mode 2 needs weights (qsym_set_guess)");
+    if (nsteps == 0 || c->ntot == 0) return QSYM_OK;
+    auto enqueue = kind == 0 ? enqueue_step : enqueue_swapped;
+    enter(c);
+    if (c->profile) {
+        for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, enqueue(c, tau, c->stream));
+        leave(c);
+        return QSYM_OK;
+    }
+    auto &G = c->g[kind];
+    if (!G.valid || G.tau != tau) {
+        if (G.exec) { hipGraphExecDestroy(G.exec); G.exec = nullptr; }
+        if (G.graph) { hipGraphDestroy(G.graph); G.graph = nullptr; }
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue(c, tau, c->stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return fail(c, QSYM_EHIP, std::string("graph capture: ") +
+                                          hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        G.graph = g;
+        HIPCHK(c, hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+        G.tau = tau;
+        G.valid = true;
+    }
+    for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, hipGraphLaunch(G.exec, c->stream));
+    leave(c);
+    return QSYM_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -699,8 +755,10 @@ void qsym_destroy(qsym_ctx *c)
 {
     if (!c) return;
     if (c->stream) hipStreamSynchronize(c->stream);
-    if (c->gexec) hipGraphExecDestroy(c->gexec);
-    if (c->graph) hipGraphDestroy(c->graph);
+    for (auto &g : c->g) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        if (g.graph) hipGraphDestroy(g.graph);
+    }
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
@@ -753,38 +811,11 @@ int qsym_get_state(qsym_ctx *c, double *q, double *v, int32_t where)
     return sync_status(c);
 }
 
-int qsym_step(qsym_ctx *c, double tau, int64_t nsteps)
+int qsym_step(qsym_ctx *c, double tau, int64_t nsteps) { return run_steps(c, tau, nsteps, 0); }
+
+int qsym_step_swapped(qsym_ctx *c, double tau, int64_t nsteps)
 {
-    if (!c || nsteps < 0 || !std::isfinite(tau)) return fail(c, QSYM_EINVAL, "step: bad argument");
-    if (c->p.kepler_mode == 2 && !c->guess_loaded)
-        return fail(c, QSYM_EINVAL, "kepler_mode 2 needs weights (qsym_set_guess)");
-    if (nsteps == 0 || c->ntot == 0) return QSYM_OK;
-    enter(c);
-    if (c->profile) {
-        for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, enqueue_step(c, tau, c->stream));
-        leave(c);
-        return QSYM_OK;
-    }
-    if (!c->gvalid || c->gtau != tau) {
-        if (c->gexec) { hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
-        if (c->graph) { hipGraphDestroy(c->graph); c->graph = nullptr; }
-        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_step(c, tau, c->stream);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
-        if (e != hipSuccess || e2 != hipSuccess) {
-            if (g) hipGraphDestroy(g);
-            return fail(c, QSYM_EHIP, std::string("graph capture: ") +
-                                          hipGetErrorString(e != hipSuccess ? e : e2));
-        }
-        c->graph = g;
-        HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
-        c->gtau = tau;
-        c->gvalid = true;
-    }
-    for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
-    leave(c);
-    return QSYM_OK;
+    return run_steps(c, tau, nsteps, 1);
 }
 
 int qsym_set_guess(qsym_ctx *c, const float *weights, int32_t where)

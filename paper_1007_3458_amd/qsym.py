@@ -87,6 +87,7 @@ SIGNATURES = {
                                  C.c_int32]),
     "qsym_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "qsym_step": (C.c_int, [C.c_void_p, C.c_double, C.c_int64]),
+    "qsym_step_swapped": (C.c_int, [C.c_void_p, C.c_double, C.c_int64]),
     "qsym_sync": (C.c_int, [C.c_void_p]),
     "qsym_energy": (C.c_int, [C.c_void_p, _dp]),
     "qsym_encounters": (C.c_int, [C.c_void_p, _ip, C.c_int64, _lp, _ip]),
@@ -267,6 +268,10 @@ class Context:
     # ------------------------------------------------------------- steps
     def step(self, tau: float, nsteps: int = 1):
         self._c(lib().qsym_step(self.ctx, float(tau), int(nsteps)))
+
+    def step_swapped(self, tau: float, nsteps: int = 1):
+        """Encounter-free steps with E_Kep and E_Int swapped (one kick per step)."""
+        self._c(lib().qsym_step_swapped(self.ctx, float(tau), int(nsteps)))
 
     def sync(self):
         self._c(lib().qsym_sync(self.ctx))
