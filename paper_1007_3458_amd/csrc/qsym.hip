@@ -379,7 +379,8 @@ hipError_t launch_kick_bs(qsym_ctx *c, int mode, int prec, hipStream_t st)
 {
     const int w = mode ? 1 : 0;
     KickArgs ka{c->d, c->d.items + (size_t)w * c->L.max_items, c->p.G, c->L.cap, c->nitems[w],
-                c->shape[w].remap, c->p.hill_mode, c->p.aE, c->p.crude_safety, c->tau_crude, 1e-200};
+                c->shape[w].remap, c->p.hill_mode, c->p.aE, c->p.crude_safety, c->tau_crude, 1e-200,
+                1.875, 1.5};
     const dim3 g(c->shape[w].remap ? c->grid_kick[w] : std::max(c->nitems[w], 1)), b(BS);
     if (prec == 0) {
         if (mode == 0) hipLaunchKernelGGL((k_kick<BS, IPL, 0, 0>), g, b, 0, st, ka);

@@ -177,6 +177,7 @@ struct KickArgs {
     int hill_mode;     // crude test form
     double aE, cs, tau_abs;
     double r2seed;     // 1e-200, passed at run time so it stays a register operand
+    double c158, c32;  // 15/8 and 3/2 of the r^-3 correction, likewise register operands
 };
 
 // workgroup b of a grid of g (multiple of 8) runs on XCD b % 8; give each
@@ -219,20 +220,20 @@ __device__ __forceinline__ void crude_exact(const KickArgs &ka, int i, int j)
 
 // FP64 pair term (see the header comment of the kick).  r^2 carries a
 // 1e-200 seed (so the own pair gives 0 * finite = 0 and r^2 >= 1e-184 is
-// unchanged); the correction m y0^3 (1 + 3/2 e + 15/8 e^2) is written as
-// ms0 + 3/2 t + 15/8 t e (t = ms0 e) so that each constant is an
-// instruction literal.
+// unchanged); the correction is the factor w = 1 + e (3/2 + 15/8 e), so the
+// term costs 17 VALU instructions: 3 add, 9 fma, 4 mul, 1 rsq.
 __device__ __forceinline__ void pair64(const double4 &pj, double xi, double yi, double zi,
-                                       double seed, double &ax, double &ay, double &az, double &r2)
+                                       double seed, double c158, double c32, double &ax,
+                                       double &ay, double &az, double &r2)
 {
     const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
     r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, seed)));
     const double y0 = __builtin_amdgcn_rsq(r2);
     const double y2 = y0 * y0;
     const double e = fma(-r2, y2, 1.0);
-    const double ms0 = pj.w * (y2 * y0);
-    const double t = ms0 * e;
-    const double ms = fma(t * e, 1.875, fma(t, 1.5, ms0));
+    // r^-3 = y0^3 (1 - e)^(-3/2) = y0^3 (1 + 3/2 e + 15/8 e^2 + O(e^3)), |e| ~ 1e-7
+    const double w = fma(e, fma(e, c158, c32), 1.0);
+    const double ms = (y2 * y0) * (pj.w * w);
     ax = fma(ms, dx, ax);
     ay = fma(ms, dy, ay);
     az = fma(ms, dz, az);
@@ -287,7 +288,7 @@ __device__ __forceinline__ void crude_drain(const KickArgs &ka, const KickItem &
 }
 
 template <int BS, int IPL, int MODE, int PREC>
-__global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_kick(KickArgs ka)
 {
     const Dev &d = ka.d;
     const int tid = threadIdx.x;
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
     if (MODE && tid == 0) qn = 0u;
     const int jend = it.j0 + it.nj;
     const double G = ka.G;
-    const double seed = ka.r2seed;
+    const double seed = ka.r2seed, c158 = ka.c158, c32 = ka.c32;
     int qtile = -1;   // tile whose queue is pending
     for (int jt = it.j0; jt < jend; jt += BS) {
         const int j = jt + tid;
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
                     for (int u = 0; u < IPL; ++u) {
                         double r2;
                         if constexpr (PREC == 0)
-                            pair64(pj, xi[u], yi[u], zi[u], seed, ax[u], ay[u], az[u], r2);
+                            pair64(pj, xi[u], yi[u], zi[u], seed, c158, c32, ax[u], ay[u], az[u], r2);
                         else
                             pair32(pj, mjf, xi[u], yi[u], zi[u], ax[u], ay[u], az[u], r2);
                         if (r2 < th2[u]) {
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(BS) void k_kick(KickArgs ka)
 #pragma unroll
                 for (int u = 0; u < IPL; ++u) {
                     double r2;
-                    pair64(pj, xi[u], yi[u], zi[u], seed, ax[u], ay[u], az[u], r2);
+                    pair64(pj, xi[u], yi[u], zi[u], seed, c158, c32, ax[u], ay[u], az[u], r2);
                 }
             }
         } else {
