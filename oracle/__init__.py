@@ -25,20 +25,22 @@ class Params(C.Structure):
     _fields_ = [("G", C.c_double), ("m0", C.c_double), ("aE", C.c_double), ("aH", C.c_double),
                 ("epsH", C.c_double), ("eta", C.c_double), ("eta_s", C.c_double),
                 ("crude_safety", C.c_double), ("hill_mode", C.c_int32),
-                ("kepler_mode", C.c_int32), ("max_substeps", C.c_int32), ("pad", C.c_int32)]
+                ("kepler_mode", C.c_int32), ("max_substeps", C.c_int32), ("pad", C.c_int32),
+                ("planet_mass", C.c_double)]
 
 
 class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "n_candidates", "n_encounters", "n_sets", "max_set", "substeps", "kepler_iters",
-        "kepler_max", "kepler_fail", "hermite_fail", "cand_overflow")]
+        "kepler_max", "kepler_fail", "hermite_fail", "cand_overflow", "whole_system")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 DEFAULTS = dict(G=1.0, m0=1.0, aE=3.0, aH=1.0, epsH=1e-8, eta=0.02, eta_s=0.01,
-                crude_safety=1.1, hill_mode=0, kepler_mode=0, max_substeps=100000)
+                crude_safety=1.1, hill_mode=0, kepler_mode=0, max_substeps=100000,
+                planet_mass=0.0)
 
 
 def make_params(**kw) -> Params:
@@ -46,7 +48,7 @@ def make_params(**kw) -> Params:
     d.update(kw)
     return Params(d["G"], d["m0"], d["aE"], d["aH"], d["epsH"], d["eta"], d["eta_s"],
                   d["crude_safety"], int(d["hill_mode"]), int(d["kepler_mode"]),
-                  int(d["max_substeps"]), 0)
+                  int(d["max_substeps"]), 0, float(d["planet_mass"]))
 
 
 def build(force: bool = False) -> str:

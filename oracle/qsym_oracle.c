@@ -49,6 +49,10 @@ typedef struct {
     int32_t kepler_mode; /* 0: Laguerre from x=r0, 1: Newton, 2: Newton from a guess */
     int32_t max_substeps;/* Hermite substep cap per set per step          */
     int32_t pad;
+    double planet_mass;  /* > 0: bodies this massive are planets, and a set
+                            holding two of them makes the step integrate
+                            the whole system with the Hermite (Sec. 2.3);
+                            0: off                                         */
 } orc_params;
 
 typedef struct {
@@ -62,6 +66,7 @@ typedef struct {
     int64_t kepler_fail;   /* solves that hit the iteration cap        */
     int64_t hermite_fail;  /* sets that hit the substep cap            */
     int64_t cand_overflow; /* candidates beyond the caller's capacity  */
+    int64_t whole_system;  /* 1 when the step ran the whole-system Hermite */
 } orc_stats;
 
 #define ORC_KEPLER_CAP 30
@@ -877,6 +882,26 @@ int orc_step(int64_t n, const orc_params *p, double tau, const double *m, const 
     }
     s.n_encounters = ne;
     s.n_sets = orc_sets(n, ne, enc, label);
+    /* Sec. 2.3, after the steps: when a set holds more than one planet the
+     * step may integrate every body with the Hermite.  Reading: all bodies
+     * form one set whose r_crit is infinite, so K = 0 and W = 1 for every
+     * pair; the corrections then take back both half kicks entirely and the
+     * Hermite integrates H_Kep + H_Int of the whole system between the two
+     * drifts. */
+    double rc_whole = 0.0;
+    if (p->planet_mass > 0.0 && s.n_sets > 0) {
+        int32_t *np = calloc((size_t)n, sizeof(int32_t));
+        int whole = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (label[i] >= 0 && m[i] >= p->planet_mass && ++np[label[i]] >= 2) whole = 1;
+        free(np);
+        if (whole) {
+            for (int64_t i = 0; i < n; ++i) label[i] = 0;
+            s.n_sets = 1;
+            s.whole_system = 1;
+            rc_whole = INFINITY;
+        }
+    }
     if (s.n_sets > 0) {
         /* members of each set, ascending, grouped by label ascending */
         int64_t nmem = 0;
@@ -903,7 +928,7 @@ int orc_step(int64_t n, const orc_params *p, double tau, const double *m, const 
                 double rh = h[mk[b]] * A[mk[b]];
                 if (rh > hmax) hmax = rh;
             }
-            double rcrit = p->aH * hmax;
+            double rcrit = s.whole_system ? rc_whole : p->aH * hmax;
             /* 5 */
             orc_correct_set(nm, mk, m, q0, v0, p->G, rcrit, tau / 2.0);
             /* 6: Hermite from (q0, v0) of the members, results into (q, v) */
