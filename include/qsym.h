@@ -71,6 +71,14 @@ typedef struct qsym_params {
                             on single-precision forces)                        */
     int32_t max_substeps;/* Hermite substep cap per set per step (>= 1)           */
     int64_t pair_capacity; /* crude-candidate capacity; 0 selects 8*ntot + 1024  */
+    double planet_mass;  /* > 0: bodies at least this massive are planets; a
+                            step whose encounter sets put two planets in one
+                            set integrates that whole system with the Hermite
+                            (Sec. 2.3, after the steps): one set of all its
+                            bodies with r_crit infinite (K = 0, W = 1), so the
+                            corrections take back both half kicks.  0: off.
+                            The workspace then holds member slots for every
+                            body.                                             */
 } qsym_params;
 
 /* Counters of the last step and totals since creation/reset. */
@@ -89,6 +97,7 @@ typedef struct qsym_stats_t {
     int64_t status;           /* latched device status bits                    */
     double phase_us[12];      /* per-kernel time when profiling is enabled     */
     int64_t phase_calls[12];  /* launches timed per kernel                     */
+    int64_t whole_system;     /* all steps: systems integrated whole (planet_mass) */
 } qsym_stats_t;
 
 typedef struct qsym_ctx qsym_ctx;
@@ -179,14 +188,18 @@ int qsym_fine_test(const qsym_params *p, double m0, double tau, int64_t n, const
  * ipl = i-bodies per lane (1, 2, 4), block = threads per workgroup (128,
  * 256), jchunk = j-bodies per workgroup (a multiple of block and at least
  * the smallest j-chunk the workspace was sized for), remap = 1 for the
- * XCD-aware workgroup order.  qsym_autotune times every candidate shape of
- * both kicks on the current state (without moving it), keeps the fastest,
- * and writes the two kick times in microseconds to us[0] (plain) and us[1]
- * (crude sweep).  Results do not depend on the shape beyond rounding. */
+ * XCD-aware workgroup order, sym = 0 for the full-matrix kick (every
+ * ordered pair) or 1, 2, 4, 8 for the symmetric kick (every unordered pair
+ * once, the reaction applied to j; sym i-blocks of block*ipl bodies per work
+ * item, jchunk a multiple of block*ipl).  qsym_autotune times every
+ * candidate shape of both kicks on the current state (without moving it),
+ * keeps the fastest, and writes the two kick times in microseconds to us[0]
+ * (plain) and us[1] (crude sweep).  Results do not depend on the shape
+ * beyond rounding. */
 int qsym_set_kick_shape(qsym_ctx *ctx, int32_t which, int32_t ipl, int32_t block, int64_t jchunk,
-                        int32_t remap);
+                        int32_t remap, int32_t sym);
 int qsym_get_kick_shape(qsym_ctx *ctx, int32_t which, int32_t *ipl, int32_t *block,
-                        int64_t *jchunk, int32_t *remap);
+                        int64_t *jchunk, int32_t *remap, int32_t *sym);
 int qsym_autotune(qsym_ctx *ctx, double tau, double *us);
 
 /* Profiling: when enabled, qsym_step launches kernels directly (no graph)

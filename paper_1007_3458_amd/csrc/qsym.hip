@@ -29,6 +29,7 @@ struct Shape {
     int block = 256;
     long long jchunk = 1024;
     int remap = 1;
+    int sym = 0;   // > 0: symmetric kick with this many i-blocks per work item
 };
 
 // workspace layout: byte offsets of every array
@@ -36,7 +37,8 @@ struct Layout {
     size_t off_state = 0, off_snap = 0, off_aux = 0, off_acc = 0, off_pm = 0, off_bsys = 0;
     size_t off_sysoff = 0, off_sysm0 = 0, off_sysS = 0, off_syspoff = 0, off_sysc0 = 0;
     size_t off_bchunk = 0, off_kchunk = 0, off_items = 0, off_eitems = 0, off_syse0 = 0, off_cand = 0;
-    size_t off_enc = 0, off_syseoff = 0, off_sysecnt = 0, off_setcount = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0;
+    size_t off_enc = 0, off_syseoff = 0, off_sysecnt = 0, off_setcount = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0, off_setlist = 0;
+    size_t off_gbar = 0, off_hpart = 0;
     size_t off_hw = 0, off_ctr = 0, off_epart = 0, off_E = 0, off_guess = 0;
     size_t total = 0;
     long long np = 0;          // padded body count
@@ -90,8 +92,10 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     L.n_eitems = 0;
     for (int s = 0; s < nsys; ++s) {
         const long long n = off[s + 1] - off[s];
+        // partial slots: up to S j-chunks, and as many again for the
+        // reaction slots of the symmetric kick
         const long long S = (n + L.jchunk_min - 1) / L.jchunk_min;
-        L.acc_len += 3 * S * n;
+        L.acc_len += 3 * (2 * S) * n;
         L.nchunks += (n + kChunk - 1) / kChunk;
         L.nkchunks += (n + kChunkK - 1) / kChunkK;
         L.max_items += ((n + 127) / 128) * S;
@@ -107,6 +111,8 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     for (int s = 0; s < nsys; ++s) L.ecap += sys_enc_cap(off[s + 1] - off[s]);
     L.ecap = std::max<long long>(L.ecap, 1);
     L.memcap = 2 * L.ecap;
+    // whole-system sets need a member slot for every body
+    if (p.planet_mass > 0.0) L.memcap += off[nsys];
     size_t o = 0;
     auto take = [&](size_t &field, size_t bytes) {
         o = align_up(o, 256);
@@ -122,7 +128,7 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_bsys, (size_t)L.np * sizeof(int));
     take(L.off_sysoff, (size_t)(nsys + 1) * sizeof(int));
     take(L.off_sysm0, (size_t)std::max(nsys, 1) * D);
-    take(L.off_sysS, 2 * (size_t)std::max(nsys, 1) * sizeof(int));
+    take(L.off_sysS, 2 * (size_t)std::max(nsys, 1) * sizeof(int4));
     take(L.off_syspoff, (size_t)std::max(nsys, 1) * sizeof(long long));
     take(L.off_sysc0, (size_t)(nsys + 1) * sizeof(int));
     take(L.off_bchunk, (size_t)L.nchunks * sizeof(int4));
@@ -138,6 +144,9 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_setcount, (size_t)L.ecap * sizeof(int));
     take(L.off_setmem, (size_t)L.memcap * sizeof(int));
     take(L.off_setrc, (size_t)L.ecap * D);
+    take(L.off_setlist, (size_t)L.ecap * sizeof(int));
+    take(L.off_gbar, 4 * sizeof(unsigned));
+    take(L.off_hpart, 2 * (size_t)kGridMax * D);
     take(L.off_hw, (size_t)HFIELDS * L.memcap * D);
     take(L.off_ctr, (size_t)C_COUNT * sizeof(unsigned long long));
     take(L.off_epart, (size_t)L.n_eitems * D);
@@ -176,7 +185,7 @@ Dev bind(char *base, const Layout &L)
     d.body_sys = (int *)(base + L.off_bsys);
     d.sys_off = (int *)(base + L.off_sysoff);
     d.sys_m0 = (double *)(base + L.off_sysm0);
-    d.sys_S = (int *)(base + L.off_sysS);
+    d.sys_K = (int4 *)(base + L.off_sysS);
     d.sys_poff = (long long *)(base + L.off_syspoff);
     d.sys_c0 = (int *)(base + L.off_sysc0);
     d.bchunk = (int4 *)(base + L.off_bchunk);
@@ -189,6 +198,10 @@ Dev bind(char *base, const Layout &L)
     d.sys_eoff = (int *)(base + L.off_syseoff);
     d.sys_ecnt = (int *)(base + L.off_sysecnt);
     d.set_count = (int *)(base + L.off_setcount);
+    d.set_list = (int *)(base + L.off_setlist);
+    d.gbar = (unsigned *)(base + L.off_gbar);
+    d.hpart = (double *)(base + L.off_hpart);
+    d.setcap = (int)L.ecap;
     d.memcap = (int)L.memcap;
     d.set_start = (int *)(base + L.off_setstart);
     d.set_mem = (int *)(base + L.off_setmem);
@@ -235,6 +248,7 @@ struct qsym_ctx {
     double phase_us[kPhases] = {};
     long long phase_calls[kPhases] = {};
     bool guess_loaded = false;
+    int grid_blocks = 256;   // workgroups of k_hermite_grid: the device's compute units
     double tau_crude = 0.0;  // |tau| of the crude sweep being enqueued
     std::string err;
 };
@@ -271,7 +285,8 @@ int validate(const qsym_params *p, int32_t nsys, const int64_t *offsets, std::st
         return QSYM_EINVAL;
     }
     if (p->hill_mode < 0 || p->hill_mode > 1 || p->kepler_mode < 0 || p->kepler_mode > 2 ||
-        p->precision < 0 || p->precision > 1 || p->max_substeps < 1 || p->pair_capacity < 0) {
+        p->precision < 0 || p->precision > 1 || p->max_substeps < 1 || p->pair_capacity < 0 ||
+        !(p->planet_mass >= 0.0) || !std::isfinite(p->planet_mass)) {
         msg = "mode out of range";
         return QSYM_EINVAL;
     }
@@ -297,7 +312,7 @@ void build_tables(qsym_ctx *c)
         const int n = nsys_bodies(c->off, s);
         T.sys_off[s] = (int)c->off[s];
         T.sys_poff[s] = poff;
-        poff += 3LL * ((n + c->L.jchunk_min - 1) / c->L.jchunk_min) * n;
+        poff += 3LL * (2 * ((n + c->L.jchunk_min - 1) / c->L.jchunk_min)) * n;
         T.sys_c0[s] = (int)T.bchunk.size();
         for (int b = 0; b < n; b += kChunk)
             T.bchunk.push_back(make_int4(s, (int)c->off[s] + b, std::min(kChunk, n - b), 0));
@@ -324,12 +339,12 @@ void build_tables(qsym_ctx *c)
 
 // kick work items for a launch shape; systems largest first, each system's
 // items j-chunk major (consecutive items share j data)
-int build_items(qsym_ctx *c, const Shape &sh, std::vector<KickItem> &items, std::vector<int> &sysS)
+int build_items(qsym_ctx *c, const Shape &sh, std::vector<KickItem> &items, std::vector<int4> &sysK)
 {
     const long long BI = (long long)sh.block * sh.ipl;
     const long long JC = sh.jchunk;
     items.clear();
-    sysS.assign(c->nsys, 0);
+    sysK.assign(c->nsys, make_int4(0, 0, 0, 0));
     std::vector<int> order(c->nsys);
     for (int s = 0; s < c->nsys; ++s) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -338,14 +353,30 @@ int build_items(qsym_ctx *c, const Shape &sh, std::vector<KickItem> &items, std:
     for (int s : order) {
         const int n = nsys_bodies(c->off, s);
         const int S = (int)((n + JC - 1) / JC);
-        sysS[s] = S;
-        for (int ch = 0; ch < S; ++ch)
-            for (long long ib = 0; ib < n; ib += BI) {
-                KickItem it{s, (int)(c->off[s] + ib), (int)std::min<long long>(BI, n - ib),
-                            (int)(c->off[s] + ch * JC), (int)std::min<long long>(JC, n - ch * JC),
-                            ch};
-                items.push_back(it);
+        const long long o = c->off[s];
+        if (sh.sym == 0) {
+            sysK[s] = make_int4(S, (int)JC, 0, 0);
+            for (int ch = 0; ch < S; ++ch)
+                for (long long ib = 0; ib < n; ib += BI) {
+                    KickItem it{s, (int)(o + ib), (int)std::min<long long>(BI, n - ib),
+                                (int)(o + ch * JC), (int)std::min<long long>(JC, n - ch * JC), ch, 0};
+                    items.push_back(it);
+                }
+        } else {
+            // chunk ch meets the i-bodies below its end, in ranges of RB
+            const long long RB = BI * sh.sym;
+            sysK[s] = make_int4(S, (int)JC, (int)RB, 0);
+            for (int ch = 0; ch < S; ++ch) {
+                const long long hi = std::min<long long>((ch + 1) * JC, n);
+                const int R = (int)((hi + RB - 1) / RB);
+                for (int r = 0; r < R; ++r) {
+                    KickItem it{s, (int)(o + r * RB), (int)std::min<long long>(RB, hi - r * RB),
+                                (int)(o + ch * JC), (int)std::min<long long>(JC, n - ch * JC), ch,
+                                S + r};
+                    items.push_back(it);
+                }
             }
+        }
     }
     return (int)items.size();
 }
@@ -353,20 +384,23 @@ int build_items(qsym_ctx *c, const Shape &sh, std::vector<KickItem> &items, std:
 int upload_shape(qsym_ctx *c, int which)
 {
     std::vector<KickItem> items;
-    std::vector<int> sysS;
-    const int n = build_items(c, c->shape[which], items, sysS);
+    std::vector<int4> sysK;
+    const int n = build_items(c, c->shape[which], items, sysK);
     if ((long long)n > c->L.max_items)
         return fail(c, QSYM_EINVAL, "kick shape needs more work items than the workspace holds");
     for (int s = 0; s < c->nsys; ++s) {
-        const long long Smax = (nsys_bodies(c->off, s) + c->L.jchunk_min - 1) / c->L.jchunk_min;
-        if (sysS[s] > Smax) return fail(c, QSYM_EINVAL, "j-chunk smaller than the workspace allows");
+        const long long ns = nsys_bodies(c->off, s);
+        const long long Smax = (ns + c->L.jchunk_min - 1) / c->L.jchunk_min;
+        const long long slots = sysK[s].x + (sysK[s].z > 0 ? (ns + sysK[s].z - 1) / sysK[s].z : 0);
+        if (sysK[s].x > Smax || slots > 2 * Smax)
+            return fail(c, QSYM_EINVAL, "j-chunk smaller than the workspace allows");
     }
     c->nitems[which] = n;
     c->grid_kick[which] = std::max(8, (n + 7) / 8 * 8);
     if (n > 0)
         HIPCHK(c, hipMemcpyAsync(c->d.items + (size_t)which * c->L.max_items, items.data(),
                                  sizeof(KickItem) * n, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->d.sys_S + (size_t)which * c->nsys, sysS.data(), sizeof(int) * c->nsys,
+    HIPCHK(c, hipMemcpyAsync(c->d.sys_K + (size_t)which * c->nsys, sysK.data(), sizeof(int4) * c->nsys,
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->g[0].valid = c->g[1].valid = false;
@@ -382,6 +416,18 @@ hipError_t launch_kick_bs(qsym_ctx *c, int mode, int prec, hipStream_t st)
                 c->shape[w].remap, c->p.hill_mode, c->p.aE, c->p.crude_safety, c->tau_crude, 1e-200,
                 1.875, 1.5};
     const dim3 g(c->shape[w].remap ? c->grid_kick[w] : std::max(c->nitems[w], 1)), b(BS);
+    if (c->shape[w].sym) {
+        if (prec == 0) {
+            if (mode == 0) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 0, 0>), g, b, 0, st, ka);
+            else if (mode == 1) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 1, 0>), g, b, 0, st, ka);
+            else hipLaunchKernelGGL((k_kick_sym<BS, IPL, 2, 0>), g, b, 0, st, ka);
+        } else {
+            if (mode == 0) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 0, 1>), g, b, 0, st, ka);
+            else if (mode == 1) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 1, 1>), g, b, 0, st, ka);
+            else hipLaunchKernelGGL((k_kick_sym<BS, IPL, 2, 1>), g, b, 0, st, ka);
+        }
+        return hipGetLastError();
+    }
     if (prec == 0) {
         if (mode == 0) hipLaunchKernelGGL((k_kick<BS, IPL, 0, 0>), g, b, 0, st, ka);
         else if (mode == 1) hipLaunchKernelGGL((k_kick<BS, IPL, 1, 0>), g, b, 0, st, ka);
@@ -483,7 +529,7 @@ hipError_t run_apply(qsym_ctx *c, double dt_kick, double dt_kep, int do_kick, in
 {
     Timer tm(c, phase);
     const bool small = do_kep && !momentum;
-    ApplyArgs a{c->d, small ? c->d.kchunk : c->d.bchunk, c->d.sys_S + (size_t)which * c->nsys,
+    ApplyArgs a{c->d, small ? c->d.kchunk : c->d.bchunk, c->d.sys_K + (size_t)which * c->nsys,
                 dt_kick, dt_kep, c->p.G, do_kick, do_kep, snapshot, c->p.kepler_mode, momentum};
     if (small)
         hipLaunchKernelGGL(k_apply_kepler<kChunkK>, dim3((unsigned)c->T.kchunk.size()), dim3(kChunkK), 0,
@@ -526,7 +572,7 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
     }
     {
         Timer tm(c, P_SETS);
-        SetsArgs sa{c->d, c->p.aH};
+        SetsArgs sa{c->d, c->p.aH, c->p.planet_mass};
         hipLaunchKernelGGL(k_sets, dim3(c->nsys), dim3(kSetsThreads), 0, st, sa);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -535,6 +581,11 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
         Timer tm(c, P_HERMITE);
         HermArgs ha{c->d, tau, c->p.G, c->p.epsH, c->p.eta, c->p.eta_s, c->p.max_substeps};
         hipLaunchKernelGGL(k_hermite, dim3(256), dim3(kHermThreads), 0, st, ha);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // sets above kCoopMin members: the whole grid on one set at a time
+        // (one workgroup per compute unit, so every workgroup is resident)
+        GridArgs ga{ha, c->d.gbar, c->d.hpart};
+        hipLaunchKernelGGL(k_hermite_grid, dim3(c->grid_blocks), dim3(kGridThreads), 0, st, ga);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // 9: kick tau/2 (all pairs), applied with the momentum partials
@@ -689,6 +740,13 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
     };
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(QSYM_EHIP, "hipStreamCreateWithFlags");
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return bail(QSYM_EHIP, "hipDeviceGetAttribute");
+        c->grid_blocks = std::max(1, std::min(cus, kGridMax));
+    }
     if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess)
         return bail(QSYM_EHIP, "hipEventCreateWithFlags");
     if (hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
@@ -955,6 +1013,7 @@ int qsym_stats(qsym_ctx *c, qsym_stats_t *out)
     out->kepler_max = (int64_t)h[C_KMAX];
     for (int k = 0; k < kHist; ++k) out->kepler_hist[k] = (int64_t)h[C_HIST + k];
     out->status = (int64_t)h[C_STATUS];
+    out->whole_system = (int64_t)h[C_WHOLE];
     for (int k = 0; k < kPhases; ++k) {
         out->phase_us[k] = c->phase_us[k];
         out->phase_calls[k] = c->phase_calls[k];
@@ -1016,17 +1075,19 @@ int qsym_fine_test(const qsym_params *p, double m0, double tau, int64_t n, const
 }
 
 int qsym_set_kick_shape(qsym_ctx *c, int32_t which, int32_t ipl, int32_t block, int64_t jchunk,
-                        int32_t remap)
+                        int32_t remap, int32_t sym)
 {
     if (!c) return QSYM_EINVAL;
     if ((which < -1 || which > 1) || (ipl != 1 && ipl != 2 && ipl != 4) ||
         (block != 128 && block != 256) || jchunk <= 0 || jchunk % block ||
-        jchunk < c->L.jchunk_min || (remap != 0 && remap != 1))
+        jchunk < c->L.jchunk_min || (remap != 0 && remap != 1) ||
+        (sym != 0 && sym != 1 && sym != 2 && sym != 4 && sym != 8) ||
+        (sym && jchunk % ((long long)block * ipl)))
         return fail(c, QSYM_EINVAL, "kick shape out of range");
     for (int w = 0; w < 2; ++w) {
         if (which >= 0 && w != which) continue;
         const Shape old = c->shape[w];
-        c->shape[w] = Shape{ipl, block, jchunk, remap};
+        c->shape[w] = Shape{ipl, block, jchunk, remap, sym};
         const int rc = upload_shape(c, w);
         if (rc) {
             c->shape[w] = old;
@@ -1038,7 +1099,7 @@ int qsym_set_kick_shape(qsym_ctx *c, int32_t which, int32_t ipl, int32_t block, 
 }
 
 int qsym_get_kick_shape(qsym_ctx *c, int32_t which, int32_t *ipl, int32_t *block, int64_t *jchunk,
-                        int32_t *remap)
+                        int32_t *remap, int32_t *sym)
 {
     if (!c || which < 0 || which > 1) return QSYM_EINVAL;
     const Shape &sh = c->shape[which];
@@ -1046,6 +1107,7 @@ int qsym_get_kick_shape(qsym_ctx *c, int32_t which, int32_t *ipl, int32_t *block
     if (block) *block = sh.block;
     if (jchunk) *jchunk = sh.jchunk;
     if (remap) *remap = sh.remap;
+    if (sym) *sym = sh.sym;
     return QSYM_OK;
 }
 
@@ -1069,29 +1131,37 @@ int qsym_autotune(qsym_ctx *c, double tau, double *us)
         const int mode = w ? 1 + c->p.hill_mode : 0;
         Shape best = c->shape[w];
         double best_us = 1e300;
+        // full-matrix shapes, then symmetric ones (i-blocks per item 1, 2, 4)
+        std::vector<Shape> cand;
         for (int bi = 0; bi < 2; ++bi)
             for (int ii = 0; ii < 3; ++ii)
                 for (long long jc = c->L.jchunk_min; jc <= std::max<long long>(c->L.jchunk_min, 8192);
                      jc *= 2) {
                     const long long jcr = (jc + blocks[bi] - 1) / blocks[bi] * blocks[bi];
-                    for (int rm = 0; rm < 2; ++rm) {
-                        c->shape[w] = Shape{ipls[ii], blocks[bi], jcr, rm};
-                        if (upload_shape(c, w) != QSYM_OK) continue;
-                        // warm-up, then 3 timed launches
-                        (void)launch_kick(c, mode, st);
-                        (void)hipEventRecord(e0, st);
-                        for (int r = 0; r < 3; ++r) (void)launch_kick(c, mode, st);
-                        (void)hipEventRecord(e1, st);
-                        (void)hipEventSynchronize(e1);
-                        float ms = 0.f;
-                        (void)hipEventElapsedTime(&ms, e0, e1);
-                        const double t_us = 1000.0 * ms / 3.0;
-                        if (t_us < best_us) {
-                            best_us = t_us;
-                            best = c->shape[w];
-                        }
-                    }
+                    for (int rm = 0; rm < 2; ++rm) cand.push_back(Shape{ipls[ii], blocks[bi], jcr, rm, 0});
+                    const long long BI = (long long)blocks[bi] * ipls[ii];
+                    const long long jcs = (jc + BI - 1) / BI * BI;
+                    for (int sy = 1; sy <= 4; sy *= 2)
+                        for (int rm = 0; rm < 2; ++rm)
+                            cand.push_back(Shape{ipls[ii], blocks[bi], jcs, rm, sy});
                 }
+        for (const Shape &sh : cand) {
+            c->shape[w] = sh;
+            if (upload_shape(c, w) != QSYM_OK) continue;
+            // warm-up, then 3 timed launches
+            (void)launch_kick(c, mode, st);
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < 3; ++r) (void)launch_kick(c, mode, st);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            const double t_us = 1000.0 * ms / 3.0;
+            if (t_us < best_us) {
+                best_us = t_us;
+                best = c->shape[w];
+            }
+        }
         c->shape[w] = best;
         const int r = upload_shape(c, w);
         if (r) rc = r;

@@ -14,6 +14,9 @@ constexpr int kHist = 32;          // Kepler iteration histogram bins
 constexpr int kSMax = 64;          // largest j-split of one system
 constexpr int kSetsThreads = 256;  // workgroup of the set-partition kernel
 constexpr int kHermThreads = 512;  // workgroup of the Hermite kernel
+constexpr int kHermWave = 64;      // lanes of the one-wave Hermite
+constexpr int kWaveMax = 16;       // sets up to this size run on one wave, larger on a workgroup
+constexpr int kGridMax = 1024;     // largest grid of the grid-wide Hermite
 constexpr double kPi = 3.14159265358979323846;
 
 // counters / status word in device memory (unsigned 64-bit for atomics)
@@ -30,8 +33,13 @@ enum Ctr {
     C_STEPS,      // steps taken
     C_STATUS,     // latched status bits
     C_NU,         // bodies in encounters, last step
+    C_NSMALL,     // sets of at most kWaveMax members (one wave each), last step
+    C_NBIG,       // larger sets (one workgroup each), last step
+    C_HQS,        // Hermite work-queue heads (small, big)
+    C_HQB,
     C_HIST = 16,  // kHist bins
-    C_COUNT = C_HIST + kHist
+    C_WHOLE = C_HIST + kHist,   // systems integrated whole (all steps)
+    C_COUNT
 };
 
 enum Status : unsigned long long {
@@ -46,7 +54,7 @@ enum Status : unsigned long long {
 // one workgroup of the pair kernels: i-bodies [i0, i0+ni) of system sys
 // against j-bodies [j0, j0+nj) (its j-chunk number `chunk`)
 struct KickItem {
-    int sys, i0, ni, j0, nj, chunk;
+    int sys, i0, ni, j0, nj, chunk, slot;   // slot: j-side partial slot (symmetric kick)
 };
 
 // device pointers into the caller-provided workspace
@@ -59,7 +67,7 @@ struct Dev {
     int *body_sys;                              // system of each body
     int *sys_off;                               // [nsys+1] first body of each system
     double *sys_m0;                             // central masses
-    int *sys_S;                                 // [2][nsys] j-split per kick shape
+    int4 *sys_K;                                // [2][nsys] partial-slot layout per kick shape
     long long *sys_poff;                        // offset of its partials in acc
     int *sys_c0;                                // [nsys+1] first O(N) chunk
     int4 *bchunk;                               // O(N) chunks (sys, first, count, 0)
@@ -75,6 +83,10 @@ struct Dev {
     int *set_count;                             // [setcap] members of each set
     int *set_mem;                               // [memcap] member body indices
     double *set_rc;                             // [setcap] r_crit per set
+    int *set_list;                              // [setcap] small sets from 0 up, big from the end down
+    int setcap;                                 // set slots
+    unsigned *gbar;                             // grid barrier of k_hermite_grid (3 words)
+    double *hpart;                              // [2][kGridMax] its per-block step minima
     int memcap;                                 // member slots (Hermite scratch stride)
     double *hw;                                 // Hermite member scratch
     unsigned long long *ctr;                    // counters and status

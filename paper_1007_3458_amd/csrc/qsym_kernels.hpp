@@ -53,6 +53,15 @@ __device__ __forceinline__ double block_min(double v, double *lds)
     return r;
 }
 
+// LDS written by some lanes of a wave and read by others: the wave's LDS
+// operations complete in order, so a fence and a wave barrier suffice
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ void latch(unsigned long long *ctr, unsigned long long bits)
 {
     atomicOr(&ctr[C_STATUS], bits);
@@ -121,6 +130,13 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
         d.ctr[C_MAXSET] = 0;
         d.ctr[C_SUB] = 0;
         d.ctr[C_NU] = 0;
+        d.ctr[C_NSMALL] = 0;
+        d.ctr[C_NBIG] = 0;
+        d.ctr[C_HQS] = 0;
+        d.ctr[C_HQB] = 0;
+        d.gbar[0] = 0u;
+        d.gbar[1] = 0u;
+        d.gbar[2] = 0u;
     }
     if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) d.ctr[C_STEPS] += 1;
     if (a.reset && threadIdx.x == 0 && (int)blockIdx.x == d.sys_c0[s]) d.sys_ecnt[s] = 0;
@@ -266,7 +282,7 @@ constexpr double kFar = 1e18;
 constexpr int kCrudeQ = 512;
 
 template <int BS, int IPL, int MODE>
-__device__ __forceinline__ void crude_drain(const KickArgs &ka, const KickItem &it, int jt,
+__device__ __forceinline__ void crude_drain(const KickArgs &ka, int i0, int ni, int jt, int jend,
                                             const int *ii, unsigned *qbuf, unsigned *qn)
 {
     const unsigned n = *qn;
@@ -275,15 +291,15 @@ __device__ __forceinline__ void crude_drain(const KickArgs &ka, const KickItem &
         for (unsigned e = tid; e < n; e += BS) {
             const unsigned v = qbuf[e];
             const int lt = (int)(v >> 16), u = (int)((v >> 8) & 0xffu), jj = (int)(v & 0xffu);
-            if (lt + u * BS < it.ni) crude_exact(ka, it.i0 + lt + u * BS, jt + jj);
+            if (lt + u * BS < ni) crude_exact(ka, i0 + lt + u * BS, jt + jj);
         }
     } else {
         // queue overflow (a dense tile): exact test of every pair of the tile
-        const int jend = min(jt + BS, it.j0 + it.nj);
+        const int je = min(jt + BS, jend);
 #pragma unroll
         for (int u = 0; u < IPL; ++u)
-            if (tid + u * BS < it.ni)
-                for (int j = jt; j < jend; ++j) crude_exact(ka, ii[u], j);
+            if (tid + u * BS < ni)
+                for (int j = jt; j < je; ++j) crude_exact(ka, ii[u], j);
     }
 }
 
@@ -333,7 +349,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
         __syncthreads();
         if constexpr (MODE != 0) {
             if (qtile >= 0) {
-                if (qn) crude_drain<BS, IPL, MODE>(ka, it, qtile, ii, qbuf, &qn);
+                if (qn) crude_drain<BS, IPL, MODE>(ka, it.i0, it.ni, qtile, it.j0 + it.nj, ii, qbuf, &qn);
                 __syncthreads();
                 if (tid == 0) qn = 0u;
                 qtile = -1;
@@ -430,7 +446,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
     }
     if constexpr (MODE != 0) {
         __syncthreads();
-        if (qtile >= 0 && qn) crude_drain<BS, IPL, MODE>(ka, it, qtile, ii, qbuf, &qn);
+        if (qtile >= 0 && qn)
+            crude_drain<BS, IPL, MODE>(ka, it.i0, it.ni, qtile, it.j0 + it.nj, ii, qbuf, &qn);
     }
     const int s = it.sys;
     const int ns = d.sys_off[s + 1] - d.sys_off[s];
@@ -446,18 +463,283 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
     }
 }
 
+// ------------------------------------------------------------------------
+// Symmetric kick (Newton's third law): each unordered pair once.  A work
+// item is a chunk of j-bodies [j0, j0 + nj) and a range of i-blocks
+// [i0, i0 + ni) (blocks of BI = BS * IPL bodies).  An i-block starting at
+// ib meets only the part j >= ib of the chunk, and in the tiles that overlap
+// the i-block only j > i, so every pair i < j of the system is met exactly
+// once over all items.  The force on i goes to its i-side slot `chunk`
+// (written as by k_kick); the reaction on j is summed over the lanes of a
+// wave (fixed xor tree) and over the waves in order, then added to the
+// item's own j-side slot `slot`, which the item first clears for every j of
+// the chunk (each entry is only ever touched by one thread of one item, so
+// no atomics and a fixed order).  Per pair: 21 VALU instructions for both
+// forces instead of 2 x 17.
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum_xor(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// FP64 pair of the symmetric kick: force on i into (ax, ay, az), reaction
+// on j added to (fx, fy, fz); keep = false drops the pair (j <= i)
+__device__ __forceinline__ void pair_sym64(const double4 &pj, double xi, double yi, double zi,
+                                           double gmi, double seed, double c158, double c32,
+                                           bool keep, double &ax, double &ay, double &az,
+                                           double &fx, double &fy, double &fz, double &r2)
+{
+    const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
+    r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, seed)));
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double y2 = y0 * y0;
+    const double e = fma(-r2, y2, 1.0);
+    const double w = fma(e, fma(e, c158, c32), 1.0);
+    double r3 = (y2 * y0) * w;
+    if (!keep) r3 = 0.0;
+    const double msj = pj.w * r3, msi = gmi * r3;
+    ax = fma(msj, dx, ax);
+    ay = fma(msj, dy, ay);
+    az = fma(msj, dz, az);
+    fx = fma(-msi, dx, fx);
+    fy = fma(-msi, dy, fy);
+    fz = fma(-msi, dz, fz);
+}
+
+// FP32 form: r^-3 from the FP32 rsq on the FP64 r^2 (as pair32)
+__device__ __forceinline__ void pair_sym32(const double4 &pj, float mjf, double xi, double yi,
+                                           double zi, float mif, bool keep, double &ax, double &ay,
+                                           double &az, double &fx, double &fy, double &fz,
+                                           double &r2)
+{
+    const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
+    r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, 1e-24)));
+    const float y = __builtin_amdgcn_rsqf((float)r2);
+    float r3 = y * y * y;
+    if (!keep) r3 = 0.0f;
+    const double msj = (double)(mjf * r3), msi = (double)(mif * r3);
+    ax = fma(msj, dx, ax);
+    ay = fma(msj, dy, ay);
+    az = fma(msj, dz, az);
+    fx = fma(-msi, dx, fx);
+    fy = fma(-msi, dy, fy);
+    fz = fma(-msi, dz, fz);
+}
+
+template <int BS, int IPL, int MODE, int PREC>
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_kick_sym(
+    KickArgs ka)
+{
+    const Dev &d = ka.d;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int b = blockIdx.x;
+    if (ka.remap) b = xcd_item(b, gridDim.x);
+    if (b >= ka.nitems) return;
+    const KickItem it = ka.items[b];
+    constexpr int NW = BS / 64;
+    constexpr int BI = BS * IPL;
+
+    __shared__ double4 sj[BS];
+    __shared__ double wpart[NW][3][BS];
+    __shared__ double smax[3][NW];
+    __shared__ unsigned qbuf[MODE ? kCrudeQ : 1];
+    __shared__ unsigned qn;
+
+    const int s = it.sys;
+    const int so = d.sys_off[s];
+    const int ns = d.sys_off[s + 1] - so;
+    const long long base = d.sys_poff[s];
+    const int jend = it.j0 + it.nj;
+    // the item's reaction slot; entry j is owned by thread (j - j0) % BS
+    double *rj = d.acc + base + (long long)it.slot * 3 * ns - so;
+    for (int k = tid; k < it.nj; k += BS) {
+        rj[it.j0 + k] = 0.0;
+        rj[ns + it.j0 + k] = 0.0;
+        rj[2 * ns + it.j0 + k] = 0.0;
+    }
+    if (MODE && tid == 0) qn = 0u;
+    const double G = ka.G;
+    const double seed = ka.r2seed, c158 = ka.c158, c32 = ka.c32;
+    for (int ib = it.i0; ib < it.i0 + it.ni; ib += BI) {
+        const int nib = min(BI, it.i0 + it.ni - ib);
+        double xi[IPL], yi[IPL], zi[IPL], gmi[IPL];
+        double ax[IPL], ay[IPL], az[IPL];
+        double hi[IPL], Ai[IPL], vi[IPL];
+        float mif[IPL];
+        int ii[IPL];
+#pragma unroll
+        for (int u = 0; u < IPL; ++u) {
+            const int i = ib + tid + u * BS;
+            const bool ok = (tid + u * BS) < nib;
+            xi[u] = ok ? d.x[i] : 0.0;
+            yi[u] = ok ? d.y[i] : 0.0;
+            zi[u] = ok ? d.z[i] : 0.0;
+            gmi[u] = ok ? G * d.m[i] : 0.0;
+            mif[u] = (float)gmi[u];
+            ax[u] = ay[u] = az[u] = 0.0;
+            if (MODE) {
+                hi[u] = ok ? d.ch[i] : 0.0;
+                Ai[u] = ok ? d.A[i] : 0.0;
+                vi[u] = ok ? d.cv[i] : 0.0;
+            }
+            ii[u] = ok ? i : 0x7fffffff;
+        }
+        int qtile = -1;
+        for (int jt = max(it.j0, ib); jt < jend; jt += BS) {
+            const int j = jt + tid;
+            const bool okj = j < jend;
+            __syncthreads();
+            if constexpr (MODE != 0) {
+                if (qtile >= 0) {
+                    if (qn) crude_drain<BS, IPL, MODE>(ka, ib, nib, qtile, jend, ii, qbuf, &qn);
+                    __syncthreads();
+                    if (tid == 0) qn = 0u;
+                    qtile = -1;
+                }
+            }
+            sj[tid] = okj ? make_double4(d.x[j], d.y[j], d.z[j], G * d.m[j])
+                          : make_double4(kFar, kFar, kFar, 0.0);
+            // this thread's reaction entry, read early (latency hidden by the pairs)
+            double racc[3] = {0.0, 0.0, 0.0};
+            if (okj) {
+                racc[0] = rj[j];
+                racc[1] = rj[ns + j];
+                racc[2] = rj[2 * ns + j];
+            }
+            const int ntile = min(jt + BS, jend) - jt;
+            const int ntj = (ntile + 3) & ~3;
+            if constexpr (MODE != 0) {
+                double t0 = okj ? d.ch[j] : 0.0, t1 = okj ? d.A[j] : 0.0, t2 = okj ? d.cv[j] : 0.0;
+                t0 = wave_max(t0);
+                t1 = wave_max(t1);
+                t2 = wave_max(t2);
+                if (lane == 0) {
+                    smax[0][wv] = t0;
+                    smax[1][wv] = t1;
+                    smax[2][wv] = t2;
+                }
+            }
+            __syncthreads();
+            double th2[IPL];
+            if constexpr (MODE != 0) {
+                double HT = smax[0][0], AT = smax[1][0], VT = smax[2][0];
+#pragma unroll
+                for (int w2 = 1; w2 < NW; ++w2) {
+                    HT = fmax(HT, smax[0][w2]);
+                    AT = fmax(AT, smax[1][w2]);
+                    VT = fmax(VT, smax[2][w2]);
+                }
+#pragma unroll
+                for (int u = 0; u < IPL; ++u) {
+                    double Rb;
+                    if (MODE == 1)
+                        Rb = ka.aE * (hi[u] + HT) * (Ai[u] + AT) / 2.0;
+                    else
+                        Rb = ka.aE * (hi[u] + HT);
+                    const double th = ka.cs * (Rb + ka.tau_abs * (vi[u] + VT));
+                    th2[u] = th * th * 1.000000000001;
+                }
+            }
+            // tiles that overlap the i-block hold pairs with j <= i
+            const bool diag = jt < ib + nib;
+#pragma unroll 4
+            for (int jj = 0; jj < ntj; ++jj) {
+                const double4 pj = sj[jj];
+                const float mjf = (float)pj.w;
+                double fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma unroll
+                for (int u = 0; u < IPL; ++u) {
+                    const bool keep = !diag || (jt + jj > ii[u]);
+                    double r2;
+                    if constexpr (PREC == 0)
+                        pair_sym64(pj, xi[u], yi[u], zi[u], gmi[u], seed, c158, c32, keep, ax[u],
+                                   ay[u], az[u], fx, fy, fz, r2);
+                    else
+                        pair_sym32(pj, mjf, xi[u], yi[u], zi[u], mif[u], keep, ax[u], ay[u], az[u],
+                                   fx, fy, fz, r2);
+                    if constexpr (MODE != 0) {
+                        if (r2 < th2[u]) {
+                            const unsigned k = atomicAdd(&qn, 1u);
+                            if (k < (unsigned)kCrudeQ)
+                                qbuf[k] = ((unsigned)tid << 16) | ((unsigned)u << 8) | (unsigned)jj;
+                        }
+                    }
+                }
+                fx = wave_sum_xor(fx);
+                fy = wave_sum_xor(fy);
+                fz = wave_sum_xor(fz);
+                if (lane == 0) {
+                    wpart[wv][0][jj] = fx;
+                    wpart[wv][1][jj] = fy;
+                    wpart[wv][2][jj] = fz;
+                }
+            }
+            __syncthreads();
+            // the tile's reactions, waves in order, onto the slot
+            if (okj) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    double sum = wpart[0][c][tid];
+#pragma unroll
+                    for (int w2 = 1; w2 < NW; ++w2) sum += wpart[w2][c][tid];
+                    rj[c * ns + j] = racc[c] + sum;
+                }
+            }
+            if constexpr (MODE != 0) qtile = jt;
+        }
+        if constexpr (MODE != 0) {
+            __syncthreads();
+            if (qtile >= 0 && qn) crude_drain<BS, IPL, MODE>(ka, ib, nib, qtile, jend, ii, qbuf, &qn);
+            __syncthreads();
+            if (tid == 0) qn = 0u;
+        }
+        // forces on this i-block: i-side slot `chunk`
+        const long long pb = base + (long long)it.chunk * 3 * ns;
+#pragma unroll
+        for (int u = 0; u < IPL; ++u) {
+            if (tid + u * BS < nib) {
+                const int il = ib + tid + u * BS - so;
+                d.acc[pb + il] = ax[u];
+                d.acc[pb + ns + il] = ay[u];
+                d.acc[pb + 2 * ns + il] = az[u];
+            }
+        }
+    }
+}
+
+
 // sum of the kick partials of body i (local index il of system s)
-__device__ __forceinline__ void sum_partials(const Dev &d, const int *sysS, int s, int il,
+// Kick partials of body il of system s.  Full-matrix kick (K.z == 0): the
+// K.x j-chunk slots.  Symmetric kick (K = {S, JC, RB}): i-side slots of the
+// chunks from il's own chunk cx on (the chunks it meets as an i), then the
+// j-side slots of its chunk, one per i-range of RB bodies below the chunk's
+// end.  Always summed in slot order.
+__device__ __forceinline__ void sum_partials(const Dev &d, const int4 *sysK, int s, int il,
                                              double a[3])
 {
     const int ns = d.sys_off[s + 1] - d.sys_off[s];
-    const int S = sysS[s];
+    const int4 K = sysK[s];
     const double *p = d.acc + d.sys_poff[s] + il;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int c = 0; c < S; ++c) {
+    int c0 = 0, c1 = K.x, r1 = 0;
+    if (K.z > 0) {
+        const int cx = il / K.y;
+        c0 = cx;
+        r1 = (min((cx + 1) * K.y, ns) + K.z - 1) / K.z;
+    }
+    for (int c = c0; c < c1; ++c) {
         ax += p[(long long)(3 * c) * ns];
         ay += p[(long long)(3 * c + 1) * ns];
         az += p[(long long)(3 * c + 2) * ns];
+    }
+    for (int r = 0; r < r1; ++r) {
+        const long long sl = K.x + r;
+        ax += p[(3 * sl) * ns];
+        ay += p[(3 * sl + 1) * ns];
+        az += p[(3 * sl + 2) * ns];
     }
     a[0] = ax;
     a[1] = ay;
@@ -472,7 +754,7 @@ __device__ __forceinline__ void sum_partials(const Dev &d, const int *sysS, int 
 struct ApplyArgs {
     Dev d;
     const int4 *chunks; // body chunks of this launch (one per workgroup)
-    const int *sysS;   // j-split of the kick being applied
+    const int4 *sysK;  // partial-slot layout of the kick being applied
     double dt_kick, dt_kep, G;
     int do_kick, do_kep, snapshot, kepler_mode, momentum;
 };
@@ -503,7 +785,7 @@ __global__ __launch_bounds__(BS) void k_apply_kepler(ApplyArgs a)
         double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
         if (a.do_kick) {
             double acc[3];
-            sum_partials(d, a.sysS, s, i - d.sys_off[s], acc);
+            sum_partials(d, a.sysK, s, i - d.sys_off[s], acc);
             vx += a.dt_kick * acc[0];
             vy += a.dt_kick * acc[1];
             vz += a.dt_kick * acc[2];
@@ -675,24 +957,76 @@ __global__ __launch_bounds__(256) void k_fine_standalone(
 // smallest body index, members ascending), r_crit = a_H max h_i a_i.
 // One workgroup; everything in LDS (<= kCapE pairs).
 // ------------------------------------------------------------------------
-template <typename T>
-__device__ void bitonic_sort_lds(T *v, int n2)
+// Ascending bitonic sort of the 32-bit keys v[0..n2) by one workgroup of
+// kSetsThreads threads, n2 = R * kSetsThreads a power of two.  Thread t keeps
+// the R keys at positions t*R .. t*R+R-1 in registers: compare-exchanges
+// between keys of one thread run in registers, between lanes of one wave
+// through cross-lane shuffles, and only partners in different waves (distance
+// >= 64 R) go through LDS with workgroup barriers.  Same network, and so the
+// same result, as the textbook LDS bitonic sort.
+template <int R>
+__device__ void bitonic_regs(unsigned *v, int n2)
 {
-    // n2 is a power of two; ascending; one compare-exchange per thread
+    const int t = threadIdx.x;
+    unsigned e[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) e[r] = v[t * R + r];
     for (int k = 2; k <= n2; k <<= 1) {
-        for (int jx = k >> 1; jx > 0; jx >>= 1) {
-            for (int p = threadIdx.x; p < (n2 >> 1); p += blockDim.x) {
-                const int i = ((p & ~(jx - 1)) << 1) | (p & (jx - 1));
-                const int l = i + jx;
-                const T a = v[i], b = v[l];
-                const bool up = ((i & k) == 0);
-                if ((a > b) == up) {
-                    v[i] = b;
-                    v[l] = a;
-                }
-            }
+        int jx = k >> 1;
+        for (; jx >= 64 * R; jx >>= 1) {
             __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[t * R + r] = e[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = t * R + r;
+                const unsigned p = v[i ^ jx];
+                const bool keep_min = ((i & jx) == 0) == ((i & k) == 0);
+                e[r] = keep_min ? min(e[r], p) : max(e[r], p);
+            }
         }
+        for (; jx >= R; jx >>= 1) {
+            const int lm = jx / R;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = t * R + r;
+                const unsigned p = (unsigned)__shfl_xor((int)e[r], lm, 64);
+                const bool keep_min = ((i & jx) == 0) == ((i & k) == 0);
+                e[r] = keep_min ? min(e[r], p) : max(e[r], p);
+            }
+        }
+#pragma unroll
+        for (int jj = R / 2; jj > 0; jj >>= 1) {
+            if (jj >= k) continue;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (r & jj) continue;
+                const unsigned x = e[r], y = e[r | jj];
+                const bool asc = ((t * R + r) & k) == 0;
+                e[r] = asc ? min(x, y) : max(x, y);
+                e[r | jj] = asc ? max(x, y) : min(x, y);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[t * R + r] = e[r];
+    __syncthreads();
+}
+
+// v[0..n2), n2 a power of two in [kSetsThreads, 32 kSetsThreads]
+__device__ void block_sort_u32(unsigned *v, int n2)
+{
+    // the same n2 on every lane: scalar loop bounds and a scalar switch
+    n2 = __builtin_amdgcn_readfirstlane(n2);
+    switch (n2 / kSetsThreads) {
+    case 1: bitonic_regs<1>(v, n2); break;
+    case 2: bitonic_regs<2>(v, n2); break;
+    case 4: bitonic_regs<4>(v, n2); break;
+    case 8: bitonic_regs<8>(v, n2); break;
+    case 16: bitonic_regs<16>(v, n2); break;
+    default: bitonic_regs<32>(v, n2); break;
     }
 }
 
@@ -748,6 +1082,7 @@ __device__ int block_scan_excl(int *v, int n, int *tmp)
 struct SetsArgs {
     Dev d;
     double aH;
+    double planet_mass;   // > 0: whole-system rule on (see k_sets)
 };
 
 // binary search of v in the ascending u[0..n)
@@ -776,8 +1111,7 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     __shared__ unsigned int rp[kCapE];   // pairs as rank pairs
     __shared__ int flag[kCapU];          // scan scratch
     __shared__ int tmp[kSetsThreads / 64 + 1];
-    __shared__ int changed;
-    __shared__ int base_set, base_mem;
+    __shared__ int base_set, base_mem, s_whole;
     const int t = threadIdx.x;
     const int sys = blockIdx.x;
     const int cnt = d.sys_ecnt[sys];
@@ -788,7 +1122,7 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     }
     const int ne = cnt;
     if (ne == 0) return;
-    int m2 = 1;
+    int m2 = kSetsThreads;
     while (m2 < 2 * ne) m2 <<= 1;
     for (int k = t; k < m2; k += blockDim.x) {
         if (k < 2 * ne) {
@@ -799,7 +1133,7 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
         }
     }
     __syncthreads();
-    bitonic_sort_lds(ep, m2);
+    block_sort_u32(ep, m2);
     for (int k = t; k < 2 * ne; k += blockDim.x) flag[k] = (k == 0 || ep[k] != ep[k - 1]) ? 1 : 0;
     __syncthreads();
     for (int k = t; k < 2 * ne; k += blockDim.x) lab[k] = (unsigned)flag[k];
@@ -816,44 +1150,82 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     }
     for (int k = t; k < nu; k += blockDim.x) lab[k] = (unsigned)k;
     __syncthreads();
-    // label propagation to the component minimum (with pointer jumping)
-    for (int iter = 0; iter < 2 * kCapU; ++iter) {
-        if (t == 0) changed = 0;
-        __syncthreads();
-        for (int k = t; k < ne; k += blockDim.x) {
-            const unsigned ri = rp[k] >> 16, rj = rp[k] & 0xffffu;
-            const unsigned li = lab[ri], lj = lab[rj];
-            if (li != lj) {
-                const unsigned mn = li < lj ? li : lj;
-                atomicMin(&lab[ri], mn);
-                atomicMin(&lab[rj], mn);
-                changed = 1;
+    // union-find with union by minimum: a root is only ever linked below a
+    // smaller root, so every component ends rooted at its smallest rank
+    // whatever the order of the links
+    volatile unsigned *vlab = lab;   // re-read: other lanes link roots meanwhile
+    for (int k = t; k < ne; k += blockDim.x) {
+        unsigned x = rp[k] >> 16, y = rp[k] & 0xffffu;
+        for (;;) {
+            while (vlab[x] != x) x = vlab[x];
+            while (vlab[y] != y) y = vlab[y];
+            if (x == y) break;
+            if (x > y) {
+                const unsigned w = x;
+                x = y;
+                y = w;
             }
+            // link root y below x unless y stopped being a root meanwhile
+            const unsigned old = atomicCAS(&lab[y], y, x);
+            if (old == y) break;
+            y = old;
         }
-        __syncthreads();
-        for (int k = t; k < nu; k += blockDim.x) {
-            const unsigned l = lab[k];
-            const unsigned ll = lab[l];
-            if (ll < l) {
-                atomicMin(&lab[k], ll);
-                changed = 1;
-            }
-        }
-        __syncthreads();
-        if (!changed) break;
-        __syncthreads();
     }
+    __syncthreads();
+    for (int k = t; k < nu; k += blockDim.x) {
+        unsigned x = k;
+        while (lab[x] != x) x = lab[x];
+        flag[k] = (int)x;
+    }
+    __syncthreads();
+    for (int k = t; k < nu; k += blockDim.x) lab[k] = (unsigned)flag[k];
+    __syncthreads();
     // roots -> set ids in ascending root order
     for (int k = t; k < nu; k += blockDim.x) flag[k] = (lab[k] == (unsigned)k) ? 1 : 0;
     __syncthreads();
     const int nsets = block_scan_excl(flag, nu, tmp);
+    // Sec. 2.3, after the steps: a set holding two planets makes the step
+    // integrate the whole system with the Hermite -- one set of all its
+    // bodies (ascending) with r_crit infinite, so K = 0 and W = 1 for every
+    // pair.  Planet counts per set reuse rp (the rank pairs are done with).
+    if (a.planet_mass > 0.0) {
+        for (int k = t; k < nsets; k += blockDim.x) rp[k] = 0u;
+        if (t == 0) s_whole = 0;
+        __syncthreads();
+        for (int k = t; k < nu; k += blockDim.x)
+            if (d.m[uq[k]] >= a.planet_mass && atomicAdd(&rp[flag[lab[k]]], 1u) >= 1u) s_whole = 1;
+        __syncthreads();
+        if (s_whole) {
+            const int o = d.sys_off[sys], ns = d.sys_off[sys + 1] - o;
+            if (t == 0) {
+                base_set = (int)atomicAdd(&d.ctr[C_NSETS], 1ull);
+                base_mem = (int)atomicAdd(&d.ctr[C_NU], (unsigned long long)ns);
+            }
+            __syncthreads();
+            const int bs = base_set, bm = base_mem;
+            for (int k = t; k < ns; k += blockDim.x) d.set_mem[bm + k] = o + k;
+            if (t == 0) {
+                d.set_start[bs] = bm;
+                d.set_count[bs] = ns;
+                d.set_rc[bs] = INFINITY;
+                if (ns <= kWaveMax)
+                    d.set_list[(int)atomicAdd(&d.ctr[C_NSMALL], 1ull)] = bs;
+                else
+                    d.set_list[d.setcap - 1 - (int)atomicAdd(&d.ctr[C_NBIG], 1ull)] = bs;
+                atomicMax(&d.ctr[C_MAXSET], (unsigned long long)ns);
+                atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
+                atomicAdd(&d.ctr[C_WHOLE], 1ull);
+            }
+            return;
+        }
+    }
     // members sorted by (root rank, rank)
-    int u2 = 1;
+    int u2 = kSetsThreads;
     while (u2 < nu) u2 <<= 1;
     for (int k = t; k < u2; k += blockDim.x)
         ep[k] = (k < nu) ? ((lab[k] << 16) | (unsigned)k) : 0xffffffffu;
     __syncthreads();
-    bitonic_sort_lds(ep, u2);
+    block_sort_u32(ep, u2);
     // global slots of this system's sets and members
     if (t == 0) {
         base_set = (int)atomicAdd(&d.ctr[C_NSETS], (unsigned long long)nsets);
@@ -894,8 +1266,15 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
         if (first) {
             int e = k + 1;
             while (e < nu && lab[e] == lab[k]) ++e;
-            d.set_count[bs + (int)lab[k]] = e - k;
+            const int sid = bs + (int)lab[k];
+            d.set_count[sid] = e - k;
             if ((unsigned)(e - k) > big) big = (unsigned)(e - k);
+            // work lists of the Hermite kernel (their order does not matter:
+            // every set is integrated on its own)
+            if (e - k <= kWaveMax)
+                d.set_list[(int)atomicAdd(&d.ctr[C_NSMALL], 1ull)] = sid;
+            else
+                d.set_list[d.setcap - 1 - (int)atomicAdd(&d.ctr[C_NBIG], 1ull)] = sid;
         }
     }
     if (big) atomicMax(&d.ctr[C_MAXSET], (unsigned long long)big);
@@ -905,22 +1284,86 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
 // ------------------------------------------------------------------------
 // Sec. 2.1 transition function and Sec. 2.2 / 2.3 set kernels
 // ------------------------------------------------------------------------
-__device__ __forceinline__ void transition(double s, double rc, double &K, double &Kp, double &Kpp)
+// sin and cos of x in [0, pi/4] from their Taylor series (Horner in x^2;
+// the first omitted terms are below 1e-19 there)
+__device__ __forceinline__ double inv_factorial(int n)
 {
-    const double y = 1.1 * s / rc - 0.1;
+    double f = 1.0;
+    for (int k = 2; k <= n; ++k) f *= (double)k;
+    return 1.0 / f;
+}
+
+__device__ __forceinline__ void sincos_quarter(double x, double &sn, double &cs)
+{
+    const double z = x * x;
+    double ps = inv_factorial(17);
+    ps = fma(ps, z, -inv_factorial(15));
+    ps = fma(ps, z, inv_factorial(13));
+    ps = fma(ps, z, -inv_factorial(11));
+    ps = fma(ps, z, inv_factorial(9));
+    ps = fma(ps, z, -inv_factorial(7));
+    ps = fma(ps, z, inv_factorial(5));
+    ps = fma(ps, z, -inv_factorial(3));
+    sn = fma(ps * z, x, x);
+    double pc = inv_factorial(18);
+    pc = fma(pc, z, -inv_factorial(16));
+    pc = fma(pc, z, inv_factorial(14));
+    pc = fma(pc, z, -inv_factorial(12));
+    pc = fma(pc, z, inv_factorial(10));
+    pc = fma(pc, z, -inv_factorial(8));
+    pc = fma(pc, z, inv_factorial(6));
+    pc = fma(pc, z, -inv_factorial(4));
+    pc = fma(pc, z, 0.5);
+    cs = fma(-pc, z, 1.0);
+}
+
+// per-set constants of the transition function: y = c1 s - 0.1 with
+// c1 = 1.1 / r_crit, K' = wc cos(pi y / 2), K'' = -wc^2 sin(pi y / 2)
+struct TransConst {
+    double rc2, c1, wc, wc2;
+};
+
+__device__ __forceinline__ TransConst trans_const(double rc)
+{
+    TransConst t;
+    t.rc2 = rc * rc;
+    t.c1 = 1.1 / rc;
+    t.wc = (kPi / 2.0) * t.c1;
+    t.wc2 = t.wc * t.wc;
+    return t;
+}
+
+// K(y) = sin(pi y / 2) on 0 < y < 1 (0 below, 1 above) and its first two
+// derivatives in s.  Above y = 1/2 the complement is used,
+// sin(pi y / 2) = cos(pi (1 - y) / 2), so the series only ever sees
+// arguments in [0, pi/4].
+__device__ __forceinline__ void transition(double s, const TransConst &tc, double &K, double &Kp,
+                                           double &Kpp)
+{
+    const double y = fma(s, tc.c1, -0.1);
     if (y <= 0.0) {
         K = 0.0; Kp = 0.0; Kpp = 0.0;
     } else if (y >= 1.0) {
         K = 1.0; Kp = 0.0; Kpp = 0.0;
     } else {
-        const double w = kPi / 2.0;
-        const double c = 1.1 / rc;
+        const bool lo = y <= 0.5;
         double sn, cs;
-        sincos(w * y, &sn, &cs);
-        K = sn;
-        Kp = w * c * cs;
-        Kpp = -(w * c) * (w * c) * sn;
+        sincos_quarter((kPi / 2.0) * (lo ? y : 1.0 - y), sn, cs);
+        const double sk = lo ? sn : cs, ck = lo ? cs : sn;
+        K = sk;
+        Kp = tc.wc * ck;
+        Kpp = -tc.wc2 * sk;
     }
+}
+
+// 1/s and s from s^2 > 0: the hardware reciprocal square root y0 refined
+// by the binomial series, 1/s = y0 (1 - e)^(-1/2) with e = 1 - s^2 y0^2
+__device__ __forceinline__ void inv_dist(double s2, double &s, double &is)
+{
+    const double y0 = __builtin_amdgcn_rsq(s2);
+    const double e = fma(-s2, y0 * y0, 1.0);
+    is = y0 * fma(e, fma(e, 0.375, 0.5), 1.0);
+    s = s2 * is;
 }
 
 struct HermArgs {
@@ -928,6 +1371,9 @@ struct HermArgs {
     double tau, G, epsH, eta, eta_s;
     int max_substeps;
 };
+
+constexpr int kCoopMin = 1024;      // larger sets run on the whole grid (k_hermite_grid)
+constexpr int kGridThreads = 256;   // workgroup of k_hermite_grid
 
 constexpr int kHermLds = 1024;   // members of one set staged in LDS
 
@@ -956,7 +1402,7 @@ __device__ __forceinline__ double group_sum(double v, int L)
 __device__ void set_pair_acc(const SetLds &S, int n, int a, int l, int L, double G, double rc,
                              double out[3])
 {
-    const double rc2 = rc * rc;
+    const TransConst tc = trans_const(rc);
     const double xi = S.x[a], yi = S.y[a], zi = S.z[a];
     out[0] = out[1] = out[2] = 0.0;
     for (int b = l; b < n; b += L) {
@@ -964,11 +1410,11 @@ __device__ void set_pair_acc(const SetLds &S, int n, int a, int l, int L, double
         const double dd0 = S.x[b] - xi, dd1 = S.y[b] - yi, dd2 = S.z[b] - zi;
         const double s2 = dd0 * dd0 + dd1 * dd1 + dd2 * dd2;
         // beyond r_crit K = 1, K' = 0: W = 0, the pair adds exactly zero
-        if (s2 == 0.0 || s2 >= rc2) continue;
-        const double s = sqrt(s2);
-        const double is = 1.0 / s;
+        if (s2 == 0.0 || s2 >= tc.rc2) continue;
+        double s, is;
+        inv_dist(s2, s, is);
         double K, Kp, Kpp;
-        transition(s, rc, K, Kp, Kpp);
+        transition(s, tc, K, Kp, Kpp);
         const double W = 1.0 - K + s * Kp;
         const double fct = G * S.m[b] * W * (is * is * is);
         out[0] += fct * dd0;
@@ -982,7 +1428,7 @@ __device__ void set_pair_acc(const SetLds &S, int n, int a, int l, int L, double
 __device__ void herm_pairs(const SetLds &S, int n, int a, int l, int L, double G, double rc,
                            double eps, double acc[3], double jrk[3])
 {
-    const double rc2 = rc * rc;
+    const TransConst tc = trans_const(rc);
     const double X0 = S.x[a], X1 = S.y[a], X2 = S.z[a];
     const double U0 = S.u[a], U1 = S.v[a], U2 = S.w[a];
     for (int c = 0; c < 3; ++c) acc[c] = jrk[c] = 0.0;
@@ -992,12 +1438,12 @@ __device__ void herm_pairs(const SetLds &S, int n, int a, int l, int L, double G
         const double w[3] = {S.u[b] - U0, S.v[b] - U1, S.w[b] - U2};
         const double s2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] + eps * eps;
         // beyond r_crit W = 0 and K'' = 0: the pair adds exactly zero
-        if (s2 == 0.0 || s2 >= rc2) continue;
-        const double s = sqrt(s2);
-        const double is = 1.0 / s;
+        if (s2 == 0.0 || s2 >= tc.rc2) continue;
+        double s, is;
+        inv_dist(s2, s, is);
         const double is2 = is * is;
         double K, Kp, Kpp;
-        transition(s, rc, K, Kp, Kpp);
+        transition(s, tc, K, Kp, Kpp);
         const double W = 1.0 - K + s * Kp;
         const double gm = G * S.m[b] * (is2 * is);
         const double gmW = gm * W;
@@ -1024,23 +1470,187 @@ __device__ __forceinline__ void herm_central(const double X[3], const double U[3
     }
 }
 
-// One workgroup per encounter set (grid-stride over sets).  The set's
-// positions, velocities and masses are staged in LDS (in the global member
-// scratch for sets of more than kHermLds members); each member's pair
-// sums are split over L lanes (L = largest power of two with L n <= 256,
-// at most 64) and combined by an xor tree.  Correction at q0 (Sec. 2.3
-// step 5), PEC Hermite over tau with one shared step per set (step 6),
-// correction at q1 (step 7); members written back to the state.
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// a value equal on all lanes (a wave reduction) moved to scalar registers,
+// so the loops and branches that test it are uniform to the compiler too
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// One set of at most kWaveMax members on one wave: member k on lanes
+// [k L, k L + L) (L = largest power of two with L n <= 64), its state in
+// registers of those lanes, the staged set state in the wave's own LDS
+// slice.  Same steps as the workgroup version below (corrections at q0
+// and q1, PEC Hermite with one shared step), with no global memory traffic
+// inside the substep loop.
+__device__ void hermite_set_wave(const HermArgs &a, int sidx, const SetLds &S, int lane,
+                                 int &nsub_out, int &fail_out)
+{
+    const Dev &d = a.d;
+    const int b0 = __builtin_amdgcn_readfirstlane(d.set_start[sidx]);
+    const int n = __builtin_amdgcn_readfirstlane(d.set_count[sidx]);
+    const double rc = d.set_rc[sidx];
+    nsub_out = 0;
+    fail_out = 0;
+    if (n < 1 || n > kWaveMax) return;   // the set kernel lists 1..kWaveMax members here
+    int L = 1;
+    while (2 * L * n <= kHermWave) L <<= 1;
+    const int k = lane / L, l = lane % L;
+    const bool mine = k < n;
+    const int kk = mine ? k : 0;   // idle lanes shadow member 0; their results are dropped
+    const int i = d.set_mem[b0 + kk];
+    const double mu = a.G * d.sys_m0[d.body_sys[i]];
+    const double half = a.tau / 2.0;
+    double X[3] = {d.x0[i], d.y0[i], d.z0[i]};
+    if (mine && l == 0) {
+        S.x[k] = X[0];
+        S.y[k] = X[1];
+        S.z[k] = X[2];
+        S.m[k] = d.m[i];
+    }
+    wave_lds_sync();
+    // step 5: v0 -= tau/2 * sum W-weighted in-set forces at q0
+    double U[3], A[3], J[3];
+    {
+        double acc[3];
+        set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
+        for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+        U[0] = d.vx0[i] - half * acc[0];
+        U[1] = d.vy0[i] - half * acc[1];
+        U[2] = d.vz0[i] - half * acc[2];
+    }
+    if (mine && l == 0) {
+        S.u[k] = U[0];
+        S.v[k] = U[1];
+        S.w[k] = U[2];
+    }
+    wave_lds_sync();
+    // initial force and first step
+    double hloc = INFINITY;
+    herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, A, J);
+    for (int c = 0; c < 3; ++c) {
+        A[c] = group_sum(A[c], L);
+        J[c] = group_sum(J[c], L);
+    }
+    herm_central(X, U, mu, A, J);
+    {
+        const double hb = a.eta_s * dnorm3(A[0], A[1], A[2]) / dnorm3(J[0], J[1], J[2]);
+        if (mine && hb > 0.0) hloc = hb;
+    }
+    double h = wave_uniform(wave_min(hloc));
+    const double sgn = a.tau >= 0.0 ? 1.0 : -1.0;
+    const double T = fabs(a.tau);
+    double tt = 0.0;
+    int nsub = 0, fail = 0;
+    bool last = (T == 0.0);
+    while (!last) {
+        if (nsub >= a.max_substeps) {
+            fail = 1;
+            break;
+        }
+        if (!(h > 0.0) || h >= T - tt) {
+            h = T - tt;
+            last = true;
+        }
+        const double hs = sgn * h;
+        double xp[3], up[3];
+        for (int c = 0; c < 3; ++c) {
+            xp[c] = X[c] + hs * U[c] + hs * hs * A[c] / 2.0 + hs * hs * hs * J[c] / 6.0;
+            up[c] = U[c] + hs * A[c] + hs * hs * J[c] / 2.0;
+        }
+        wave_lds_sync();   // every lane is done reading the previous state
+        if (mine && l == 0) {
+            S.x[k] = xp[0]; S.y[k] = xp[1]; S.z[k] = xp[2];
+            S.u[k] = up[0]; S.v[k] = up[1]; S.w[k] = up[2];
+        }
+        wave_lds_sync();
+        double a1[3], j1[3];
+        herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, a1, j1);
+        for (int c = 0; c < 3; ++c) {
+            a1[c] = group_sum(a1[c], L);
+            j1[c] = group_sum(j1[c], L);
+        }
+        herm_central(xp, up, mu, a1, j1);
+        double A2e[3], A3v[3];
+        for (int c = 0; c < 3; ++c) {
+            const double A2 = (-6.0 * (A[c] - a1[c]) - hs * (4.0 * J[c] + 2.0 * j1[c])) / (hs * hs);
+            const double A3 = (12.0 * (A[c] - a1[c]) + 6.0 * hs * (J[c] + j1[c])) / (hs * hs * hs);
+            X[c] = xp[c] + A2 * hs * hs * hs * hs / 24.0 + A3 * hs * hs * hs * hs * hs / 120.0;
+            U[c] = up[c] + A2 * hs * hs * hs / 6.0 + A3 * hs * hs * hs * hs / 24.0;
+            A[c] = a1[c];
+            J[c] = j1[c];
+            A2e[c] = A2 + hs * A3;
+            A3v[c] = A3;
+        }
+        const double na = dnorm3(a1[0], a1[1], a1[2]), nj = dnorm3(j1[0], j1[1], j1[2]);
+        const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]);
+        const double n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
+        const double hb = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
+        tt += h;
+        ++nsub;
+        h = wave_uniform(wave_min((mine && hb > 0.0) ? hb : INFINITY));
+    }
+    // step 7: v1 -= tau/2 * W-weighted in-set forces at q1, write back
+    wave_lds_sync();
+    if (mine && l == 0) {
+        S.x[k] = X[0];
+        S.y[k] = X[1];
+        S.z[k] = X[2];
+    }
+    wave_lds_sync();
+    double acc[3];
+    set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
+    for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+    if (mine && l == 0) {
+        d.x[i] = X[0];
+        d.y[i] = X[1];
+        d.z[i] = X[2];
+        d.vx[i] = U[0] - half * acc[0];
+        d.vy[i] = U[1] - half * acc[1];
+        d.vz[i] = U[2] - half * acc[2];
+    }
+    wave_lds_sync();   // the slice is reused by the wave's next set
+    nsub_out = nsub;
+    fail_out = fail;
+}
+
+// Sec. 2.3 steps 5-7 for every set.  Sets of more than kWaveMax members
+// first, one workgroup each: positions, velocities and masses staged in LDS
+// (in the global member scratch beyond kHermLds members), each member's pair
+// sums split over L lanes (L = largest power of two with L n <= 512, at most
+// 64) and combined by an xor tree.  Then the small sets, one wave each
+// (hermite_set_wave).  Both take their sets from work queues, so a block or
+// wave that finishes early takes the next set; every set is integrated on
+// its own, so the order changes nothing in the results.
 __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
 {
     const Dev &d = a.d;
     __shared__ double s_x[kHermLds], s_y[kHermLds], s_z[kHermLds];
     __shared__ double s_u[kHermLds], s_v[kHermLds], s_w[kHermLds], s_m[kHermLds];
     __shared__ double lds[kHermThreads];
-    __shared__ int s_fail;
+    __shared__ int s_fail, s_item;
     const int t = threadIdx.x;
-    const int nsets = (int)d.ctr[C_NSETS];
-    for (int sidx = blockIdx.x; sidx < nsets; sidx += gridDim.x) {
+    const int nbig = (int)d.ctr[C_NBIG];
+    int nsub_b = 0, fail_b = 0;   // statistics of thread 0, added after the loop
+    for (;;) {
+        if (t == 0) s_item = (int)atomicAdd(&d.ctr[C_HQB], 1ull);
+        __syncthreads();
+        const int q = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (q >= nbig) break;
+        const int sidx = d.set_list[d.setcap - 1 - q];
+        if (d.set_count[sidx] > kCoopMin) continue;   // k_hermite_grid takes it
+
         const int b0 = d.set_start[sidx];
         const int n = d.set_count[sidx];
         const double rc = d.set_rc[sidx];
@@ -1209,11 +1819,315 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
             }
         }
         if (t == 0) {
-            atomicAdd(&d.ctr[C_SUB], (unsigned long long)nsub);
-            atomicAdd(&d.ctr[C_TSUB], (unsigned long long)nsub);
-            if (s_fail) latch(d.ctr, S_HERMITE);
+            nsub_b += nsub;
+            fail_b |= s_fail;
         }
         __syncthreads();
+    }
+    if (t == 0 && nsub_b > 0) {
+        atomicAdd(&d.ctr[C_SUB], (unsigned long long)nsub_b);
+        atomicAdd(&d.ctr[C_TSUB], (unsigned long long)nsub_b);
+    }
+    if (t == 0 && fail_b) latch(d.ctr, S_HERMITE);
+    // small sets, one wave each, in the wave's slice of the staging arrays
+    const int w = t >> 6, lane = t & 63;
+    const SetLds S = {s_x + w * kWaveMax, s_y + w * kWaveMax, s_z + w * kWaveMax,
+                      s_u + w * kWaveMax, s_v + w * kWaveMax, s_w + w * kWaveMax,
+                      s_m + w * kWaveMax};
+    const int nsmall = (int)d.ctr[C_NSMALL];
+    // The pop has no lane branch: every lane takes part in the atomic (lane
+    // 0 adds one, the others zero) and lane 0's old value, read into a
+    // scalar register, is the wave's item.  A pop under `if (lane == 0)`
+    // followed by a shuffle lets the compiler merge that branch with the
+    // lane-0 statistics branch of the previous iteration, which splits the
+    // wave over two loop nests and leaves the shuffle without lane 0.  The
+    // statistics are therefore also kept out of the loop.
+    int nsub_w = 0, fail_w = 0;
+    for (;;) {
+        const unsigned long long old = atomicAdd(&d.ctr[C_HQS], lane == 0 ? 1ull : 0ull);
+        const int q = __builtin_amdgcn_readfirstlane((int)old);
+        if (q >= nsmall) break;
+        int nsub, fail;
+        hermite_set_wave(a, d.set_list[q], S, lane, nsub, fail);
+        nsub_w += nsub;
+        fail_w |= fail;
+    }
+    if (lane == 0 && nsub_w > 0) {
+        atomicAdd(&d.ctr[C_SUB], (unsigned long long)nsub_w);
+        atomicAdd(&d.ctr[C_TSUB], (unsigned long long)nsub_w);
+    }
+    if (lane == 0 && fail_w) latch(d.ctr, S_HERMITE);
+}
+
+
+// ------------------------------------------------------------------------
+// Sets of more than kCoopMin members (the giant sets a nearly parabolic
+// body makes through its Hill radius, or a whole system): the same steps
+// as k_hermite, spread over the whole grid.  Member k belongs to lane group
+// k mod NG (L lanes, NG = grid lanes / L); its pair sums run over the staged
+// set in global memory; grid-wide barriers separate the phases of a
+// substep, and the step size is the minimum of per-block partial minima
+// read by every block (double-buffered by substep parity), so all blocks
+// take the same sequence of steps.  The barrier waits are bounded: a wait
+// that runs out raises an abort flag that every block polls, every block
+// leaves, and the Hermite status bit is latched.
+// ------------------------------------------------------------------------
+struct GridArgs {
+    HermArgs h;
+    unsigned *bar;      // [0] arrivals (cumulative), [1] generation, [2] abort
+    double *hpart;      // [2][gridDim] per-block step minima
+};
+
+// longest wait at one barrier before giving up, in ticks of the 100 MHz
+// real-time counter (10 s: far beyond any phase of a legitimate set)
+constexpr unsigned long long kGridWaitTicks = 1000000000ull;
+
+// Grid-wide barrier over the arrivals counter (cumulative, so barrier p
+// completes at gridDim * p arrivals) and a generation word.  Every wave
+// fences at agent scope on both sides, so the stores of all blocks before
+// the barrier are visible to all blocks after it.  Returns false when the
+// wait ran out or another block aborted.
+__device__ bool grid_sync(const GridArgs &ga, unsigned &phase, int *s_ok)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned target = phase + 1;
+        const unsigned prev =
+            __hip_atomic_fetch_add(&ga.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev + 1 == gridDim.x * target) {
+            __hip_atomic_store(&ga.bar[1], target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+            while (__hip_atomic_load(&ga.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (__hip_atomic_load(&ga.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                    __builtin_amdgcn_s_memrealtime() - t0 > kGridWaitTicks) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        if (!ok) __hip_atomic_store(&ga.bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *s_ok = ok;
+        phase = target;
+    }
+    __syncthreads();
+    __threadfence();
+    return __builtin_amdgcn_readfirstlane(*s_ok) != 0;
+}
+
+// a failed barrier ends the kernel in this block (the others follow through
+// the abort flag) and reports the set as failed
+#define GSYNC()                                           \
+    do {                                                  \
+        if (!grid_sync(ga, phase, &s_ok)) {               \
+            if (threadIdx.x == 0) latch(d.ctr, S_HERMITE); \
+            return;                                       \
+        }                                                 \
+    } while (0)
+
+__global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
+{
+    const HermArgs &a = ga.h;
+    const Dev &d = a.d;
+    __shared__ double red[kGridThreads];
+    __shared__ int s_ok;
+    const int t = threadIdx.x;
+    const int gtid = blockIdx.x * kGridThreads + t;
+    const int nthr = gridDim.x * kGridThreads;
+    const long long fs = d.memcap;
+    unsigned phase = 0;
+    int par = 0;
+    const int nbig = (int)d.ctr[C_NBIG];
+    for (int q = 0; q < nbig; ++q) {
+        const int sidx = d.set_list[d.setcap - 1 - q];
+        const int n = d.set_count[sidx];
+        if (n <= kCoopMin) continue;
+        const int b0 = d.set_start[sidx];
+        const double rc = d.set_rc[sidx];
+        double *gs = d.hw + (long long)HS * fs + b0;
+        const SetLds S{gs, gs + fs, gs + 2 * fs, gs + 3 * fs, gs + 4 * fs, gs + 5 * fs, gs + 6 * fs};
+        int L = 1;
+        while (L < 64 && 2 * L * n <= nthr) L <<= 1;
+        const int NG = nthr / L;
+        const int g = gtid / L, l = gtid % L;
+        const double mu = a.G * d.sys_m0[d.body_sys[d.set_mem[b0]]];
+        const double half = a.tau / 2.0;
+        // stage q0 and masses
+        for (int k = gtid; k < n; k += nthr) {
+            const int i = d.set_mem[b0 + k];
+            S.x[k] = d.x0[i];
+            S.y[k] = d.y0[i];
+            S.z[k] = d.z0[i];
+            S.m[k] = d.m[i];
+        }
+        GSYNC();
+        // step 5: v0 -= tau/2 * W-weighted in-set forces at q0
+        for (int k0 = 0; k0 < n; k0 += NG) {
+            const int k = k0 + g;
+            const int kk = k < n ? k : 0;
+            double acc[3];
+            set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
+            for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+            if (k < n && l == 0) {
+                const int i = d.set_mem[b0 + k];
+                hw_at(d, HX + 0, b0 + k) = S.x[k];
+                hw_at(d, HX + 1, b0 + k) = S.y[k];
+                hw_at(d, HX + 2, b0 + k) = S.z[k];
+                hw_at(d, HU + 0, b0 + k) = d.vx0[i] - half * acc[0];
+                hw_at(d, HU + 1, b0 + k) = d.vy0[i] - half * acc[1];
+                hw_at(d, HU + 2, b0 + k) = d.vz0[i] - half * acc[2];
+            }
+        }
+        GSYNC();
+        for (int k = gtid; k < n; k += nthr) {
+            S.u[k] = hw_at(d, HU + 0, b0 + k);
+            S.v[k] = hw_at(d, HU + 1, b0 + k);
+            S.w[k] = hw_at(d, HU + 2, b0 + k);
+        }
+        GSYNC();
+        // initial force and first step
+        double hloc = INFINITY;
+        for (int k0 = 0; k0 < n; k0 += NG) {
+            const int k = k0 + g;
+            const int kk = k < n ? k : 0;
+            double acc[3], jr[3];
+            herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, acc, jr);
+            for (int c = 0; c < 3; ++c) {
+                acc[c] = group_sum(acc[c], L);
+                jr[c] = group_sum(jr[c], L);
+            }
+            if (k < n && l == 0) {
+                const double X[3] = {S.x[k], S.y[k], S.z[k]}, U[3] = {S.u[k], S.v[k], S.w[k]};
+                herm_central(X, U, mu, acc, jr);
+                for (int c = 0; c < 3; ++c) {
+                    hw_at(d, HA + c, b0 + k) = acc[c];
+                    hw_at(d, HJ + c, b0 + k) = jr[c];
+                }
+                const double hb =
+                    a.eta_s * dnorm3(acc[0], acc[1], acc[2]) / dnorm3(jr[0], jr[1], jr[2]);
+                if (hb > 0.0 && hb < hloc) hloc = hb;
+            }
+        }
+        {
+            const double bm = block_min<kGridThreads>(hloc, red);
+            if (t == 0) ga.hpart[par * gridDim.x + blockIdx.x] = bm;
+        }
+        GSYNC();
+        double h = INFINITY;
+        for (int b = 0; b < (int)gridDim.x; ++b) h = fmin(h, ga.hpart[par * gridDim.x + b]);
+        par ^= 1;
+        const double sgn = a.tau >= 0.0 ? 1.0 : -1.0;
+        const double T = fabs(a.tau);
+        double tt = 0.0;
+        int nsub = 0, fail = 0;
+        bool last = (T == 0.0);
+        while (!last) {
+            if (nsub >= a.max_substeps) {
+                fail = 1;
+                break;
+            }
+            if (!(h > 0.0) || h >= T - tt) {
+                h = T - tt;
+                last = true;
+            }
+            const double hs = sgn * h;
+            // predict: scratch and the staged copy read by every member's force
+            for (int k = gtid; k < n; k += nthr) {
+                double xp[3], up[3];
+                for (int c = 0; c < 3; ++c) {
+                    const double x = hw_at(d, HX + c, b0 + k), u = hw_at(d, HU + c, b0 + k);
+                    const double ac = hw_at(d, HA + c, b0 + k), jc = hw_at(d, HJ + c, b0 + k);
+                    xp[c] = x + hs * u + hs * hs * ac / 2.0 + hs * hs * hs * jc / 6.0;
+                    up[c] = u + hs * ac + hs * hs * jc / 2.0;
+                    hw_at(d, HXP + c, b0 + k) = xp[c];
+                    hw_at(d, HUP + c, b0 + k) = up[c];
+                }
+                S.x[k] = xp[0]; S.y[k] = xp[1]; S.z[k] = xp[2];
+                S.u[k] = up[0]; S.v[k] = up[1]; S.w[k] = up[2];
+            }
+            GSYNC();
+            double hn = INFINITY;
+            for (int k0 = 0; k0 < n; k0 += NG) {
+                const int k = k0 + g;
+                const int kk = k < n ? k : 0;
+                double a1[3], j1[3];
+                herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, a1, j1);
+                for (int c = 0; c < 3; ++c) {
+                    a1[c] = group_sum(a1[c], L);
+                    j1[c] = group_sum(j1[c], L);
+                }
+                if (k < n && l == 0) {
+                    const double X[3] = {S.x[k], S.y[k], S.z[k]}, U[3] = {S.u[k], S.v[k], S.w[k]};
+                    herm_central(X, U, mu, a1, j1);
+                    double A2e[3], A3v[3];
+                    for (int c = 0; c < 3; ++c) {
+                        const double a0c = hw_at(d, HA + c, b0 + k), j0c = hw_at(d, HJ + c, b0 + k);
+                        const double A2 =
+                            (-6.0 * (a0c - a1[c]) - hs * (4.0 * j0c + 2.0 * j1[c])) / (hs * hs);
+                        const double A3 =
+                            (12.0 * (a0c - a1[c]) + 6.0 * hs * (j0c + j1[c])) / (hs * hs * hs);
+                        const double xp = hw_at(d, HXP + c, b0 + k), up = hw_at(d, HUP + c, b0 + k);
+                        hw_at(d, HX + c, b0 + k) =
+                            xp + A2 * hs * hs * hs * hs / 24.0 + A3 * hs * hs * hs * hs * hs / 120.0;
+                        hw_at(d, HU + c, b0 + k) =
+                            up + A2 * hs * hs * hs / 6.0 + A3 * hs * hs * hs * hs / 24.0;
+                        hw_at(d, HA + c, b0 + k) = a1[c];
+                        hw_at(d, HJ + c, b0 + k) = j1[c];
+                        A2e[c] = A2 + hs * A3;
+                        A3v[c] = A3;
+                    }
+                    const double na = dnorm3(a1[0], a1[1], a1[2]), nj = dnorm3(j1[0], j1[1], j1[2]);
+                    const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]);
+                    const double n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
+                    const double hb = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
+                    if (hb > 0.0 && hb < hn) hn = hb;
+                }
+            }
+            {
+                const double bm = block_min<kGridThreads>(hn, red);
+                if (t == 0) ga.hpart[par * gridDim.x + blockIdx.x] = bm;
+            }
+            GSYNC();
+            double hnext = INFINITY;
+            for (int b = 0; b < (int)gridDim.x; ++b) hnext = fmin(hnext, ga.hpart[par * gridDim.x + b]);
+            par ^= 1;
+            tt += h;
+            ++nsub;
+            h = hnext;
+        }
+        // step 7: stage q1, v1 -= tau/2 * W-weighted in-set forces at q1
+        for (int k = gtid; k < n; k += nthr) {
+            S.x[k] = hw_at(d, HX + 0, b0 + k);
+            S.y[k] = hw_at(d, HX + 1, b0 + k);
+            S.z[k] = hw_at(d, HX + 2, b0 + k);
+        }
+        GSYNC();
+        for (int k0 = 0; k0 < n; k0 += NG) {
+            const int k = k0 + g;
+            const int kk = k < n ? k : 0;
+            double acc[3];
+            set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
+            for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+            if (k < n && l == 0) {
+                const int i = d.set_mem[b0 + k];
+                d.x[i] = S.x[k];
+                d.y[i] = S.y[k];
+                d.z[i] = S.z[k];
+                d.vx[i] = hw_at(d, HU + 0, b0 + k) - half * acc[0];
+                d.vy[i] = hw_at(d, HU + 1, b0 + k) - half * acc[1];
+                d.vz[i] = hw_at(d, HU + 2, b0 + k) - half * acc[2];
+            }
+        }
+        if (gtid == 0) {
+            atomicAdd(&d.ctr[C_SUB], (unsigned long long)nsub);
+            atomicAdd(&d.ctr[C_TSUB], (unsigned long long)nsub);
+            if (fail) latch(d.ctr, S_HERMITE);
+        }
+        // every block is done with this set's staging before the next one
+        GSYNC();
     }
 }
 

@@ -30,6 +30,9 @@ stand in for it:
   65,536-planetesimal disk with the 4 planets (disk16k distributions, seed 6).
 * ``guess_init`` Glorot-uniform starting weights of the 4-32-32-1 network,
   zero biases, rounded to float32; seed 7.
+* ``two_planet_encounter`` two Jupiter-mass planets on circular orbits at
+  5.2 and 5.45 (inside three mutual Hill radii) with small bodies
+  (m = 1e-9, a ~ U[4, 7], e ~ U[0, 0.05], i ~ U[0, 0.02]) around them.
 
 Positions are heliocentric; velocities are barycentric, i.e. the heliocentric
 velocity minus sum_j m_j u_j / (m0 + sum_j m_j) (the democratic-heliocentric
@@ -264,3 +267,17 @@ def guess_init(seed: int = 7) -> np.ndarray:
     w = np.concatenate(parts).astype(np.float32).astype(np.float64)
     assert w.size == 1249
     return w
+
+
+def two_planet_encounter(n_small: int = 8, seed: int = 3, G: float = 1.0,
+                         m0: float = 1.0) -> System:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = np.concatenate([[1e-3, 1e-3], np.full(n_small, 1e-9)])
+    a = np.concatenate([[5.2, 5.45], rng.uniform(4.0, 7.0, n_small)])
+    e = np.concatenate([[0.0, 0.0], rng.uniform(0, 0.05, n_small)])
+    inc = np.concatenate([[0.0, 0.001], rng.uniform(0, 0.02, n_small)])
+    ang = rng.uniform(0, 2 * np.pi, (3, n_small + 2))
+    ang[:, 0] = 0.0
+    ang[:, 1] = [0.0, 0.0, 0.02]
+    q, u = elements_to_cartesian(G * m0, a, e, inc, ang[0], ang[1], ang[2])
+    return System("two_planets", G, m0, m, q, _to_barycentric(m0, m, u))

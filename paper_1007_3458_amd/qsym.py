@@ -34,7 +34,8 @@ class Params(C.Structure):
     _fields_ = [("G", C.c_double), ("aE", C.c_double), ("aH", C.c_double), ("epsH", C.c_double),
                 ("eta", C.c_double), ("eta_s", C.c_double), ("crude_safety", C.c_double),
                 ("hill_mode", C.c_int32), ("kepler_mode", C.c_int32), ("precision", C.c_int32),
-                ("max_substeps", C.c_int32), ("pair_capacity", C.c_int64)]
+                ("max_substeps", C.c_int32), ("pair_capacity", C.c_int64),
+                ("planet_mass", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -43,7 +44,8 @@ class Stats(C.Structure):
                 ("total_encounters", C.c_int64), ("total_substeps", C.c_int64),
                 ("kepler_iters", C.c_int64), ("kepler_max", C.c_int64),
                 ("kepler_hist", C.c_int64 * 32), ("status", C.c_int64),
-                ("phase_us", C.c_double * 12), ("phase_calls", C.c_int64 * 12)]
+                ("phase_us", C.c_double * 12), ("phase_calls", C.c_int64 * 12),
+                ("whole_system", C.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -57,7 +59,8 @@ PHASES = ["drift+prepass", "kick+crude", "apply+kepler", "fine", "sets", "hermit
           "apply2+momentum", "drift2", "energy", "momentum", "other"]
 
 DEFAULTS = dict(G=1.0, aE=3.0, aH=1.0, epsH=1e-8, eta=0.02, eta_s=0.01, crude_safety=1.1,
-                hill_mode=0, kepler_mode=0, precision=0, max_substeps=100000, pair_capacity=0)
+                hill_mode=0, kepler_mode=0, precision=0, max_substeps=100000, pair_capacity=0,
+                planet_mass=0.0)
 
 
 def make_params(**kw) -> Params:
@@ -69,7 +72,7 @@ def make_params(**kw) -> Params:
     return Params(float(d["G"]), float(d["aE"]), float(d["aH"]), float(d["epsH"]), float(d["eta"]),
                   float(d["eta_s"]), float(d["crude_safety"]), int(d["hill_mode"]),
                   int(d["kepler_mode"]), int(d["precision"]), int(d["max_substeps"]),
-                  int(d["pair_capacity"]))
+                  int(d["pair_capacity"]), float(d["planet_mass"]))
 
 
 _lib = None
@@ -101,8 +104,8 @@ SIGNATURES = {
                        [C.c_void_p] * 7 + [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p]),
     "qsym_set_kick_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int64,
-                                      C.c_int32]),
-    "qsym_get_kick_shape": (C.c_int, [C.c_void_p, C.c_int32, _ip, _ip, _lp, _ip]),
+                                      C.c_int32, C.c_int32]),
+    "qsym_get_kick_shape": (C.c_int, [C.c_void_p, C.c_int32, _ip, _ip, _lp, _ip, _ip]),
     "qsym_autotune": (C.c_int, [C.c_void_p, C.c_double, _dp]),
     "qsym_profile": (C.c_int, [C.c_void_p, C.c_int32]),
     "qsym_set_guess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
@@ -220,7 +223,8 @@ class Context:
             if e:
                 for w, key in ((0, "plain"), (1, "crude")):
                     sh = e[key]
-                    self.set_kick_shape(sh["ipl"], sh["block"], sh["jchunk"], sh["remap"], which=w)
+                    self.set_kick_shape(sh["ipl"], sh["block"], sh["jchunk"], sh["remap"], which=w,
+                                        sym=sh.get("sym", 0))
                 self.tuned = e
         if self.params.kepler_mode == 2 and guess is not None:
             if isinstance(guess, str) and guess == "packaged":
@@ -312,16 +316,17 @@ class Context:
         self._c(lib().qsym_apply_kepler(self.ctx, float(dt)))
 
     # -------------------------------------------------------- tuning
-    def set_kick_shape(self, ipl, block, jchunk, remap=1, which=-1):
-        """which: 0 plain kick, 1 kick with the crude sweep, -1 both."""
-        self._c(lib().qsym_set_kick_shape(self.ctx, which, ipl, block, jchunk, remap))
+    def set_kick_shape(self, ipl, block, jchunk, remap=1, which=-1, sym=0):
+        """which: 0 plain kick, 1 kick with the crude sweep, -1 both; sym > 0
+        selects the symmetric kick with sym i-blocks per work item."""
+        self._c(lib().qsym_set_kick_shape(self.ctx, which, ipl, block, jchunk, remap, sym))
 
     def kick_shape(self, which=1):
-        a, b, r = C.c_int32(), C.c_int32(), C.c_int32()
+        a, b, r, y = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         j = C.c_int64()
         self._c(lib().qsym_get_kick_shape(self.ctx, which, C.byref(a), C.byref(b), C.byref(j),
-                                          C.byref(r)))
-        return dict(ipl=a.value, block=b.value, jchunk=j.value, remap=r.value)
+                                          C.byref(r), C.byref(y)))
+        return dict(ipl=a.value, block=b.value, jchunk=j.value, remap=r.value, sym=y.value)
 
     def autotune(self, tau):
         """Tune both kick shapes; returns (plain_us, crude_us)."""

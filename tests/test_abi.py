@@ -43,8 +43,8 @@ def test_workspace_bytes_and_validation():
 
 def test_params_struct_layout_matches_header():
     from paper_1007_3458_amd import qsym
-    assert C.sizeof(qsym.Params) == 7 * 8 + 4 * 4 + 8
-    assert C.sizeof(qsym.Stats) == 10 * 8 + 32 * 8 + 8 + 12 * 8 + 12 * 8
+    assert C.sizeof(qsym.Params) == 7 * 8 + 4 * 4 + 8 + 8
+    assert C.sizeof(qsym.Stats) == 10 * 8 + 32 * 8 + 8 + 12 * 8 + 12 * 8 + 8
 
 
 def test_product_path_does_not_import_oracle():
@@ -56,3 +56,30 @@ def test_product_path_does_not_import_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
                 assert "qsym_oracle" not in src and "liboracle" not in src, f
+
+
+def test_params_and_stats_match_the_c_header(tmp_path):
+    """Sizes and field offsets of the ctypes mirrors equal the C compiler's."""
+    import shutil
+    import subprocess
+    from paper_1007_3458_amd import qsym
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    fields = [f for f, _ in qsym.Params._fields_]
+    sfields = [f for f, _ in qsym.Stats._fields_]
+    src = tmp_path / "probe.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "qsym.h"', 'int main(void) {',
+             'printf("%zu %zu\\n", sizeof(qsym_params), sizeof(qsym_stats_t));']
+    lines += [f'printf("%zu\\n", offsetof(qsym_params, {f}));' for f in fields]
+    lines += [f'printf("%zu\\n", offsetof(qsym_stats_t, {f}));' for f in sfields]
+    lines += ['return 0; }']
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.check_call([gcc, "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    sp, ss = int(out[0]), int(out[1])
+    assert sp == C.sizeof(qsym.Params) and ss == C.sizeof(qsym.Stats)
+    offs = [int(x) for x in out[2:]]
+    assert offs[:len(fields)] == [getattr(qsym.Params, f).offset for f in fields]
+    assert offs[len(fields):] == [getattr(qsym.Stats, f).offset for f in sfields]

@@ -54,7 +54,12 @@ SYSTEMS = {
 }
 
 SHAPES = [dict(ipl=1, block=128, jchunk=128, remap=0), dict(ipl=2, block=256, jchunk=256, remap=1),
-          dict(ipl=4, block=256, jchunk=512, remap=1), dict(ipl=2, block=128, jchunk=384, remap=1)]
+          dict(ipl=4, block=256, jchunk=512, remap=1), dict(ipl=2, block=128, jchunk=384, remap=1),
+          # symmetric kick: each unordered pair once, reaction on j
+          dict(ipl=1, block=128, jchunk=128, remap=0, sym=1),
+          dict(ipl=2, block=128, jchunk=256, remap=1, sym=2),
+          dict(ipl=2, block=256, jchunk=1024, remap=1, sym=1),
+          dict(ipl=4, block=128, jchunk=512, remap=0, sym=4)]
 
 
 @pytest.mark.parametrize("name", list(SYSTEMS))
@@ -75,12 +80,15 @@ def test_kick_parity(Q, orc, name, shape):
 
 
 @pytest.mark.parametrize("name", list(SYSTEMS))
-def test_crude_candidates_match(Q, orc, name):
+@pytest.mark.parametrize("shape", [None, 4, 6])
+def test_crude_candidates_match(Q, orc, name, shape):
     s = SYSTEMS[name]()
-    say("crude candidates", name)
+    say("crude candidates", name, shape)
     p = orc.make_params()
     tau = 0.05
     ctx = Q.Context(s)
+    if shape is not None:
+        ctx.set_kick_shape(**SHAPES[shape])
     ctx.apply_kick(0.0, crude_tau=tau)
     got = {tuple(x) for x in ctx.candidates()}
     A, ve = orc.prepass(1.0, s.q, s.v)
@@ -368,4 +376,53 @@ def test_set_larger_than_lds_stage(Q, orc):
     qo, vo, res = orc.step(orc.make_params(), 0.05, s.m, s.h, s.q, s.v)
     assert res.stats["max_set"] == st["max_set"]
     assert per_body_rel(qg, qo) < 1e-12 and per_body_rel(vg, vo) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("sym", [1, 2])
+def test_symmetric_kick_lockstep_steps(Q, orc, sym):
+    """Whole hybrid steps with the symmetric kick for both kicks equal the
+    oracle steps (the step never depends on the kick shape beyond rounding)."""
+    s = crowded(300, 3)
+    say("symmetric kick steps", sym)
+    ctx = Q.Context(s)
+    ctx.set_kick_shape(2, 128, 256, 1, sym=sym)
+    p = orc.make_params()
+    q, v = s.q, s.v
+    for k in range(3):
+        ctx.set_state(s.m, s.h, q, v)
+        ctx.step(0.05, 1)
+        qg, vg = ctx.get_state()
+        pg, _ = ctx.encounters()
+        q, v, r = orc.step(p, 0.05, s.m, s.h, q, v)
+        assert per_body_rel(qg, q) < 1e-12 and per_body_rel(vg, v) < 1e-12
+        assert {tuple(x) for x in pg} == {tuple(x) for x in r.pairs}
+    ctx.close()
+
+
+def test_symmetric_kick_full_size_and_batched(Q, orc):
+    s = inputs.disk16k()
+    say("symmetric kick disk16k")
+    s0 = s.copy()
+    s0.v[:] = 0.0
+    ctx = Q.Context(s0)
+    ctx.set_kick_shape(2, 256, 1024, 1, sym=1)
+    ctx.apply_kick(1.0)
+    _, a = ctx.get_state()
+    rows = np.arange(0, s.n, 97)
+    ao = orc.accel_rows(s.G, s.m, s.q, rows)
+    assert per_body_rel(a[rows], ao) < 1e-13
+    ctx.close()
+    sizes = [64, 300, 1, 2, 777, 130]
+    systems = [inputs.batch_system(k, n) for k, n in enumerate(sizes)]
+    for b in systems:
+        b.v[:] = 0.0
+    ctx = Q.Context(systems)
+    ctx.set_kick_shape(1, 128, 128, 0, sym=2)
+    ctx.apply_kick(1.0)
+    _, a = ctx.get_state()
+    off = ctx.offsets
+    for k, b in enumerate(systems):
+        sl = slice(off[k], off[k + 1])
+        assert per_body_rel(a[sl], orc.accel(b.G, b.m, b.q)) < 1e-13
     ctx.close()

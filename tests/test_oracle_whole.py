@@ -13,21 +13,8 @@ from paper_1007_3458_amd import inputs
 
 
 def _two_planet_system(n_small=8, seed=3):
-    """Two Jupiter-mass planets 0.25 apart at 5.2 (inside 3 mutual Hill
-    radii) and a few small bodies around them."""
-    mu = 1.0
-    rng = np.random.Generator(np.random.PCG64(seed))
-    m = np.concatenate([[1e-3, 1e-3], np.full(n_small, 1e-9)])
-    a = np.concatenate([[5.2, 5.45], rng.uniform(4.0, 7.0, n_small)])
-    e = np.concatenate([[0.0, 0.0], rng.uniform(0, 0.05, n_small)])
-    inc = np.concatenate([[0.0, 0.001], rng.uniform(0, 0.02, n_small)])
-    ang = rng.uniform(0, 2 * np.pi, (3, n_small + 2))
-    ang[:, 0] = 0.0
-    ang[:, 1] = [0.0, 0.0, 0.02]
-    q, v = inputs.elements_to_cartesian(mu, a, e, inc, ang[0], ang[1], ang[2])
-    v = v - (m[:, None] * v).sum(0) / (1.0 + m.sum())
-    h = np.cbrt(m / 3.0)
-    return m, h, q, v
+    s = inputs.two_planet_encounter(n_small, seed)
+    return s.m, s.h, s.q, s.v
 
 
 def test_rule_fires_only_for_two_planets_in_one_set(orc):
@@ -107,4 +94,4 @@ def test_whole_system_energy_across_planet_encounter(orc):
             qq, vv, _ = orc.step(p, 0.05, m, h, qq, vv)
             w = max(w, abs(orc.energy(G, m0, m, qq, vv) / E0 - 1))
         worst[pm] = w
-    assert worst[1e-4] < worst[0.0]
+    assert worst[1e-4] < 0.01 * worst[0.0]
