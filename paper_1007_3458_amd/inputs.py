@@ -160,6 +160,17 @@ def make_disk(name, seed, n_disk, m_disk, a_lo, a_hi, e_dist, i_dist, e_par, i_p
     return System(name, G, m0, m, q, v)
 
 
+def enhanced_outer(seed: int, scale: float = 50.0, G: float = 1.0, m0: float = 1.0) -> System:
+    """The four giant planets with their masses multiplied by ``scale`` (an
+    unstable configuration with planet-planet encounters), at a = 5.2, 9.5,
+    19.2, 30.1 with e ~ U[0, 0.05], i ~ U[0, 0.02] and uniform angles (seeded
+    elements stand in for the unpublished epoch elements)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m, a, e, inc, ang = _draw_planets(rng, PLANET_M * scale, PLANET_A)
+    q, u = elements_to_cartesian(G * m0, a, e, inc, ang[0], ang[1], ang[2])
+    return System(f"outer_x{scale:g}_s{seed}", G, m0, m, q, _to_barycentric(m0, m, u))
+
+
 def small(seed: int = 1) -> System:
     """4 planets + 100 planetesimals (the oracle-sized case)."""
     return make_disk("small", seed, 100, 1e-9, 20.0, 35.0, "uniform", "uniform", 0.1, 0.05)
