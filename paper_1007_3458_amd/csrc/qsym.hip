@@ -79,6 +79,16 @@ long long jchunk_min_for(const std::vector<long long> &off)
     return jm;
 }
 
+// partial-sum slots of a system of n bodies: up to ceil(n / jchunk_min)
+// i-side slots (one per j-chunk), and for the symmetric kick one j-side slot
+// per i-range of at least 128 bodies, at most kSMax * 2 of them
+long long partial_slots(long long n, long long jchunk_min)
+{
+    const long long si = (n + jchunk_min - 1) / jchunk_min;
+    const long long sj = std::min<long long>((n + 127) / 128, 2 * kSMax);
+    return si + sj;
+}
+
 Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
 {
     Layout L;
@@ -92,13 +102,10 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     L.n_eitems = 0;
     for (int s = 0; s < nsys; ++s) {
         const long long n = off[s + 1] - off[s];
-        // partial slots: up to S j-chunks, and as many again for the
-        // reaction slots of the symmetric kick
-        const long long S = (n + L.jchunk_min - 1) / L.jchunk_min;
-        L.acc_len += 3 * (2 * S) * n;
+        L.acc_len += 3 * partial_slots(n, L.jchunk_min) * n;
         L.nchunks += (n + kChunk - 1) / kChunk;
         L.nkchunks += (n + kChunkK - 1) / kChunkK;
-        L.max_items += ((n + 127) / 128) * S;
+        L.max_items += ((n + 127) / 128) * ((n + L.jchunk_min - 1) / L.jchunk_min);
         L.n_eitems += ((n + 255) / 256) * ((n + 1023) / 1024);
     }
     L.acc_len = std::max<long long>(L.acc_len, 3);
@@ -312,7 +319,7 @@ void build_tables(qsym_ctx *c)
         const int n = nsys_bodies(c->off, s);
         T.sys_off[s] = (int)c->off[s];
         T.sys_poff[s] = poff;
-        poff += 3LL * (2 * ((n + c->L.jchunk_min - 1) / c->L.jchunk_min)) * n;
+        poff += 3LL * partial_slots(n, c->L.jchunk_min) * n;
         T.sys_c0[s] = (int)T.bchunk.size();
         for (int b = 0; b < n; b += kChunk)
             T.bchunk.push_back(make_int4(s, (int)c->off[s] + b, std::min(kChunk, n - b), 0));
@@ -392,7 +399,7 @@ int upload_shape(qsym_ctx *c, int which)
         const long long ns = nsys_bodies(c->off, s);
         const long long Smax = (ns + c->L.jchunk_min - 1) / c->L.jchunk_min;
         const long long slots = sysK[s].x + (sysK[s].z > 0 ? (ns + sysK[s].z - 1) / sysK[s].z : 0);
-        if (sysK[s].x > Smax || slots > 2 * Smax)
+        if (sysK[s].x > Smax || slots > partial_slots(ns, c->L.jchunk_min))
             return fail(c, QSYM_EINVAL, "j-chunk smaller than the workspace allows");
     }
     c->nitems[which] = n;
@@ -417,16 +424,20 @@ hipError_t launch_kick_bs(qsym_ctx *c, int mode, int prec, hipStream_t st)
                 1.875, 1.5};
     const dim3 g(c->shape[w].remap ? c->grid_kick[w] : std::max(c->nitems[w], 1)), b(BS);
     if (c->shape[w].sym) {
-        if (prec == 0) {
-            if (mode == 0) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 0, 0>), g, b, 0, st, ka);
-            else if (mode == 1) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 1, 0>), g, b, 0, st, ka);
-            else hipLaunchKernelGGL((k_kick_sym<BS, IPL, 2, 0>), g, b, 0, st, ka);
-        } else {
-            if (mode == 0) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 0, 1>), g, b, 0, st, ka);
-            else if (mode == 1) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 1, 1>), g, b, 0, st, ka);
-            else hipLaunchKernelGGL((k_kick_sym<BS, IPL, 2, 1>), g, b, 0, st, ka);
+        // one or two i per lane (the shape check admits no other)
+        if constexpr (IPL <= 2) {
+            if (prec == 0) {
+                if (mode == 0) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 0, 0>), g, b, 0, st, ka);
+                else if (mode == 1) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 1, 0>), g, b, 0, st, ka);
+                else hipLaunchKernelGGL((k_kick_sym<BS, IPL, 2, 0>), g, b, 0, st, ka);
+            } else {
+                if (mode == 0) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 0, 1>), g, b, 0, st, ka);
+                else if (mode == 1) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 1, 1>), g, b, 0, st, ka);
+                else hipLaunchKernelGGL((k_kick_sym<BS, IPL, 2, 1>), g, b, 0, st, ka);
+            }
+            return hipGetLastError();
         }
-        return hipGetLastError();
+        return hipErrorInvalidValue;
     }
     if (prec == 0) {
         if (mode == 0) hipLaunchKernelGGL((k_kick<BS, IPL, 0, 0>), g, b, 0, st, ka);
@@ -1082,7 +1093,7 @@ int qsym_set_kick_shape(qsym_ctx *c, int32_t which, int32_t ipl, int32_t block, 
         (block != 128 && block != 256) || jchunk <= 0 || jchunk % block ||
         jchunk < c->L.jchunk_min || (remap != 0 && remap != 1) ||
         (sym != 0 && sym != 1 && sym != 2 && sym != 4 && sym != 8) ||
-        (sym && jchunk % ((long long)block * ipl)))
+        (sym && (ipl > 2 || jchunk % ((long long)block * ipl))))
         return fail(c, QSYM_EINVAL, "kick shape out of range");
     for (int w = 0; w < 2; ++w) {
         if (which >= 0 && w != which) continue;
@@ -1139,11 +1150,13 @@ int qsym_autotune(qsym_ctx *c, double tau, double *us)
                      jc *= 2) {
                     const long long jcr = (jc + blocks[bi] - 1) / blocks[bi] * blocks[bi];
                     for (int rm = 0; rm < 2; ++rm) cand.push_back(Shape{ipls[ii], blocks[bi], jcr, rm, 0});
+                    // symmetric kick: one or two i per lane
                     const long long BI = (long long)blocks[bi] * ipls[ii];
                     const long long jcs = (jc + BI - 1) / BI * BI;
-                    for (int sy = 1; sy <= 4; sy *= 2)
-                        for (int rm = 0; rm < 2; ++rm)
-                            cand.push_back(Shape{ipls[ii], blocks[bi], jcs, rm, sy});
+                    if (ipls[ii] <= 2)
+                        for (int sy = 1; sy <= 4; sy *= 2)
+                            for (int rm = 0; rm < 2; ++rm)
+                                cand.push_back(Shape{ipls[ii], blocks[bi], jcs, rm, sy});
                 }
         for (const Shape &sh : cand) {
             c->shape[w] = sh;

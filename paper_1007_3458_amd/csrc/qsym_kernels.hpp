@@ -466,33 +466,49 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
 // ------------------------------------------------------------------------
 // Symmetric kick (Newton's third law): each unordered pair once.  A work
 // item is a chunk of j-bodies [j0, j0 + nj) and a range of i-blocks
-// [i0, i0 + ni) (blocks of BI = BS * IPL bodies).  An i-block starting at
-// ib meets only the part j >= ib of the chunk, and in the tiles that overlap
-// the i-block only j > i, so every pair i < j of the system is met exactly
-// once over all items.  The force on i goes to its i-side slot `chunk`
-// (written as by k_kick); the reaction on j is summed over the lanes of a
-// wave (fixed xor tree) and over the waves in order, then added to the
-// item's own j-side slot `slot`, which the item first clears for every j of
-// the chunk (each entry is only ever touched by one thread of one item, so
-// no atomics and a fixed order).  Per pair: 21 VALU instructions for both
-// forces instead of 2 x 17.
+// [i0, i0 + ni) (blocks of BS * IPL bodies, IPL = 1 or 2 per thread).  An
+// i-block starting at ib meets only the part j >= ib of the chunk.  Each
+// wave owns 64 IPL i (IPL per lane, in groups of 64) and meets the j-tile in
+// sub-tiles of 64: in step k lane l pairs its i with sub-tile entry
+// (l + k) mod 64, so the 64 lanes touch 64 different j and the reaction on
+// each j travels with it in three registers that move one lane down after
+// every step (both i of a lane add to it); after 64 steps
+// every lane holds the whole reaction on "its" j again.  For each lane
+// group a sub-tile that starts before the group's i is skipped, the one
+// that starts at it keeps only the pairs l < (l + k) mod 64, so every pair
+// i < j of the system is met exactly once over all items.  The force on i
+// goes to its i-side slot
+// `chunk` (as written by k_kick); the reactions of the waves are added in
+// wave order and then to the item's own j-side slot `slot`, which the item
+// first clears for every j of the chunk.  Each slot entry is only ever
+// touched by one thread of one item: no atomics, a fixed order.  Per pair:
+// one pair term for both forces (21 VALU instructions, one rsq) and 6/IPL
+// instructions of lane rotation (DPP), against 2 x 17 for the two ordered
+// pairs of k_kick.  The sub-tile sits twice in a row in LDS, so
+// entry l + k needs no wrap-around and every read takes its offset from
+// the instruction.
 // ------------------------------------------------------------------------
 
-__device__ __forceinline__ double wave_sum_xor(double v)
+// lane l receives v of lane (l + 1) mod 64: DPP wave_rol:1 (control 0x134)
+// on both halves, every row and bank enabled (its lane layout checked on
+// the device: lane l reads lane l + 1, lane 63 lane 0)
+__device__ __forceinline__ double lane_rotate1(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x134, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x134, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // FP64 pair of the symmetric kick: force on i into (ax, ay, az), reaction
-// on j added to (fx, fy, fz); keep = false drops the pair (j <= i)
-__device__ __forceinline__ void pair_sym64(const double4 &pj, double xi, double yi, double zi,
-                                           double gmi, double seed, double c158, double c32,
-                                           bool keep, double &ax, double &ay, double &az,
-                                           double &fx, double &fy, double &fz, double &r2)
+// on j into (fx, fy, fz); keep = false drops the pair
+__device__ __forceinline__ void pair_sym64(double xj, double yj, double zj, double gmj, double xi,
+                                           double yi, double zi, double gmi, double seed,
+                                           double c158, double c32, bool keep, double &ax,
+                                           double &ay, double &az, double &fx, double &fy,
+                                           double &fz, double &r2)
 {
-    const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
+    const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
     r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, seed)));
     const double y0 = __builtin_amdgcn_rsq(r2);
     const double y2 = y0 * y0;
@@ -500,7 +516,7 @@ __device__ __forceinline__ void pair_sym64(const double4 &pj, double xi, double 
     const double w = fma(e, fma(e, c158, c32), 1.0);
     double r3 = (y2 * y0) * w;
     if (!keep) r3 = 0.0;
-    const double msj = pj.w * r3, msi = gmi * r3;
+    const double msj = gmj * r3, msi = gmi * r3;
     ax = fma(msj, dx, ax);
     ay = fma(msj, dy, ay);
     az = fma(msj, dz, az);
@@ -510,17 +526,17 @@ __device__ __forceinline__ void pair_sym64(const double4 &pj, double xi, double 
 }
 
 // FP32 form: r^-3 from the FP32 rsq on the FP64 r^2 (as pair32)
-__device__ __forceinline__ void pair_sym32(const double4 &pj, float mjf, double xi, double yi,
-                                           double zi, float mif, bool keep, double &ax, double &ay,
-                                           double &az, double &fx, double &fy, double &fz,
-                                           double &r2)
+__device__ __forceinline__ void pair_sym32(double xj, double yj, double zj, double gmj, double xi,
+                                           double yi, double zi, float mif, bool keep, double &ax,
+                                           double &ay, double &az, double &fx, double &fy,
+                                           double &fz, double &r2)
 {
-    const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
+    const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
     r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, 1e-24)));
     const float y = __builtin_amdgcn_rsqf((float)r2);
     float r3 = y * y * y;
     if (!keep) r3 = 0.0f;
-    const double msj = (double)(mjf * r3), msi = (double)(mif * r3);
+    const double msj = (double)((float)gmj * r3), msi = (double)(mif * r3);
     ax = fma(msj, dx, ax);
     ay = fma(msj, dy, ay);
     az = fma(msj, dz, az);
@@ -529,10 +545,82 @@ __device__ __forceinline__ void pair_sym32(const double4 &pj, float mjf, double 
     fz = fma(-msi, dz, fz);
 }
 
+// How one lane group of 64 i meets a sub-tile of 64 j: all pairs (the
+// sub-tile lies past the group), the pairs l < (l + k) mod 64 (the sub-tile
+// is the group itself), or none (the sub-tile lies before it).
+enum { SYM_FULL = 0, SYM_DIAG = 1, SYM_SKIP = 2 };
+
+// 64 rotation steps of one wave over one sub-tile; lane group u (i_u =
+// u-th i of the lane) meets it as M0 (u = 0) / M1 (u = 1).  s* point at
+// the doubled sub-tile (x, y, z, G m rows of 128).  Crude-sweep hits are
+// queued as (i - ib) << 16 | (j - jt).
+template <int MODE, int PREC, int IPL, int M0, int M1>
+__device__ __forceinline__ void sym_subtile(const double *sx, const double *sy, const double *sz,
+                                            const double *sm, int lane, const double *xi,
+                                            const double *yi, const double *zi, const double *gmi,
+                                            const float *mif, const double *th2, const int *lt,
+                                            double seed, double c158, double c32, double *ax,
+                                            double *ay, double *az, double &fx, double &fy,
+                                            double &fz, unsigned *qbuf, unsigned *qn, int jsub)
+{
+    // the crude test's queue pushes split the loop body into blocks, and a
+    // deep unroll then keeps too many values live: unroll less with it
+    constexpr int UNR = MODE != 0 ? 2 : 8;
+#pragma unroll UNR
+    for (int k = 0; k < 64; ++k) {
+        const double xj = sx[lane + k], yj = sy[lane + k], zj = sz[lane + k], gmj = sm[lane + k];
+#pragma unroll
+        for (int u = 0; u < IPL; ++u) {
+            const int M = u == 0 ? M0 : M1;
+            if (M == SYM_SKIP) continue;
+            const bool keep = M == SYM_DIAG ? (k > 0 && lane + k < 64) : true;
+            double r2;
+            if constexpr (PREC == 0)
+                pair_sym64(xj, yj, zj, gmj, xi[u], yi[u], zi[u], gmi[u], seed, c158, c32, keep,
+                           ax[u], ay[u], az[u], fx, fy, fz, r2);
+            else
+                pair_sym32(xj, yj, zj, gmj, xi[u], yi[u], zi[u], mif[u], keep, ax[u], ay[u], az[u],
+                           fx, fy, fz, r2);
+            if constexpr (MODE != 0) {
+                if (keep && r2 < th2[u]) {
+                    const unsigned q = atomicAdd(qn, 1u);
+                    if (q < (unsigned)kCrudeQ)
+                        qbuf[q] = ((unsigned)lt[u] << 16) | (unsigned)(jsub + ((lane + k) & 63));
+                }
+            }
+        }
+        fx = lane_rotate1(fx);
+        fy = lane_rotate1(fy);
+        fz = lane_rotate1(fz);
+    }
+}
+
+// exact crude test of the queued pairs of one tile (or, after a queue
+// overflow, of every pair of the tile with j > i)
+template <int BS, int IPL>
+__device__ void sym_drain(const KickArgs &ka, int ib, int jt, int jend, const int *iu,
+                          const bool *oku, const unsigned *qbuf, unsigned n)
+{
+    const int tid = threadIdx.x;
+    if (n <= (unsigned)kCrudeQ) {
+        for (unsigned e = tid; e < n; e += BS) {
+            const unsigned v = qbuf[e];
+            crude_exact(ka, ib + (int)(v >> 16), jt + (int)(v & 0xffffu));
+        }
+    } else {
+        const int je = min(jt + BS, jend);
+#pragma unroll
+        for (int u = 0; u < IPL; ++u)
+            if (oku[u])
+                for (int j = jt; j < je; ++j) crude_exact(ka, iu[u], j);
+    }
+}
+
 template <int BS, int IPL, int MODE, int PREC>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_kick_sym(
     KickArgs ka)
 {
+    static_assert(IPL == 1 || IPL == 2, "one or two i per lane");
     const Dev &d = ka.d;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     int b = blockIdx.x;
@@ -542,7 +630,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
     constexpr int NW = BS / 64;
     constexpr int BI = BS * IPL;
 
-    __shared__ double4 sj[BS];
+    // the j-tile, each sub-tile of 64 stored twice in a row (128 entries)
+    __shared__ double tx[NW][128], ty[NW][128], tz[NW][128], tm[NW][128];
     __shared__ double wpart[NW][3][BS];
     __shared__ double smax[3][NW];
     __shared__ unsigned qbuf[MODE ? kCrudeQ : 1];
@@ -565,43 +654,46 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
     const double seed = ka.r2seed, c158 = ka.c158, c32 = ka.c32;
     for (int ib = it.i0; ib < it.i0 + it.ni; ib += BI) {
         const int nib = min(BI, it.i0 + it.ni - ib);
-        double xi[IPL], yi[IPL], zi[IPL], gmi[IPL];
-        double ax[IPL], ay[IPL], az[IPL];
-        double hi[IPL], Ai[IPL], vi[IPL];
+        // lane group u of wave w holds i = ib + 64 (IPL w + u) + lane
+        double xi[IPL], yi[IPL], zi[IPL], gmi[IPL], hi[IPL], Ai[IPL], vi[IPL];
+        double ax[IPL], ay[IPL], az[IPL], th2[IPL];
         float mif[IPL];
-        int ii[IPL];
+        int iu[IPL], lt[IPL];
+        bool oku[IPL];
 #pragma unroll
         for (int u = 0; u < IPL; ++u) {
-            const int i = ib + tid + u * BS;
-            const bool ok = (tid + u * BS) < nib;
-            xi[u] = ok ? d.x[i] : 0.0;
-            yi[u] = ok ? d.y[i] : 0.0;
-            zi[u] = ok ? d.z[i] : 0.0;
-            gmi[u] = ok ? G * d.m[i] : 0.0;
+            lt[u] = 64 * (IPL * wv + u) + lane;
+            iu[u] = ib + lt[u];
+            oku[u] = lt[u] < nib;
+            const int i = iu[u];
+            xi[u] = oku[u] ? d.x[i] : kFar;
+            yi[u] = oku[u] ? d.y[i] : kFar;
+            zi[u] = oku[u] ? d.z[i] : kFar;
+            gmi[u] = oku[u] ? G * d.m[i] : 0.0;
             mif[u] = (float)gmi[u];
-            ax[u] = ay[u] = az[u] = 0.0;
-            if (MODE) {
-                hi[u] = ok ? d.ch[i] : 0.0;
-                Ai[u] = ok ? d.A[i] : 0.0;
-                vi[u] = ok ? d.cv[i] : 0.0;
+            hi[u] = Ai[u] = vi[u] = 0.0;
+            if (MODE && oku[u]) {
+                hi[u] = d.ch[i];
+                Ai[u] = d.A[i];
+                vi[u] = d.cv[i];
             }
-            ii[u] = ok ? i : 0x7fffffff;
+            ax[u] = ay[u] = az[u] = 0.0;
+            th2[u] = -1.0;
         }
-        int qtile = -1;
+        const int iw = ib + 64 * IPL * wv;   // first i of this wave
+        const bool wave_i = 64 * IPL * wv < nib;
         for (int jt = max(it.j0, ib); jt < jend; jt += BS) {
             const int j = jt + tid;
             const bool okj = j < jend;
-            __syncthreads();
-            if constexpr (MODE != 0) {
-                if (qtile >= 0) {
-                    if (qn) crude_drain<BS, IPL, MODE>(ka, ib, nib, qtile, jend, ii, qbuf, &qn);
-                    __syncthreads();
-                    if (tid == 0) qn = 0u;
-                    qtile = -1;
-                }
+            __syncthreads();   // the previous tile's LDS reads and queue are done
+            {
+                const double xj = okj ? d.x[j] : kFar, yj = okj ? d.y[j] : kFar;
+                const double zj = okj ? d.z[j] : kFar, mj = okj ? G * d.m[j] : 0.0;
+                tx[wv][lane] = xj; tx[wv][lane + 64] = xj;
+                ty[wv][lane] = yj; ty[wv][lane + 64] = yj;
+                tz[wv][lane] = zj; tz[wv][lane + 64] = zj;
+                tm[wv][lane] = mj; tm[wv][lane + 64] = mj;
             }
-            sj[tid] = okj ? make_double4(d.x[j], d.y[j], d.z[j], G * d.m[j])
-                          : make_double4(kFar, kFar, kFar, 0.0);
             // this thread's reaction entry, read early (latency hidden by the pairs)
             double racc[3] = {0.0, 0.0, 0.0};
             if (okj) {
@@ -609,8 +701,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
                 racc[1] = rj[ns + j];
                 racc[2] = rj[2 * ns + j];
             }
-            const int ntile = min(jt + BS, jend) - jt;
-            const int ntj = (ntile + 3) & ~3;
             if constexpr (MODE != 0) {
                 double t0 = okj ? d.ch[j] : 0.0, t1 = okj ? d.A[j] : 0.0, t2 = okj ? d.cv[j] : 0.0;
                 t0 = wave_max(t0);
@@ -623,7 +713,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
                 }
             }
             __syncthreads();
-            double th2[IPL];
             if constexpr (MODE != 0) {
                 double HT = smax[0][0], AT = smax[1][0], VT = smax[2][0];
 #pragma unroll
@@ -632,6 +721,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
                     AT = fmax(AT, smax[1][w2]);
                     VT = fmax(VT, smax[2][w2]);
                 }
+                // per-(i, tile) upper bound of the crude threshold (as in k_kick)
 #pragma unroll
                 for (int u = 0; u < IPL; ++u) {
                     double Rb;
@@ -640,42 +730,36 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
                     else
                         Rb = ka.aE * (hi[u] + HT);
                     const double th = ka.cs * (Rb + ka.tau_abs * (vi[u] + VT));
-                    th2[u] = th * th * 1.000000000001;
+                    th2[u] = oku[u] ? th * th * 1.000000000001 : -1.0;
                 }
             }
-            // tiles that overlap the i-block hold pairs with j <= i
-            const bool diag = jt < ib + nib;
-#pragma unroll 4
-            for (int jj = 0; jj < ntj; ++jj) {
-                const double4 pj = sj[jj];
-                const float mjf = (float)pj.w;
+#pragma unroll 1
+            for (int sub = 0; sub < NW; ++sub) {
+                const int jw = jt + 64 * sub;
                 double fx = 0.0, fy = 0.0, fz = 0.0;
-#pragma unroll
-                for (int u = 0; u < IPL; ++u) {
-                    const bool keep = !diag || (jt + jj > ii[u]);
-                    double r2;
-                    if constexpr (PREC == 0)
-                        pair_sym64(pj, xi[u], yi[u], zi[u], gmi[u], seed, c158, c32, keep, ax[u],
-                                   ay[u], az[u], fx, fy, fz, r2);
-                    else
-                        pair_sym32(pj, mjf, xi[u], yi[u], zi[u], mif[u], keep, ax[u], ay[u], az[u],
-                                   fx, fy, fz, r2);
-                    if constexpr (MODE != 0) {
-                        if (r2 < th2[u]) {
-                            const unsigned k = atomicAdd(&qn, 1u);
-                            if (k < (unsigned)kCrudeQ)
-                                qbuf[k] = ((unsigned)tid << 16) | ((unsigned)u << 8) | (unsigned)jj;
-                        }
-                    }
+                const int rel = jw - iw;   // a multiple of 64
+                const double *px = &tx[sub][0], *py = &ty[sub][0], *pz = &tz[sub][0],
+                             *pm = &tm[sub][0];
+                // whole waves past the i-block's end or sub-tiles past the
+                // chunk's end have no pairs (uniform per wave)
+                if (!wave_i || jw >= jend || rel < 0) {
+                    // nothing to add
+                } else if (rel >= 64 * IPL) {
+                    sym_subtile<MODE, PREC, IPL, SYM_FULL, SYM_FULL>(
+                        px, py, pz, pm, lane, xi, yi, zi, gmi, mif, th2, lt, seed, c158, c32, ax, ay,
+                        az, fx, fy, fz, qbuf, &qn, 64 * sub);
+                } else if (IPL == 2 && rel == 64) {
+                    sym_subtile<MODE, PREC, IPL, SYM_FULL, SYM_DIAG>(
+                        px, py, pz, pm, lane, xi, yi, zi, gmi, mif, th2, lt, seed, c158, c32, ax, ay,
+                        az, fx, fy, fz, qbuf, &qn, 64 * sub);
+                } else {   // rel == 0
+                    sym_subtile<MODE, PREC, IPL, SYM_DIAG, SYM_SKIP>(
+                        px, py, pz, pm, lane, xi, yi, zi, gmi, mif, th2, lt, seed, c158, c32, ax, ay,
+                        az, fx, fy, fz, qbuf, &qn, 64 * sub);
                 }
-                fx = wave_sum_xor(fx);
-                fy = wave_sum_xor(fy);
-                fz = wave_sum_xor(fz);
-                if (lane == 0) {
-                    wpart[wv][0][jj] = fx;
-                    wpart[wv][1][jj] = fy;
-                    wpart[wv][2][jj] = fz;
-                }
+                wpart[wv][0][64 * sub + lane] = fx;
+                wpart[wv][1][64 * sub + lane] = fy;
+                wpart[wv][2][64 * sub + lane] = fz;
             }
             __syncthreads();
             // the tile's reactions, waves in order, onto the slot
@@ -688,20 +772,19 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
                     rj[c * ns + j] = racc[c] + sum;
                 }
             }
-            if constexpr (MODE != 0) qtile = jt;
-        }
-        if constexpr (MODE != 0) {
-            __syncthreads();
-            if (qtile >= 0 && qn) crude_drain<BS, IPL, MODE>(ka, ib, nib, qtile, jend, ii, qbuf, &qn);
-            __syncthreads();
-            if (tid == 0) qn = 0u;
+            if constexpr (MODE != 0) {
+                const unsigned nq = qn;
+                if (nq) sym_drain<BS, IPL>(ka, ib, jt, jend, iu, oku, qbuf, nq);
+                __syncthreads();
+                if (tid == 0) qn = 0u;
+            }
         }
         // forces on this i-block: i-side slot `chunk`
         const long long pb = base + (long long)it.chunk * 3 * ns;
 #pragma unroll
         for (int u = 0; u < IPL; ++u) {
-            if (tid + u * BS < nib) {
-                const int il = ib + tid + u * BS - so;
+            if (oku[u]) {
+                const int il = iu[u] - so;
                 d.acc[pb + il] = ax[u];
                 d.acc[pb + ns + il] = ay[u];
                 d.acc[pb + 2 * ns + il] = az[u];
@@ -709,7 +792,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
         }
     }
 }
-
 
 // sum of the kick partials of body i (local index il of system s)
 // Kick partials of body il of system s.  Full-matrix kick (K.z == 0): the

@@ -55,11 +55,12 @@ SYSTEMS = {
 
 SHAPES = [dict(ipl=1, block=128, jchunk=128, remap=0), dict(ipl=2, block=256, jchunk=256, remap=1),
           dict(ipl=4, block=256, jchunk=512, remap=1), dict(ipl=2, block=128, jchunk=384, remap=1),
-          # symmetric kick: each unordered pair once, reaction on j
+          # symmetric kick: each unordered pair once, reaction on j (one or two i per lane)
           dict(ipl=1, block=128, jchunk=128, remap=0, sym=1),
           dict(ipl=2, block=128, jchunk=256, remap=1, sym=2),
-          dict(ipl=2, block=256, jchunk=1024, remap=1, sym=1),
-          dict(ipl=4, block=128, jchunk=512, remap=0, sym=4)]
+          dict(ipl=1, block=256, jchunk=1024, remap=1, sym=1),
+          dict(ipl=2, block=256, jchunk=512, remap=0, sym=1),
+          dict(ipl=1, block=128, jchunk=512, remap=0, sym=4)]
 
 
 @pytest.mark.parametrize("name", list(SYSTEMS))
@@ -386,6 +387,8 @@ def test_symmetric_kick_lockstep_steps(Q, orc, sym):
     s = crowded(300, 3)
     say("symmetric kick steps", sym)
     ctx = Q.Context(s)
+    with pytest.raises(Q.QsymError):   # the symmetric kick takes one or two i per lane
+        ctx.set_kick_shape(4, 128, 512, 1, sym=sym)
     ctx.set_kick_shape(2, 128, 256, 1, sym=sym)
     p = orc.make_params()
     q, v = s.q, s.v
