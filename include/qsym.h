@@ -190,12 +190,15 @@ int qsym_fine_test(const qsym_params *p, double m0, double tau, int64_t n, const
  * the smallest j-chunk the workspace was sized for), remap = 1 for the
  * XCD-aware workgroup order, sym = 0 for the full-matrix kick (every
  * ordered pair) or 1, 2, 4, 8 for the symmetric kick (every unordered pair
- * once, the reaction applied to j; sym i-blocks of block*ipl bodies per work
- * item, jchunk a multiple of block*ipl).  qsym_autotune times every
- * candidate shape of both kicks on the current state (without moving it),
- * keeps the fastest, and writes the two kick times in microseconds to us[0]
- * (plain) and us[1] (crude sweep).  Results do not depend on the shape
- * beyond rounding. */
+ * once, the reaction applied to j; ipl 1 or 2 only; sym i-blocks of
+ * block*ipl bodies per work item, jchunk a multiple of block*ipl; the
+ * j-side partial sums need at most min(ceil(n/128), 128) slots, so a shape
+ * whose i-ranges of sym*block*ipl bodies exceed that fails with
+ * QSYM_EINVAL).  qsym_autotune times every candidate shape of both kicks on
+ * the current state (without moving it), each launch followed by the
+ * reduction of its partial sums, keeps the fastest, and writes those two
+ * times (kick + reduction) in microseconds to us[0] (plain) and us[1]
+ * (crude sweep).  Results do not depend on the shape beyond rounding. */
 int qsym_set_kick_shape(qsym_ctx *ctx, int32_t which, int32_t ipl, int32_t block, int64_t jchunk,
                         int32_t remap, int32_t sym);
 int qsym_get_kick_shape(qsym_ctx *ctx, int32_t which, int32_t *ipl, int32_t *block,

@@ -1161,10 +1161,17 @@ int qsym_autotune(qsym_ctx *c, double tau, double *us)
         for (const Shape &sh : cand) {
             c->shape[w] = sh;
             if (upload_shape(c, w) != QSYM_OK) continue;
-            // warm-up, then 3 timed launches
+            // warm-up, then 3 timed launches of the kick and of the
+            // reduction of its partial sums (an apply with dt = 0, which
+            // leaves the state as it is): shapes with more partial slots
+            // pay for them there
             (void)launch_kick(c, mode, st);
+            (void)run_apply(c, 0.0, 0.0, 1, 0, 0, 0, st, P_OTHER, w);
             (void)hipEventRecord(e0, st);
-            for (int r = 0; r < 3; ++r) (void)launch_kick(c, mode, st);
+            for (int r = 0; r < 3; ++r) {
+                (void)launch_kick(c, mode, st);
+                (void)run_apply(c, 0.0, 0.0, 1, 0, 0, 0, st, P_OTHER, w);
+            }
             (void)hipEventRecord(e1, st);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;

@@ -479,8 +479,8 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
 // i < j of the system is met exactly once over all items.  The force on i
 // goes to its i-side slot
 // `chunk` (as written by k_kick); the reactions of the waves are added in
-// wave order and then to the item's own j-side slot `slot`, which the item
-// first clears for every j of the chunk.  Each slot entry is only ever
+// wave order and then to the item's own j-side slot `slot` (the item's
+// first i-block stores, later ones add).  Each slot entry is only ever
 // touched by one thread of one item: no atomics, a fixed order.  Per pair:
 // one pair term for both forces (21 VALU instructions, one rsq) and 6/IPL
 // instructions of lane rotation (DPP), against 2 x 17 for the two ordered
@@ -642,9 +642,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
     const int ns = d.sys_off[s + 1] - so;
     const long long base = d.sys_poff[s];
     const int jend = it.j0 + it.nj;
-    // the item's reaction slot; entry j is owned by thread (j - j0) % BS
+    // the item's reaction slot; entry j is owned by thread (j - j0) % BS.
+    // The first i-block stores every entry from max(j0, i0) on without
+    // reading it; only the entries before (no i of the item precedes them)
+    // are cleared here.
     double *rj = d.acc + base + (long long)it.slot * 3 * ns - so;
-    for (int k = tid; k < it.nj; k += BS) {
+    const int jfirst = max(it.j0, it.i0);
+    for (int k = tid; k < jfirst - it.j0; k += BS) {
         rj[it.j0 + k] = 0.0;
         rj[ns + it.j0 + k] = 0.0;
         rj[2 * ns + it.j0 + k] = 0.0;
@@ -653,6 +657,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
     const double G = ka.G;
     const double seed = ka.r2seed, c158 = ka.c158, c32 = ka.c32;
     for (int ib = it.i0; ib < it.i0 + it.ni; ib += BI) {
+        const bool first_ib = ib == it.i0;
         const int nib = min(BI, it.i0 + it.ni - ib);
         // lane group u of wave w holds i = ib + 64 (IPL w + u) + lane
         double xi[IPL], yi[IPL], zi[IPL], gmi[IPL], hi[IPL], Ai[IPL], vi[IPL];
@@ -694,9 +699,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
                 tz[wv][lane] = zj; tz[wv][lane + 64] = zj;
                 tm[wv][lane] = mj; tm[wv][lane + 64] = mj;
             }
-            // this thread's reaction entry, read early (latency hidden by the pairs)
+            // this thread's reaction entry, read early (latency hidden by the
+            // pairs); the item's first i-block starts it from zero
             double racc[3] = {0.0, 0.0, 0.0};
-            if (okj) {
+            if (okj && !first_ib) {
                 racc[0] = rj[j];
                 racc[1] = rj[ns + j];
                 racc[2] = rj[2 * ns + j];
