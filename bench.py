@@ -132,9 +132,10 @@ def cpu_baseline(systems, tau, seconds, swapped=False):
     return out
 
 
-def make_context(systems, precision, tau, force_tune, kepler_mode=0, guess=None):
+def make_context(systems, precision, tau, force_tune, kepler_mode=0, guess=None, sweep=0):
     from paper_1007_3458_amd import qsym
-    ctx = qsym.Context(systems, precision=precision, kepler_mode=kepler_mode, guess=guess)
+    ctx = qsym.Context(systems, precision=precision, kepler_mode=kepler_mode, guess=guess,
+                       sweep=sweep)
     tune_us = None
     if force_tune or ctx.tuned is None:
         tune_us = ctx.autotune(tau)
@@ -279,6 +280,8 @@ def main():
                     help="precision 1: skip the FP64 run on the same initial conditions")
     ap.add_argument("--swapped", action="store_true",
                     help="encounter-free steps with E_Kep and E_Int swapped (one kick per step)")
+    ap.add_argument("--sweep", choices=["fused", "grid"], default="fused",
+                    help="crude sweep fused into the first kick, or on the hashed grid ahead of it")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device-to-device copies of MIB MiB (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -316,7 +319,9 @@ def main():
     if args.workload == "learned":
         guess, extra["learned_report"] = learned_report()
         kepler_mode = 2
-    ctx, shape = make_context(systems, args.precision, args.tau, args.autotune, kepler_mode, guess)
+    sweep = 1 if args.sweep == "grid" else 0
+    ctx, shape = make_context(systems, args.precision, args.tau, args.autotune, kepler_mode, guess,
+                              sweep)
     if args.workload == "learned" and not args.no_compare:
         # the same disk from the first-order Newton start
         ctx1, _ = make_context(systems, args.precision, args.tau, False, 1)
@@ -375,15 +380,17 @@ def main():
     # (the plain kick for the swapped step).  Its flops are the algorithmic
     # count of all N(N-1) ordered interactions, also for the symmetric kick,
     # which evaluates each unordered pair once.
-    t_kick = kern.get("kick2") if args.swapped else kern.get("kick+crude")
-    kick_name = "k_kick_sym" if shape["plain" if args.swapped else "crude"]["sym"] else "k_kick"
-    flops = npairs * FLOP_PAIR + (0 if args.swapped else npairs / 2 * FLOP_CRUDE)
+    # With the grid sweep both kicks are plain: the roofline is the plain kick.
+    plain_roof = args.swapped or sweep == 1
+    t_kick = kern.get("kick2") if plain_roof else kern.get("kick+crude")
+    kick_name = "k_kick_sym" if shape["plain" if plain_roof else "crude"]["sym"] else "k_kick"
+    flops = npairs * FLOP_PAIR + (0 if plain_roof else npairs / 2 * FLOP_CRUDE)
     peak = FP64_PEAK_TFLOPS if args.precision == 0 else FP32_PEAK_TFLOPS
     achieved = flops / (t_kick * 1e-6) / 1e12 if t_kick else None
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": (achieved / peak) if achieved else None,
             "traffic": measured_traffic(args.workload, args.precision),
-            "kernel": kick_name + (" (E_Int)" if args.swapped else " (E_Int + fused crude sweep)"),
+            "kernel": kick_name + (" (E_Int)" if plain_roof else " (E_Int + fused crude sweep)"),
             "flop_per_launch": flops, "avg_launch_us": t_kick,
             "pairs_per_s_kernel": (npairs / (t_kick * 1e-6)) if t_kick else None}
     out = {
@@ -408,6 +415,7 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "n_bodies": ntot, "n_systems": len(systems),
                    "tau": args.tau, "precision": args.precision, "kepler_mode": kepler_mode,
                    "step": "swapped E_Kep/E_Int, no encounter search" if args.swapped else "hybrid",
+                   "crude_sweep": None if args.swapped else args.sweep,
                    "kick_shape": shape},
         "energy_error": energy_err,
         "encounters_last_step": r["st"]["n_encounters"],

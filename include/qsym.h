@@ -79,6 +79,14 @@ typedef struct qsym_params {
                             corrections take back both half kicks.  0: off.
                             The workspace then holds member slots for every
                             body.                                             */
+    int32_t sweep;       /* crude sweep of Sec. 2.4: 0 fused into the first kick's
+                            pair loop (all pairs); 1 on a hashed uniform grid
+                            (expected O(N) tests) ahead of a plain first kick.
+                            Both decide every pair by the same exact test, so
+                            the candidate set is the same.  1 adds a hash
+                            table of 2^k >= 2 ntot buckets x 17 ints to the
+                            workspace.                                        */
+    int32_t pad2;        /* 0 */
 } qsym_params;
 
 /* Counters of the last step and totals since creation/reset. */

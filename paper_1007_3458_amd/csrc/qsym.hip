@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "qsym_kernels.hpp"
+#include "qsym_sweep.hpp"
 
 using namespace qsym;
 
@@ -39,6 +40,9 @@ struct Layout {
     size_t off_bchunk = 0, off_kchunk = 0, off_items = 0, off_eitems = 0, off_syse0 = 0, off_cand = 0;
     size_t off_enc = 0, off_syseoff = 0, off_sysecnt = 0, off_setcount = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0, off_setlist = 0;
     size_t off_gbar = 0, off_hpart = 0;
+    size_t off_swcnt = 0, off_swslot = 0, off_swrec = 0, off_swlarge = 0, off_syssw = 0,
+           off_swpart = 0;
+    long long sw_nb = 1;       // grid-sweep buckets
     size_t off_hw = 0, off_ctr = 0, off_epart = 0, off_E = 0, off_guess = 0;
     size_t total = 0;
     long long np = 0;          // padded body count
@@ -155,6 +159,17 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_gbar, 4 * sizeof(unsigned));
     take(L.off_hpart, 2 * (size_t)kGridMax * D);
     take(L.off_hw, (size_t)HFIELDS * L.memcap * D);
+    // grid sweep: a hash table of >= 2 ntot buckets (only when selected)
+    L.sw_nb = 1;
+    if (p.sweep == 1)
+        while (L.sw_nb < std::max<long long>(1024, 2 * ntot)) L.sw_nb <<= 1;
+    const size_t swb = p.sweep == 1 ? (size_t)L.np : 1;
+    take(L.off_swcnt, (size_t)L.sw_nb * sizeof(int));
+    take(L.off_swslot, (size_t)L.sw_nb * kSweepCap * sizeof(int));
+    take(L.off_swrec, swb * sizeof(SweepRec));
+    take(L.off_swlarge, swb * sizeof(int));
+    take(L.off_syssw, (size_t)std::max(nsys, 1) * sizeof(double4));
+    take(L.off_swpart, 3 * (size_t)L.nchunks * D);
     take(L.off_ctr, (size_t)C_COUNT * sizeof(unsigned long long));
     take(L.off_epart, (size_t)L.n_eitems * D);
     take(L.off_E, (size_t)std::max(nsys, 1) * D);
@@ -209,6 +224,13 @@ Dev bind(char *base, const Layout &L)
     d.gbar = (unsigned *)(base + L.off_gbar);
     d.hpart = (double *)(base + L.off_hpart);
     d.setcap = (int)L.ecap;
+    d.sw_cnt = (int *)(base + L.off_swcnt);
+    d.sw_slot = (int *)(base + L.off_swslot);
+    d.sw_rec = (SweepRec *)(base + L.off_swrec);
+    d.sw_large = (int *)(base + L.off_swlarge);
+    d.sys_sw = (double4 *)(base + L.off_syssw);
+    d.sw_nb = (int)L.sw_nb;
+    d.sw_part = (double *)(base + L.off_swpart);
     d.memcap = (int)L.memcap;
     d.set_start = (int *)(base + L.off_setstart);
     d.set_mem = (int *)(base + L.off_setmem);
@@ -293,7 +315,7 @@ int validate(const qsym_params *p, int32_t nsys, const int64_t *offsets, std::st
     }
     if (p->hill_mode < 0 || p->hill_mode > 1 || p->kepler_mode < 0 || p->kepler_mode > 2 ||
         p->precision < 0 || p->precision > 1 || p->max_substeps < 1 || p->pair_capacity < 0 ||
-        !(p->planet_mass >= 0.0) || !std::isfinite(p->planet_mass)) {
+        !(p->planet_mass >= 0.0) || !std::isfinite(p->planet_mass) || p->sweep < 0 || p->sweep > 1) {
         msg = "mode out of range";
         return QSYM_EINVAL;
     }
@@ -520,7 +542,7 @@ hipError_t run_drift(qsym_ctx *c, double dt, int prepass, double tau_crude, int 
 {
     Timer tm(c, phase);
     DriftArgs a{c->d, dt, c->p.G, tau_crude, c->p.aE, c->p.crude_safety, prepass, c->p.hill_mode,
-                reset, count_step};
+                reset, count_step, prepass && c->p.sweep == 1};
     hipLaunchKernelGGL(k_drift, dim3(nblocks_chunks(c)), dim3(kChunk), 0, st, a);
     return hipGetLastError();
 }
@@ -557,6 +579,40 @@ hipError_t run_kick(qsym_ctx *c, int crude, double tau_crude, hipStream_t st, in
     return launch_kick(c, crude ? 1 + c->p.hill_mode : 0, st);
 }
 
+// grid crude sweep (qsym_params.sweep = 1): grid constants and bucket
+// clear, binning, search; the candidates land where the fused sweep puts
+// them.  Timed with the first kick by the caller.
+hipError_t launch_sweep(qsym_ctx *c, double tau, hipStream_t st)
+{
+    c->tau_crude = std::fabs(tau);
+    KickArgs ka{c->d, nullptr, c->p.G, c->L.cap, 0, 0, c->p.hill_mode, c->p.aE, c->p.crude_safety,
+                c->tau_crude, 1e-200, 1.875, 1.5};
+    long long nmax = 0;
+    for (int s = 0; s < c->nsys; ++s) nmax = std::max<long long>(nmax, nsys_bodies(c->off, s));
+    SweepArgs a;
+    a.ka = ka;
+    a.nsys = c->nsys;
+    a.ntot = (int)c->ntot;
+    a.nsmall = (int)((14 * c->ntot + kSweepThreads - 1) / kSweepThreads);
+    a.tiles = (int)std::max<long long>(1, (nmax + kSweepLargeTile - 1) / kSweepLargeTile);
+    hipLaunchKernelGGL(k_sweep_bin, dim3(nblocks_chunks(c)), dim3(kChunk), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sweep_search, dim3(a.nsmall + 256), dim3(kSweepThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+// the first kick with its crude sweep: fused into the kick's pair loop
+// (kick shape 1), or on the grid ahead of a plain kick (kick shape 0)
+hipError_t run_kick1(qsym_ctx *c, double tau, hipStream_t st)
+{
+    if (!c->p.sweep) return run_kick(c, 1, tau, st, P_KICK1);
+    Timer tm(c, P_KICK1);
+    hipError_t e = launch_sweep(c, tau, st);
+    if (e != hipSuccess) return e;
+    return launch_kick(c, 0, st);
+}
+
 int fine_grid(qsym_ctx *c)
 {
     long long g = (c->L.cap + 255) / 256;
@@ -570,10 +626,11 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
     const double half = tau / 2.0;
     // 1: drift tau/2 + per-body encounter terms, reset per-step counters
     if ((e = run_drift(c, half, 1, tau, 1, st, P_DRIFT)) != hipSuccess) return e;
-    // 2: kick tau/2 with the crude sweep fused in
-    if ((e = run_kick(c, 1, tau, st, P_KICK1)) != hipSuccess) return e;
+    // 2: kick tau/2 with the crude sweep
+    if ((e = run_kick1(c, tau, st)) != hipSuccess) return e;
     // 2-3: apply the kick, snapshot (q0, v0), Kepler tau -> (q1, v1)
-    if ((e = run_apply(c, half, tau, 1, 1, 1, 0, st, P_APPLY1, 1)) != hipSuccess) return e;
+    if ((e = run_apply(c, half, tau, 1, 1, 1, 0, st, P_APPLY1, c->p.sweep ? 0 : 1)) != hipSuccess)
+        return e;
     // 4: fine sweep, sets, r_crit
     {
         Timer tm(c, P_FINE);
@@ -1050,8 +1107,11 @@ int qsym_apply_kick(qsym_ctx *c, double dt, double crude_tau)
     hipStream_t st = c->stream;
     const int crude = crude_tau != 0.0;
     if (crude) HIPCHK(c, run_drift(c, 0.0, 1, crude_tau, 1, st, P_DRIFT));
-    HIPCHK(c, run_kick(c, crude, crude_tau, st, crude ? P_KICK1 : P_KICK2));
-    HIPCHK(c, run_apply(c, dt, 0.0, 1, 0, 0, 1, st, P_APPLY2, crude ? 1 : 0));
+    if (crude)
+        HIPCHK(c, run_kick1(c, crude_tau, st));
+    else
+        HIPCHK(c, run_kick(c, 0, 0.0, st, P_KICK2));
+    HIPCHK(c, run_apply(c, dt, 0.0, 1, 0, 0, 1, st, P_APPLY2, crude && !c->p.sweep ? 1 : 0));
     leave(c);
     return QSYM_OK;
 }

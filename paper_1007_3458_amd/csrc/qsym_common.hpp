@@ -39,6 +39,7 @@ enum Ctr {
     C_HQB,
     C_HIST = 16,  // kHist bins
     C_WHOLE = C_HIST + kHist,   // systems integrated whole (all steps)
+    C_NLARGE,     // grid sweep: bodies on the large list, last step
     C_COUNT
 };
 
@@ -55,6 +56,14 @@ enum Status : unsigned long long {
 // against j-bodies [j0, j0+nj) (its j-chunk number `chunk`)
 struct KickItem {
     int sys, i0, ni, j0, nj, chunk, slot;   // slot: j-side partial slot (symmetric kick)
+};
+
+// one body's operands of the crude test, packed into one 64-byte line for
+// the grid sweep: position, h, a, ve, grid cell, and its system (negative,
+// -(sys + 1), for bodies on the large list)
+struct SweepRec {
+    double x, y, z, h, A, cv;
+    int cx, cy, cz, sys;
 };
 
 // device pointers into the caller-provided workspace
@@ -87,6 +96,13 @@ struct Dev {
     int setcap;                                 // set slots
     unsigned *gbar;                             // grid barrier of k_hermite_grid (3 words)
     double *hpart;                              // [2][kGridMax] its per-block step minima
+    int *sw_cnt;                                // grid sweep: [sw_nb] bucket counts
+    int *sw_slot;                               // [sw_nb][kSweepCap] bodies per bucket
+    SweepRec *sw_rec;                           // [np] packed crude-test operands and cell
+    int *sw_large;                              // [np] bodies of the large list
+    double4 *sys_sw;                            // [nsys] A_lim, rho_lim, cell size
+    double *sw_part;                            // [chunk][3] sums of a, h (or h a), ve
+    int sw_nb;                                  // buckets (a power of two)
     int memcap;                                 // member slots (Hermite scratch stride)
     double *hw;                                 // Hermite member scratch
     unsigned long long *ctr;                    // counters and status

@@ -113,6 +113,7 @@ struct DriftArgs {
     Dev d;
     double dt, G, tau_crude, aE, cs;
     int prepass, hill_mode, reset, count_step;
+    int sweep_stats;   // grid crude sweep next: per-chunk sums of (a, h or h a, ve), clear its table
 };
 
 __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
@@ -134,6 +135,7 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
         d.ctr[C_NBIG] = 0;
         d.ctr[C_HQS] = 0;
         d.ctr[C_HQB] = 0;
+        d.ctr[C_NLARGE] = 0;
         d.gbar[0] = 0u;
         d.gbar[1] = 0u;
         d.gbar[2] = 0u;
@@ -141,25 +143,40 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
     if (a.count_step && blockIdx.x == 0 && threadIdx.x == 0) d.ctr[C_STEPS] += 1;
     if (a.reset && threadIdx.x == 0 && (int)blockIdx.x == d.sys_c0[s]) d.sys_ecnt[s] = 0;
     const int t = threadIdx.x;
-    if (t >= bc.z) return;
+    const bool ok = t < bc.z;
     const int i = bc.y + t;
     const double m0 = d.sys_m0[s];
-    const double x = d.x[i] + a.dt * (P[0] / m0);
-    const double y = d.y[i] + a.dt * (P[1] / m0);
-    const double z = d.z[i] + a.dt * (P[2] / m0);
-    d.x[i] = x;
-    d.y[i] = y;
-    d.z[i] = z;
-    if (a.prepass) {
-        const double mu = a.G * m0;
-        const double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
-        const double r = sqrt(x * x + y * y + z * z);
-        const double inva = 2.0 / r - (vx * vx + vy * vy + vz * vz) / mu;
-        const double A = (inva > 0.0) ? 1.0 / inva : r;
-        const double ve = sqrt(2.0 * mu / r);
-        d.A[i] = A;
-        d.ch[i] = (a.hill_mode == 0) ? d.h[i] : d.h[i] * A;
-        d.cv[i] = ve;
+    double sw[3] = {0.0, 0.0, 0.0};
+    if (ok) {
+        const double x = d.x[i] + a.dt * (P[0] / m0);
+        const double y = d.y[i] + a.dt * (P[1] / m0);
+        const double z = d.z[i] + a.dt * (P[2] / m0);
+        d.x[i] = x;
+        d.y[i] = y;
+        d.z[i] = z;
+        if (a.prepass) {
+            const double mu = a.G * m0;
+            const double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
+            const double r = sqrt(x * x + y * y + z * z);
+            const double inva = 2.0 / r - (vx * vx + vy * vy + vz * vz) / mu;
+            const double A = (inva > 0.0) ? 1.0 / inva : r;
+            const double ve = sqrt(2.0 * mu / r);
+            const double ch = (a.hill_mode == 0) ? d.h[i] : d.h[i] * A;
+            d.A[i] = A;
+            d.ch[i] = ch;
+            d.cv[i] = ve;
+            sw[0] = A;
+            sw[1] = ch;
+            sw[2] = ve;
+        }
+    }
+    if (a.sweep_stats) {
+        // the grid sweep's statistics: chunk sums in a fixed order
+        for (int k = 0; k < 3; ++k) {
+            const double v = block_sum<kChunk>(sw[k], lds);
+            if (t == 0) d.sw_part[3 * blockIdx.x + k] = v;
+        }
+        for (int k = blockIdx.x * kChunk + t; k < d.sw_nb; k += gridDim.x * kChunk) d.sw_cnt[k] = 0;
     }
 }
 

@@ -35,7 +35,7 @@ class Params(C.Structure):
                 ("eta", C.c_double), ("eta_s", C.c_double), ("crude_safety", C.c_double),
                 ("hill_mode", C.c_int32), ("kepler_mode", C.c_int32), ("precision", C.c_int32),
                 ("max_substeps", C.c_int32), ("pair_capacity", C.c_int64),
-                ("planet_mass", C.c_double)]
+                ("planet_mass", C.c_double), ("sweep", C.c_int32), ("pad2", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -60,7 +60,7 @@ PHASES = ["drift+prepass", "kick+crude", "apply+kepler", "fine", "sets", "hermit
 
 DEFAULTS = dict(G=1.0, aE=3.0, aH=1.0, epsH=1e-8, eta=0.02, eta_s=0.01, crude_safety=1.1,
                 hill_mode=0, kepler_mode=0, precision=0, max_substeps=100000, pair_capacity=0,
-                planet_mass=0.0)
+                planet_mass=0.0, sweep=0)
 
 
 def make_params(**kw) -> Params:
@@ -72,7 +72,7 @@ def make_params(**kw) -> Params:
     return Params(float(d["G"]), float(d["aE"]), float(d["aH"]), float(d["epsH"]), float(d["eta"]),
                   float(d["eta_s"]), float(d["crude_safety"]), int(d["hill_mode"]),
                   int(d["kepler_mode"]), int(d["precision"]), int(d["max_substeps"]),
-                  int(d["pair_capacity"]), float(d["planet_mass"]))
+                  int(d["pair_capacity"]), float(d["planet_mass"]), int(d["sweep"]), 0)
 
 
 _lib = None
