@@ -1477,10 +1477,10 @@ struct HermArgs {
     int max_substeps;
 };
 
-constexpr int kCoopMin = 1024;      // larger sets run on the whole grid (k_hermite_grid)
+constexpr int kCoopMin = 256;       // larger sets run on the whole grid (k_hermite_grid)
 constexpr int kGridThreads = 256;   // workgroup of k_hermite_grid
 
-constexpr int kHermLds = 1024;   // members of one set staged in LDS
+constexpr int kHermLds = kHermThreads;   // members of one set staged in LDS
 
 // member scratch layout: field f of member slot k at hw[f * memcap + k]
 // HS..HS+6: staging of sets too large for LDS (x y z u v w m)
@@ -1729,21 +1729,174 @@ __device__ void hermite_set_wave(const HermArgs &a, int sidx, const SetLds &S, i
     fail_out = fail;
 }
 
-// Sec. 2.3 steps 5-7 for every set.  Sets of more than kWaveMax members
-// first, one workgroup each: positions, velocities and masses staged in LDS
-// (in the global member scratch beyond kHermLds members), each member's pair
-// sums split over L lanes (L = largest power of two with L n <= 512, at most
-// 64) and combined by an xor tree.  Then the small sets, one wave each
-// (hermite_set_wave).  Both take their sets from work queues, so a block or
-// wave that finishes early takes the next set; every set is integrated on
-// its own, so the order changes nothing in the results.
+// minimum over the workgroup of a value that is equal on the L lanes of
+// each group: a wave minimum, then the kHermThreads / 64 wave minima
+// through LDS (one barrier); every thread gets the same value
+__device__ __forceinline__ double block_min_waves(double v, double *red)
+{
+    v = wave_min(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < kHermThreads / 64; ++w) r = fmin(r, red[w]);
+    return wave_uniform(r);
+}
+
+// One set of kWaveMax < n <= kHermThreads members on one workgroup: member
+// k on the L lanes of group k (L the largest power of two <= 64 with
+// L n <= kHermThreads, so no group holds two members), its state (X, U, A,
+// J) in registers of those lanes, the staged set in LDS.  Same steps and
+// arithmetic as hermite_set_wave; per substep three barriers: the staged
+// prediction written, read, and the step-size minimum.
+__device__ void hermite_set_block(const HermArgs &a, int sidx, const SetLds &S, double *red,
+                                  int &nsub_out, int &fail_out)
+{
+    const Dev &d = a.d;
+    const int t = threadIdx.x;
+    const int b0 = __builtin_amdgcn_readfirstlane(d.set_start[sidx]);
+    const int n = __builtin_amdgcn_readfirstlane(d.set_count[sidx]);
+    const double rc = d.set_rc[sidx];
+    int L = 1;
+    while (L < 64 && 2 * L * n <= kHermThreads) L <<= 1;
+    const int k = t / L, l = t % L;
+    const bool mine = k < n;
+    const int kk = mine ? k : 0;   // idle groups shadow member 0; their results are dropped
+    const int i = d.set_mem[b0 + kk];
+    const double mu = a.G * d.sys_m0[d.body_sys[i]];
+    const double half = a.tau / 2.0;
+    double X[3] = {d.x0[i], d.y0[i], d.z0[i]};
+    if (mine && l == 0) {
+        S.x[k] = X[0];
+        S.y[k] = X[1];
+        S.z[k] = X[2];
+        S.m[k] = d.m[i];
+    }
+    __syncthreads();
+    // step 5: v0 -= tau/2 * sum W-weighted in-set forces at q0
+    double U[3], A[3], J[3];
+    {
+        double acc[3];
+        set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
+        for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+        U[0] = d.vx0[i] - half * acc[0];
+        U[1] = d.vy0[i] - half * acc[1];
+        U[2] = d.vz0[i] - half * acc[2];
+    }
+    if (mine && l == 0) {
+        S.u[k] = U[0];
+        S.v[k] = U[1];
+        S.w[k] = U[2];
+    }
+    __syncthreads();
+    // initial force and first step
+    herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, A, J);
+    for (int c = 0; c < 3; ++c) {
+        A[c] = group_sum(A[c], L);
+        J[c] = group_sum(J[c], L);
+    }
+    herm_central(X, U, mu, A, J);
+    double hloc = INFINITY;
+    {
+        const double hb = a.eta_s * dnorm3(A[0], A[1], A[2]) / dnorm3(J[0], J[1], J[2]);
+        if (mine && hb > 0.0) hloc = hb;
+    }
+    double h = block_min_waves(hloc, red);
+    const double sgn = a.tau >= 0.0 ? 1.0 : -1.0;
+    const double T = fabs(a.tau);
+    double tt = 0.0;
+    int nsub = 0, fail = 0;
+    bool last = (T == 0.0);
+    while (!last) {
+        if (nsub >= a.max_substeps) {
+            fail = 1;
+            break;
+        }
+        if (!(h > 0.0) || h >= T - tt) {
+            h = T - tt;
+            last = true;
+        }
+        const double hs = sgn * h;
+        double xp[3], up[3];
+        for (int c = 0; c < 3; ++c) {
+            xp[c] = X[c] + hs * U[c] + hs * hs * A[c] / 2.0 + hs * hs * hs * J[c] / 6.0;
+            up[c] = U[c] + hs * A[c] + hs * hs * J[c] / 2.0;
+        }
+        __syncthreads();   // every lane is done reading the previous state (and red)
+        if (mine && l == 0) {
+            S.x[k] = xp[0]; S.y[k] = xp[1]; S.z[k] = xp[2];
+            S.u[k] = up[0]; S.v[k] = up[1]; S.w[k] = up[2];
+        }
+        __syncthreads();
+        double a1[3], j1[3];
+        herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, a1, j1);
+        for (int c = 0; c < 3; ++c) {
+            a1[c] = group_sum(a1[c], L);
+            j1[c] = group_sum(j1[c], L);
+        }
+        herm_central(xp, up, mu, a1, j1);
+        double A2e[3], A3v[3];
+        for (int c = 0; c < 3; ++c) {
+            const double A2 = (-6.0 * (A[c] - a1[c]) - hs * (4.0 * J[c] + 2.0 * j1[c])) / (hs * hs);
+            const double A3 = (12.0 * (A[c] - a1[c]) + 6.0 * hs * (J[c] + j1[c])) / (hs * hs * hs);
+            X[c] = xp[c] + A2 * hs * hs * hs * hs / 24.0 + A3 * hs * hs * hs * hs * hs / 120.0;
+            U[c] = up[c] + A2 * hs * hs * hs / 6.0 + A3 * hs * hs * hs * hs / 24.0;
+            A[c] = a1[c];
+            J[c] = j1[c];
+            A2e[c] = A2 + hs * A3;
+            A3v[c] = A3;
+        }
+        const double na = dnorm3(a1[0], a1[1], a1[2]), nj = dnorm3(j1[0], j1[1], j1[2]);
+        const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]);
+        const double n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
+        const double hb = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
+        tt += h;
+        ++nsub;
+        h = block_min_waves((mine && hb > 0.0) ? hb : INFINITY, red);
+    }
+    // step 7: v1 -= tau/2 * W-weighted in-set forces at q1, write back
+    __syncthreads();
+    if (mine && l == 0) {
+        S.x[k] = X[0];
+        S.y[k] = X[1];
+        S.z[k] = X[2];
+    }
+    __syncthreads();
+    double acc[3];
+    set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
+    for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+    if (mine && l == 0) {
+        d.x[i] = X[0];
+        d.y[i] = X[1];
+        d.z[i] = X[2];
+        d.vx[i] = U[0] - half * acc[0];
+        d.vy[i] = U[1] - half * acc[1];
+        d.vz[i] = U[2] - half * acc[2];
+    }
+    __syncthreads();   // the staging arrays are reused by the next set
+    nsub_out = nsub;
+    fail_out = fail;
+}
+
+// Sec. 2.3 steps 5-7 for every set of at most kCoopMin members.  Sets of
+// more than kWaveMax members first, one workgroup each (hermite_set_block:
+// the set staged in LDS, each member's state in the registers of its lane
+// group); then the small sets, one wave each (hermite_set_wave).  Both take
+// their sets from work queues, so a block or wave that finishes early takes
+// the next set; every set is integrated on its own, so the order changes
+// nothing in the results.  Larger sets run on the whole grid
+// (k_hermite_grid): from about 250 members its two grid barriers per
+// substep cost less than the n^2 / 512 pair terms per lane of one
+// workgroup.
 __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
 {
+    static_assert(kCoopMin <= kHermThreads && kHermThreads <= kHermLds,
+                  "a workgroup set has at most one member per lane group");
     const Dev &d = a.d;
     __shared__ double s_x[kHermLds], s_y[kHermLds], s_z[kHermLds];
     __shared__ double s_u[kHermLds], s_v[kHermLds], s_w[kHermLds], s_m[kHermLds];
-    __shared__ double lds[kHermThreads];
-    __shared__ int s_fail, s_item;
+    __shared__ double lds[kHermThreads / 64];
+    __shared__ int s_item;
     const int t = threadIdx.x;
     const int nbig = (int)d.ctr[C_NBIG];
     int nsub_b = 0, fail_b = 0;   // statistics of thread 0, added after the loop
@@ -1755,179 +1908,12 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
         if (q >= nbig) break;
         const int sidx = d.set_list[d.setcap - 1 - q];
         if (d.set_count[sidx] > kCoopMin) continue;   // k_hermite_grid takes it
-
-        const int b0 = d.set_start[sidx];
-        const int n = d.set_count[sidx];
-        const double rc = d.set_rc[sidx];
-        // sets beyond the LDS capacity stage through the member scratch in
-        // global memory (same code, slower loads)
-        const bool big = n > kHermLds;
-        double *gs = d.hw + (long long)HS * d.memcap + b0;
-        const long long fs = d.memcap;
-        const SetLds S = big ? SetLds{gs, gs + fs, gs + 2 * fs, gs + 3 * fs, gs + 4 * fs, gs + 5 * fs,
-                                      gs + 6 * fs}
-                             : SetLds{s_x, s_y, s_z, s_u, s_v, s_w, s_m};
-        int L = 1;
-        while (L < 64 && 2 * L * n <= kHermThreads) L <<= 1;
-        const int G = kHermThreads / L;
-        const int g = t / L, l = t % L;
-        const double mu = a.G * d.sys_m0[d.body_sys[d.set_mem[b0]]];
-        const double half = a.tau / 2.0;
-        // stage q0, v0 and masses
-        for (int k = t; k < n; k += kHermThreads) {
-            const int i = d.set_mem[b0 + k];
-            S.x[k] = d.x0[i];
-            S.y[k] = d.y0[i];
-            S.z[k] = d.z0[i];
-            S.m[k] = d.m[i];
-        }
-        __syncthreads();
-        // step 5: v0 -= tau/2 * sum W-weighted in-set forces at q0
-        for (int k = g; k < n; k += G) {
-            double acc[3];
-            set_pair_acc(S, n, k, l, L, a.G, rc, acc);
-            for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
-            if (l == 0) {
-                const int i = d.set_mem[b0 + k];
-                hw_at(d, HX + 0, b0 + k) = S.x[k];
-                hw_at(d, HX + 1, b0 + k) = S.y[k];
-                hw_at(d, HX + 2, b0 + k) = S.z[k];
-                const double u0 = d.vx0[i] - half * acc[0];
-                const double u1 = d.vy0[i] - half * acc[1];
-                const double u2 = d.vz0[i] - half * acc[2];
-                hw_at(d, HU + 0, b0 + k) = u0;
-                hw_at(d, HU + 1, b0 + k) = u1;
-                hw_at(d, HU + 2, b0 + k) = u2;
-                S.u[k] = u0;
-                S.v[k] = u1;
-                S.w[k] = u2;
-            }
-        }
-        __syncthreads();
-        // initial force and first step
-        double hloc = INFINITY;
-        for (int k = g; k < n; k += G) {
-            double acc[3], jr[3];
-            herm_pairs(S, n, k, l, L, a.G, rc, a.epsH, acc, jr);
-            for (int c = 0; c < 3; ++c) {
-                acc[c] = group_sum(acc[c], L);
-                jr[c] = group_sum(jr[c], L);
-            }
-            if (l == 0) {
-                const double X[3] = {S.x[k], S.y[k], S.z[k]}, U[3] = {S.u[k], S.v[k], S.w[k]};
-                herm_central(X, U, mu, acc, jr);
-                for (int c = 0; c < 3; ++c) {
-                    hw_at(d, HA + c, b0 + k) = acc[c];
-                    hw_at(d, HJ + c, b0 + k) = jr[c];
-                }
-                const double hb =
-                    a.eta_s * dnorm3(acc[0], acc[1], acc[2]) / dnorm3(jr[0], jr[1], jr[2]);
-                if (hb > 0.0 && hb < hloc) hloc = hb;
-            }
-        }
-        double h = block_min<kHermThreads>(hloc, lds);
-        const double sgn = a.tau >= 0.0 ? 1.0 : -1.0;
-        const double T = fabs(a.tau);
-        double tt = 0.0;
-        int nsub = 0;
-        bool last = (T == 0.0);
-        if (t == 0) s_fail = 0;
-        __syncthreads();
-        while (!last) {
-            if (nsub >= a.max_substeps) {
-                if (t == 0) s_fail = 1;
-                break;
-            }
-            if (!(h > 0.0) || h >= T - tt) {
-                h = T - tt;
-                last = true;
-            }
-            const double hs = sgn * h;
-            // predict into LDS (read by every member's force) and scratch
-            for (int k = t; k < n; k += kHermThreads) {
-                double xp[3], up[3];
-                for (int c = 0; c < 3; ++c) {
-                    const double x = hw_at(d, HX + c, b0 + k), u = hw_at(d, HU + c, b0 + k);
-                    const double ac = hw_at(d, HA + c, b0 + k), jc = hw_at(d, HJ + c, b0 + k);
-                    xp[c] = x + hs * u + hs * hs * ac / 2.0 + hs * hs * hs * jc / 6.0;
-                    up[c] = u + hs * ac + hs * hs * jc / 2.0;
-                    hw_at(d, HXP + c, b0 + k) = xp[c];
-                    hw_at(d, HUP + c, b0 + k) = up[c];
-                }
-                S.x[k] = xp[0]; S.y[k] = xp[1]; S.z[k] = xp[2];
-                S.u[k] = up[0]; S.v[k] = up[1]; S.w[k] = up[2];
-            }
-            __syncthreads();
-            double hn = INFINITY;
-            for (int k = g; k < n; k += G) {
-                double a1[3], j1[3];
-                herm_pairs(S, n, k, l, L, a.G, rc, a.epsH, a1, j1);
-                for (int c = 0; c < 3; ++c) {
-                    a1[c] = group_sum(a1[c], L);
-                    j1[c] = group_sum(j1[c], L);
-                }
-                if (l == 0) {
-                    const double X[3] = {S.x[k], S.y[k], S.z[k]}, U[3] = {S.u[k], S.v[k], S.w[k]};
-                    herm_central(X, U, mu, a1, j1);
-                    double A2e[3], A3v[3];
-                    for (int c = 0; c < 3; ++c) {
-                        const double a0c = hw_at(d, HA + c, b0 + k), j0c = hw_at(d, HJ + c, b0 + k);
-                        const double A2 =
-                            (-6.0 * (a0c - a1[c]) - hs * (4.0 * j0c + 2.0 * j1[c])) / (hs * hs);
-                        const double A3 =
-                            (12.0 * (a0c - a1[c]) + 6.0 * hs * (j0c + j1[c])) / (hs * hs * hs);
-                        const double xp = hw_at(d, HXP + c, b0 + k), up = hw_at(d, HUP + c, b0 + k);
-                        // only this lane touches member k's scratch during the
-                        // force loop (the others read the LDS copy)
-                        hw_at(d, HX + c, b0 + k) =
-                            xp + A2 * hs * hs * hs * hs / 24.0 + A3 * hs * hs * hs * hs * hs / 120.0;
-                        hw_at(d, HU + c, b0 + k) =
-                            up + A2 * hs * hs * hs / 6.0 + A3 * hs * hs * hs * hs / 24.0;
-                        hw_at(d, HA + c, b0 + k) = a1[c];
-                        hw_at(d, HJ + c, b0 + k) = j1[c];
-                        A2e[c] = A2 + hs * A3;
-                        A3v[c] = A3;
-                    }
-                    const double na = dnorm3(a1[0], a1[1], a1[2]), nj = dnorm3(j1[0], j1[1], j1[2]);
-                    const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]);
-                    const double n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
-                    const double hb = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
-                    if (hb > 0.0 && hb < hn) hn = hb;
-                }
-            }
-            hn = block_min<kHermThreads>(hn, lds);   // barriers: forces and scratch done
-            tt += h;
-            ++nsub;
-            h = hn;
-        }
-        __syncthreads();
-        // step 7: stage the final positions, v1 -= tau/2 * W-weighted
-        // in-set forces at q1, write back
-        for (int k = t; k < n; k += kHermThreads) {
-            S.x[k] = hw_at(d, HX + 0, b0 + k);
-            S.y[k] = hw_at(d, HX + 1, b0 + k);
-            S.z[k] = hw_at(d, HX + 2, b0 + k);
-        }
-        __syncthreads();
-        for (int k = g; k < n; k += G) {
-            double acc[3];
-            set_pair_acc(S, n, k, l, L, a.G, rc, acc);
-            for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
-            if (l == 0) {
-                const int i = d.set_mem[b0 + k];
-                d.x[i] = S.x[k];
-                d.y[i] = S.y[k];
-                d.z[i] = S.z[k];
-                d.vx[i] = hw_at(d, HU + 0, b0 + k) - half * acc[0];
-                d.vy[i] = hw_at(d, HU + 1, b0 + k) - half * acc[1];
-                d.vz[i] = hw_at(d, HU + 2, b0 + k) - half * acc[2];
-            }
-        }
+        int nsub, fail;
+        hermite_set_block(a, sidx, SetLds{s_x, s_y, s_z, s_u, s_v, s_w, s_m}, lds, nsub, fail);
         if (t == 0) {
             nsub_b += nsub;
-            fail_b |= s_fail;
+            fail_b |= fail;
         }
-        __syncthreads();
     }
     if (t == 0 && nsub_b > 0) {
         atomicAdd(&d.ctr[C_SUB], (unsigned long long)nsub_b);
