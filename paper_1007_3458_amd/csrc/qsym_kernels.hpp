@@ -506,16 +506,21 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
 // the instruction.
 // ------------------------------------------------------------------------
 
-// lane l receives v of lane (l + 1) mod 64: DPP wave_rol:1 (control 0x134)
-// on both halves, every row and bank enabled (its lane layout checked on
-// the device: lane l reads lane l + 1, lane 63 lane 0)
-__device__ __forceinline__ double lane_rotate1(double v)
+// a double moved between lanes by the DPP pattern CTRL (both halves, every
+// row and bank enabled)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x134, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x134, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+
+// lane l receives v of lane (l + 1) mod 64: DPP wave_rol:1 (control 0x134;
+// its lane layout checked on the device: lane l reads lane l + 1, lane 63
+// lane 0)
+__device__ __forceinline__ double lane_rotate1(double v) { return dpp_f64<0x134>(v); }
 
 // FP64 pair of the symmetric kick: force on i into (ax, ay, az), reaction
 // on j into (fx, fy, fz); keep = false drops the pair
@@ -1483,8 +1488,9 @@ constexpr int kGridThreads = 256;   // workgroup of k_hermite_grid
 constexpr int kHermLds = kHermThreads;   // members of one set staged in LDS
 
 // member scratch layout: field f of member slot k at hw[f * memcap + k]
-// HS..HS+6: staging of sets too large for LDS (x y z u v w m)
-enum { HX = 0, HU = 3, HA = 6, HJ = 9, HXP = 12, HUP = 15, HS = 18, HFIELDS = 25 };
+// HS..HS+6: staging of sets too large for LDS (x y z u v w m; during a
+// substep the predicted state)
+enum { HX = 0, HU = 3, HA = 6, HJ = 9, HS = 12, HFIELDS = 19 };
 
 __device__ __forceinline__ double &hw_at(const Dev &d, int f, int k)
 {
@@ -1495,11 +1501,60 @@ struct SetLds {
     double *x, *y, *z, *u, *v, *w, *m;
 };
 
-// sum over the L lanes of an aligned lane group (fixed xor-tree order)
-__device__ __forceinline__ double group_sum(double v, int L)
+// One level of the sums over aligned lane groups: every lane adds the value
+// of its partner in the next larger group.  Within a row of 16 the
+// partners come through DPP (quad_perm [1,0,3,2] and [2,3,0,1]: the other
+// lane of the pair and of the quad; row_half_mirror and row_mirror: a lane
+// of the other quad of the half row, of the other half of the row), which
+// costs a VALU move instead of an LDS permute; rows exchange through
+// __shfl_xor.  Both partners add the same two values, so every lane of a
+// group ends with the same sum.
+template <int LEVEL>
+__device__ __forceinline__ double group_partner(double v)
 {
-    for (int o = L >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    if constexpr (LEVEL == 0) return dpp_f64<0xB1>(v);
+    else if constexpr (LEVEL == 1) return dpp_f64<0x4E>(v);
+    else if constexpr (LEVEL == 2) return dpp_f64<0x141>(v);
+    else if constexpr (LEVEL == 3) return dpp_f64<0x140>(v);
+    else return __shfl_xor(v, LEVEL == 4 ? 16 : 32, 64);
+}
+
+// one level for N values at once: all N partners are moved before any is
+// added, so the moves' latencies overlap
+template <int LEVEL, int N>
+__device__ __forceinline__ void group_level(double *const (&v)[N], int L)
+{
+    if (L < (2 << LEVEL)) return;
+    double p[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) p[q] = group_partner<LEVEL>(*v[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q) *v[q] += p[q];
+}
+
+// sums over the L lanes (a power of two <= 64, wave-uniform) of each
+// aligned lane group, of N values
+template <int N>
+__device__ __forceinline__ void group_sums(double *const (&v)[N], int L)
+{
+    group_level<0>(v, L);
+    group_level<1>(v, L);
+    group_level<2>(v, L);
+    group_level<3>(v, L);
+    group_level<4>(v, L);
+    group_level<5>(v, L);
+}
+
+__device__ __forceinline__ void group_sum3(double a[3], int L)
+{
+    double *const v[3] = {&a[0], &a[1], &a[2]};
+    group_sums<3>(v, L);
+}
+
+__device__ __forceinline__ void group_sum6(double a[3], double b[3], int L)
+{
+    double *const v[6] = {&a[0], &a[1], &a[2], &b[0], &b[1], &b[2]};
+    group_sums<6>(v, L);
 }
 
 // partial W-weighted in-set acceleration on member a from members
@@ -1567,19 +1622,94 @@ __device__ __forceinline__ void herm_central(const double X[3], const double U[3
 {
     const double r2 = X[0] * X[0] + X[1] * X[1] + X[2] * X[2];
     const double r = sqrt(r2);
-    const double r3 = r2 * r;
+    const double ir3 = 1.0 / (r2 * r);
+    const double ir5 = ir3 / r2;
     const double xv = X[0] * U[0] + X[1] * U[1] + X[2] * U[2];
     for (int c = 0; c < 3; ++c) {
-        acc[c] += -mu * X[c] / r3;
-        jrk[c] += -mu * (U[c] / r3 - 3.0 * xv * X[c] / (r3 * r2));
+        acc[c] += -mu * X[c] * ir3;
+        jrk[c] += -mu * (U[c] * ir3 - 3.0 * xv * X[c] * ir5);
     }
 }
 
+// powers of one signed substep hs of the Hermite scheme: the Taylor
+// factors hs^k / k! of the predictor and corrector and 1/hs^2, 1/hs^3 of
+// the interpolated second and third derivatives (one division per substep)
+struct HermStep {
+    double hs, c2, c3, c4, c5, i2, i3;
+};
+
+__device__ __forceinline__ HermStep herm_step(double hs)
+{
+    HermStep k;
+    const double h2 = hs * hs, h3 = h2 * hs;
+    k.hs = hs;
+    k.c2 = h2 * 0.5;
+    k.c3 = h3 * (1.0 / 6.0);
+    k.c4 = h2 * h2 * (1.0 / 24.0);
+    k.c5 = h3 * h2 * (1.0 / 120.0);
+    const double ih = 1.0 / hs;
+    k.i2 = ih * ih;
+    k.i3 = k.i2 * ih;
+    return k;
+}
+
+// predictor: Taylor series of x to the jerk term, of u to the jerk term
+__device__ __forceinline__ void herm_predict(const HermStep &k, const double X[3], const double U[3],
+                                             const double A[3], const double J[3], double xp[3],
+                                             double up[3])
+{
+    for (int c = 0; c < 3; ++c) {
+        xp[c] = X[c] + k.hs * U[c] + k.c2 * A[c] + k.c3 * J[c];
+        up[c] = U[c] + k.hs * A[c] + k.c2 * J[c];
+    }
+}
+
+// corrector: second and third derivatives from (A, J) at the start and
+// (a1, j1) at the predicted end, the fourth- and fifth-order terms added to
+// the prediction; (A, J) become (a1, j1).  Returns the member's next step
+// from the time-step criterion on |a|, |j|, |a''|, |a'''| at the end.
+__device__ __forceinline__ double herm_correct(const HermStep &k, double eta, const double a1[3],
+                                               const double j1[3], const double xp[3],
+                                               const double up[3], double X[3], double U[3],
+                                               double A[3], double J[3])
+{
+    double A2e[3], A3v[3];
+    for (int c = 0; c < 3; ++c) {
+        const double da = A[c] - a1[c];
+        const double A2 = (-6.0 * da - k.hs * (4.0 * J[c] + 2.0 * j1[c])) * k.i2;
+        const double A3 = (12.0 * da + 6.0 * k.hs * (J[c] + j1[c])) * k.i3;
+        X[c] = xp[c] + A2 * k.c4 + A3 * k.c5;
+        U[c] = up[c] + A2 * k.c3 + A3 * k.c4;
+        A[c] = a1[c];
+        J[c] = j1[c];
+        A2e[c] = A2 + k.hs * A3;
+        A3v[c] = A3;
+    }
+    const double na = dnorm3(a1[0], a1[1], a1[2]), nj = dnorm3(j1[0], j1[1], j1[2]);
+    const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]);
+    const double n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
+    return sqrt(eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// minimum over the wave (fmin: NaN only where every lane has NaN): the
+// row minima through the DPP levels of the group sums, then the four rows
+// read into scalar registers
 __device__ __forceinline__ double wave_min(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmin(v, group_partner<0>(v));
+    v = fmin(v, group_partner<1>(v));
+    v = fmin(v, group_partner<2>(v));
+    v = fmin(v, group_partner<3>(v));
+    return fmin(fmin(readlane_f64(v, 0), readlane_f64(v, 16)),
+                fmin(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
 // a value equal on all lanes (a wave reduction) moved to scalar registers,
@@ -1629,7 +1759,7 @@ __device__ void hermite_set_wave(const HermArgs &a, int sidx, const SetLds &S, i
     {
         double acc[3];
         set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
-        for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+        group_sum3(acc, L);
         U[0] = d.vx0[i] - half * acc[0];
         U[1] = d.vy0[i] - half * acc[1];
         U[2] = d.vz0[i] - half * acc[2];
@@ -1643,10 +1773,7 @@ __device__ void hermite_set_wave(const HermArgs &a, int sidx, const SetLds &S, i
     // initial force and first step
     double hloc = INFINITY;
     herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, A, J);
-    for (int c = 0; c < 3; ++c) {
-        A[c] = group_sum(A[c], L);
-        J[c] = group_sum(J[c], L);
-    }
+    group_sum6(A, J, L);
     herm_central(X, U, mu, A, J);
     {
         const double hb = a.eta_s * dnorm3(A[0], A[1], A[2]) / dnorm3(J[0], J[1], J[2]);
@@ -1667,12 +1794,9 @@ __device__ void hermite_set_wave(const HermArgs &a, int sidx, const SetLds &S, i
             h = T - tt;
             last = true;
         }
-        const double hs = sgn * h;
+        const HermStep hk = herm_step(sgn * h);
         double xp[3], up[3];
-        for (int c = 0; c < 3; ++c) {
-            xp[c] = X[c] + hs * U[c] + hs * hs * A[c] / 2.0 + hs * hs * hs * J[c] / 6.0;
-            up[c] = U[c] + hs * A[c] + hs * hs * J[c] / 2.0;
-        }
+        herm_predict(hk, X, U, A, J, xp, up);
         wave_lds_sync();   // every lane is done reading the previous state
         if (mine && l == 0) {
             S.x[k] = xp[0]; S.y[k] = xp[1]; S.z[k] = xp[2];
@@ -1681,26 +1805,9 @@ __device__ void hermite_set_wave(const HermArgs &a, int sidx, const SetLds &S, i
         wave_lds_sync();
         double a1[3], j1[3];
         herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, a1, j1);
-        for (int c = 0; c < 3; ++c) {
-            a1[c] = group_sum(a1[c], L);
-            j1[c] = group_sum(j1[c], L);
-        }
+        group_sum6(a1, j1, L);
         herm_central(xp, up, mu, a1, j1);
-        double A2e[3], A3v[3];
-        for (int c = 0; c < 3; ++c) {
-            const double A2 = (-6.0 * (A[c] - a1[c]) - hs * (4.0 * J[c] + 2.0 * j1[c])) / (hs * hs);
-            const double A3 = (12.0 * (A[c] - a1[c]) + 6.0 * hs * (J[c] + j1[c])) / (hs * hs * hs);
-            X[c] = xp[c] + A2 * hs * hs * hs * hs / 24.0 + A3 * hs * hs * hs * hs * hs / 120.0;
-            U[c] = up[c] + A2 * hs * hs * hs / 6.0 + A3 * hs * hs * hs * hs / 24.0;
-            A[c] = a1[c];
-            J[c] = j1[c];
-            A2e[c] = A2 + hs * A3;
-            A3v[c] = A3;
-        }
-        const double na = dnorm3(a1[0], a1[1], a1[2]), nj = dnorm3(j1[0], j1[1], j1[2]);
-        const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]);
-        const double n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
-        const double hb = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
+        const double hb = herm_correct(hk, a.eta, a1, j1, xp, up, X, U, A, J);
         tt += h;
         ++nsub;
         h = wave_uniform(wave_min((mine && hb > 0.0) ? hb : INFINITY));
@@ -1715,7 +1822,7 @@ __device__ void hermite_set_wave(const HermArgs &a, int sidx, const SetLds &S, i
     wave_lds_sync();
     double acc[3];
     set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
-    for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+    group_sum3(acc, L);
     if (mine && l == 0) {
         d.x[i] = X[0];
         d.y[i] = X[1];
@@ -1778,7 +1885,7 @@ __device__ void hermite_set_block(const HermArgs &a, int sidx, const SetLds &S, 
     {
         double acc[3];
         set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
-        for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+        group_sum3(acc, L);
         U[0] = d.vx0[i] - half * acc[0];
         U[1] = d.vy0[i] - half * acc[1];
         U[2] = d.vz0[i] - half * acc[2];
@@ -1791,10 +1898,7 @@ __device__ void hermite_set_block(const HermArgs &a, int sidx, const SetLds &S, 
     __syncthreads();
     // initial force and first step
     herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, A, J);
-    for (int c = 0; c < 3; ++c) {
-        A[c] = group_sum(A[c], L);
-        J[c] = group_sum(J[c], L);
-    }
+    group_sum6(A, J, L);
     herm_central(X, U, mu, A, J);
     double hloc = INFINITY;
     {
@@ -1816,12 +1920,9 @@ __device__ void hermite_set_block(const HermArgs &a, int sidx, const SetLds &S, 
             h = T - tt;
             last = true;
         }
-        const double hs = sgn * h;
+        const HermStep hk = herm_step(sgn * h);
         double xp[3], up[3];
-        for (int c = 0; c < 3; ++c) {
-            xp[c] = X[c] + hs * U[c] + hs * hs * A[c] / 2.0 + hs * hs * hs * J[c] / 6.0;
-            up[c] = U[c] + hs * A[c] + hs * hs * J[c] / 2.0;
-        }
+        herm_predict(hk, X, U, A, J, xp, up);
         __syncthreads();   // every lane is done reading the previous state (and red)
         if (mine && l == 0) {
             S.x[k] = xp[0]; S.y[k] = xp[1]; S.z[k] = xp[2];
@@ -1830,26 +1931,9 @@ __device__ void hermite_set_block(const HermArgs &a, int sidx, const SetLds &S, 
         __syncthreads();
         double a1[3], j1[3];
         herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, a1, j1);
-        for (int c = 0; c < 3; ++c) {
-            a1[c] = group_sum(a1[c], L);
-            j1[c] = group_sum(j1[c], L);
-        }
+        group_sum6(a1, j1, L);
         herm_central(xp, up, mu, a1, j1);
-        double A2e[3], A3v[3];
-        for (int c = 0; c < 3; ++c) {
-            const double A2 = (-6.0 * (A[c] - a1[c]) - hs * (4.0 * J[c] + 2.0 * j1[c])) / (hs * hs);
-            const double A3 = (12.0 * (A[c] - a1[c]) + 6.0 * hs * (J[c] + j1[c])) / (hs * hs * hs);
-            X[c] = xp[c] + A2 * hs * hs * hs * hs / 24.0 + A3 * hs * hs * hs * hs * hs / 120.0;
-            U[c] = up[c] + A2 * hs * hs * hs / 6.0 + A3 * hs * hs * hs * hs / 24.0;
-            A[c] = a1[c];
-            J[c] = j1[c];
-            A2e[c] = A2 + hs * A3;
-            A3v[c] = A3;
-        }
-        const double na = dnorm3(a1[0], a1[1], a1[2]), nj = dnorm3(j1[0], j1[1], j1[2]);
-        const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]);
-        const double n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
-        const double hb = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
+        const double hb = herm_correct(hk, a.eta, a1, j1, xp, up, X, U, A, J);
         tt += h;
         ++nsub;
         h = block_min_waves((mine && hb > 0.0) ? hb : INFINITY, red);
@@ -1864,7 +1948,7 @@ __device__ void hermite_set_block(const HermArgs &a, int sidx, const SetLds &S, 
     __syncthreads();
     double acc[3];
     set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
-    for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+    group_sum3(acc, L);
     if (mine && l == 0) {
         d.x[i] = X[0];
         d.y[i] = X[1];
@@ -2061,7 +2145,7 @@ __global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
             const int kk = k < n ? k : 0;
             double acc[3];
             set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
-            for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+            group_sum3(acc, L);
             if (k < n && l == 0) {
                 const int i = d.set_mem[b0 + k];
                 hw_at(d, HX + 0, b0 + k) = S.x[k];
@@ -2086,10 +2170,7 @@ __global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
             const int kk = k < n ? k : 0;
             double acc[3], jr[3];
             herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, acc, jr);
-            for (int c = 0; c < 3; ++c) {
-                acc[c] = group_sum(acc[c], L);
-                jr[c] = group_sum(jr[c], L);
-            }
+            group_sum6(acc, jr, L);
             if (k < n && l == 0) {
                 const double X[3] = {S.x[k], S.y[k], S.z[k]}, U[3] = {S.u[k], S.v[k], S.w[k]};
                 herm_central(X, U, mu, acc, jr);
@@ -2124,18 +2205,18 @@ __global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
                 h = T - tt;
                 last = true;
             }
-            const double hs = sgn * h;
-            // predict: scratch and the staged copy read by every member's force
+            const HermStep hk = herm_step(sgn * h);
+            // predict into the staged copy: every member's force reads it, the
+            // corrector takes it as the prediction
             for (int k = gtid; k < n; k += nthr) {
-                double xp[3], up[3];
+                double X[3], U[3], A[3], J[3], xp[3], up[3];
                 for (int c = 0; c < 3; ++c) {
-                    const double x = hw_at(d, HX + c, b0 + k), u = hw_at(d, HU + c, b0 + k);
-                    const double ac = hw_at(d, HA + c, b0 + k), jc = hw_at(d, HJ + c, b0 + k);
-                    xp[c] = x + hs * u + hs * hs * ac / 2.0 + hs * hs * hs * jc / 6.0;
-                    up[c] = u + hs * ac + hs * hs * jc / 2.0;
-                    hw_at(d, HXP + c, b0 + k) = xp[c];
-                    hw_at(d, HUP + c, b0 + k) = up[c];
+                    X[c] = hw_at(d, HX + c, b0 + k);
+                    U[c] = hw_at(d, HU + c, b0 + k);
+                    A[c] = hw_at(d, HA + c, b0 + k);
+                    J[c] = hw_at(d, HJ + c, b0 + k);
                 }
+                herm_predict(hk, X, U, A, J, xp, up);
                 S.x[k] = xp[0]; S.y[k] = xp[1]; S.z[k] = xp[2];
                 S.u[k] = up[0]; S.v[k] = up[1]; S.w[k] = up[2];
             }
@@ -2146,34 +2227,22 @@ __global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
                 const int kk = k < n ? k : 0;
                 double a1[3], j1[3];
                 herm_pairs(S, n, kk, l, L, a.G, rc, a.epsH, a1, j1);
-                for (int c = 0; c < 3; ++c) {
-                    a1[c] = group_sum(a1[c], L);
-                    j1[c] = group_sum(j1[c], L);
-                }
+                group_sum6(a1, j1, L);
                 if (k < n && l == 0) {
-                    const double X[3] = {S.x[k], S.y[k], S.z[k]}, U[3] = {S.u[k], S.v[k], S.w[k]};
-                    herm_central(X, U, mu, a1, j1);
-                    double A2e[3], A3v[3];
+                    const double xp[3] = {S.x[k], S.y[k], S.z[k]}, up[3] = {S.u[k], S.v[k], S.w[k]};
+                    herm_central(xp, up, mu, a1, j1);
+                    double X[3], U[3], A[3], J[3];
                     for (int c = 0; c < 3; ++c) {
-                        const double a0c = hw_at(d, HA + c, b0 + k), j0c = hw_at(d, HJ + c, b0 + k);
-                        const double A2 =
-                            (-6.0 * (a0c - a1[c]) - hs * (4.0 * j0c + 2.0 * j1[c])) / (hs * hs);
-                        const double A3 =
-                            (12.0 * (a0c - a1[c]) + 6.0 * hs * (j0c + j1[c])) / (hs * hs * hs);
-                        const double xp = hw_at(d, HXP + c, b0 + k), up = hw_at(d, HUP + c, b0 + k);
-                        hw_at(d, HX + c, b0 + k) =
-                            xp + A2 * hs * hs * hs * hs / 24.0 + A3 * hs * hs * hs * hs * hs / 120.0;
-                        hw_at(d, HU + c, b0 + k) =
-                            up + A2 * hs * hs * hs / 6.0 + A3 * hs * hs * hs * hs / 24.0;
-                        hw_at(d, HA + c, b0 + k) = a1[c];
-                        hw_at(d, HJ + c, b0 + k) = j1[c];
-                        A2e[c] = A2 + hs * A3;
-                        A3v[c] = A3;
+                        A[c] = hw_at(d, HA + c, b0 + k);
+                        J[c] = hw_at(d, HJ + c, b0 + k);
                     }
-                    const double na = dnorm3(a1[0], a1[1], a1[2]), nj = dnorm3(j1[0], j1[1], j1[2]);
-                    const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]);
-                    const double n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
-                    const double hb = sqrt(a.eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
+                    const double hb = herm_correct(hk, a.eta, a1, j1, xp, up, X, U, A, J);
+                    for (int c = 0; c < 3; ++c) {
+                        hw_at(d, HX + c, b0 + k) = X[c];
+                        hw_at(d, HU + c, b0 + k) = U[c];
+                        hw_at(d, HA + c, b0 + k) = A[c];
+                        hw_at(d, HJ + c, b0 + k) = J[c];
+                    }
                     if (hb > 0.0 && hb < hn) hn = hb;
                 }
             }
@@ -2201,7 +2270,7 @@ __global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
             const int kk = k < n ? k : 0;
             double acc[3];
             set_pair_acc(S, n, kk, l, L, a.G, rc, acc);
-            for (int c = 0; c < 3; ++c) acc[c] = group_sum(acc[c], L);
+            group_sum3(acc, L);
             if (k < n && l == 0) {
                 const int i = d.set_mem[b0 + k];
                 d.x[i] = S.x[k];
