@@ -35,8 +35,6 @@ enum Ctr {
     C_NU,         // bodies in encounters, last step
     C_NSMALL,     // sets of at most kWaveMax members (one wave each), last step
     C_NBIG,       // larger sets (one workgroup each), last step
-    C_HQS,        // Hermite work-queue heads (small, big)
-    C_HQB,
     C_HIST = 16,  // kHist bins
     C_WHOLE = C_HIST + kHist,   // systems integrated whole (all steps)
     C_NLARGE,     // grid sweep: bodies on the large list, last step

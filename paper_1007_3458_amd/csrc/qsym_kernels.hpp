@@ -133,8 +133,6 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
         d.ctr[C_NU] = 0;
         d.ctr[C_NSMALL] = 0;
         d.ctr[C_NBIG] = 0;
-        d.ctr[C_HQS] = 0;
-        d.ctr[C_HQB] = 0;
         d.ctr[C_NLARGE] = 0;
         d.gbar[0] = 0u;
         d.gbar[1] = 0u;
@@ -1965,10 +1963,9 @@ __device__ void hermite_set_block(const HermArgs &a, int sidx, const SetLds &S, 
 // Sec. 2.3 steps 5-7 for every set of at most kCoopMin members.  Sets of
 // more than kWaveMax members first, one workgroup each (hermite_set_block:
 // the set staged in LDS, each member's state in the registers of its lane
-// group); then the small sets, one wave each (hermite_set_wave).  Both take
-// their sets from work queues, so a block or wave that finishes early takes
-// the next set; every set is integrated on its own, so the order changes
-// nothing in the results.  Larger sets run on the whole grid
+// group); then the small sets, one wave each (hermite_set_wave), both in a
+// fixed assignment; every set is integrated on its own, so the assignment
+// changes nothing in the results.  Larger sets run on the whole grid
 // (k_hermite_grid): from about 250 members its two grid barriers per
 // substep cost less than the n^2 / 512 pair terms per lane of one
 // workgroup.
@@ -1980,16 +1977,16 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
     __shared__ double s_x[kHermLds], s_y[kHermLds], s_z[kHermLds];
     __shared__ double s_u[kHermLds], s_v[kHermLds], s_w[kHermLds], s_m[kHermLds];
     __shared__ double lds[kHermThreads / 64];
-    __shared__ int s_item;
     const int t = threadIdx.x;
+    const int nwg = gridDim.x, wpb = kHermThreads / 64;
     const int nbig = (int)d.ctr[C_NBIG];
+    // Sets are assigned statically, with no work-queue counter: thousands
+    // of atomics on one counter congest its L2 channel, and every wave with
+    // a lane whose load maps there waits for them.  Workgroup b takes the
+    // larger sets b, b + grid, ... (at most one each unless there are more
+    // larger sets than workgroups).
     int nsub_b = 0, fail_b = 0;   // statistics of thread 0, added after the loop
-    for (;;) {
-        if (t == 0) s_item = (int)atomicAdd(&d.ctr[C_HQB], 1ull);
-        __syncthreads();
-        const int q = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (q >= nbig) break;
+    for (int q = blockIdx.x; q < nbig; q += nwg) {
         const int sidx = d.set_list[d.setcap - 1 - q];
         if (d.set_count[sidx] > kCoopMin) continue;   // k_hermite_grid takes it
         int nsub, fail;
@@ -2004,24 +2001,21 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
         atomicAdd(&d.ctr[C_TSUB], (unsigned long long)nsub_b);
     }
     if (t == 0 && fail_b) latch(d.ctr, S_HERMITE);
-    // small sets, one wave each, in the wave's slice of the staging arrays
-    const int w = t >> 6, lane = t & 63;
+    // small sets, one wave each, in the wave's slice of the staging arrays:
+    // round robin over the waves, those of the workgroups without a larger
+    // set first
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
     const SetLds S = {s_x + w * kWaveMax, s_y + w * kWaveMax, s_z + w * kWaveMax,
                       s_u + w * kWaveMax, s_v + w * kWaveMax, s_w + w * kWaveMax,
                       s_m + w * kWaveMax};
     const int nsmall = (int)d.ctr[C_NSMALL];
-    // The pop has no lane branch: every lane takes part in the atomic (lane
-    // 0 adds one, the others zero) and lane 0's old value, read into a
-    // scalar register, is the wave's item.  A pop under `if (lane == 0)`
-    // followed by a shuffle lets the compiler merge that branch with the
-    // lane-0 statistics branch of the previous iteration, which splits the
-    // wave over two loop nests and leaves the shuffle without lane 0.  The
-    // statistics are therefore also kept out of the loop.
+    const int busy = min(nbig, nwg);
+    const int rank = ((int)blockIdx.x - busy + nwg) % nwg;
+    // The loop runs on scalar values only and keeps the statistics out of
+    // its body: lane-0 branches at both ends of a loop body can be merged
+    // by the compiler across the back edge, which splits the wave.
     int nsub_w = 0, fail_w = 0;
-    for (;;) {
-        const unsigned long long old = atomicAdd(&d.ctr[C_HQS], lane == 0 ? 1ull : 0ull);
-        const int q = __builtin_amdgcn_readfirstlane((int)old);
-        if (q >= nsmall) break;
+    for (int q = rank * wpb + w; q < nsmall; q += nwg * wpb) {
         int nsub, fail;
         hermite_set_wave(a, d.set_list[q], S, lane, nsub, fail);
         nsub_w += nsub;
