@@ -278,6 +278,7 @@ struct qsym_ctx {
     long long phase_calls[kPhases] = {};
     bool guess_loaded = false;
     int grid_blocks = 256;   // workgroups of k_hermite_grid: the device's compute units
+    int apply_parts = 1;     // threads per body of the partial-sum reduction (1 or 4)
     double tau_crude = 0.0;  // |tau| of the crude sweep being enqueued
     std::string err;
 };
@@ -564,11 +565,17 @@ hipError_t run_apply(qsym_ctx *c, double dt_kick, double dt_kep, int do_kick, in
     const bool small = do_kep && !momentum;
     ApplyArgs a{c->d, small ? c->d.kchunk : c->d.bchunk, c->d.sys_K + (size_t)which * c->nsys,
                 dt_kick, dt_kep, c->p.G, do_kick, do_kep, snapshot, c->p.kepler_mode, momentum};
-    if (small)
-        hipLaunchKernelGGL(k_apply_kepler<kChunkK>, dim3((unsigned)c->T.kchunk.size()), dim3(kChunkK), 0,
-                           st, a);
-    else
-        hipLaunchKernelGGL(k_apply_kepler<kChunk>, dim3(nblocks_chunks(c)), dim3(kChunk), 0, st, a);
+    // systems of many bodies (tens of partial-sum slots per body, few
+    // chunks) share each body's reduction over four threads; many small
+    // systems keep one thread per body
+    const dim3 gk((unsigned)c->T.kchunk.size()), gb(nblocks_chunks(c));
+    if (c->apply_parts == 4) {
+        if (small) hipLaunchKernelGGL((k_apply_kepler<kChunkK, 4>), gk, dim3(kChunkK * 4), 0, st, a);
+        else hipLaunchKernelGGL((k_apply_kepler<kChunk, 4>), gb, dim3(kChunk * 4), 0, st, a);
+    } else {
+        if (small) hipLaunchKernelGGL((k_apply_kepler<kChunkK, 1>), gk, dim3(kChunkK), 0, st, a);
+        else hipLaunchKernelGGL((k_apply_kepler<kChunk, 1>), gb, dim3(kChunk), 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -820,6 +827,11 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
     if (hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
         return bail(QSYM_EHIP, "hipEventCreateWithFlags");
     build_tables(c);
+    {
+        long long nmax = 0;
+        for (int k = 0; k < nsys; ++k) nmax = std::max<long long>(nmax, c->off[k + 1] - c->off[k]);
+        c->apply_parts = nmax >= 8192 ? 4 : 1;
+    }
     enter(c);
     hipStream_t st = c->stream;
     // zero the whole workspace once (outside any graph)

@@ -825,8 +825,11 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
 // chunks from il's own chunk cx on (the chunks it meets as an i), then the
 // j-side slots of its chunk, one per i-range of RB bodies below the chunk's
 // end.  Always summed in slot order.
+// share `part` of P of the partial-sum slots of local body il: the body's
+// slots (its i-side chunks, then for the symmetric kick the j-side
+// i-ranges that reach it) in list order, every P-th from the part-th
 __device__ __forceinline__ void sum_partials(const Dev &d, const int4 *sysK, int s, int il,
-                                             double a[3])
+                                             int part, int P, double a[3])
 {
     const int ns = d.sys_off[s + 1] - d.sys_off[s];
     const int4 K = sysK[s];
@@ -838,13 +841,9 @@ __device__ __forceinline__ void sum_partials(const Dev &d, const int4 *sysK, int
         c0 = cx;
         r1 = (min((cx + 1) * K.y, ns) + K.z - 1) / K.z;
     }
-    for (int c = c0; c < c1; ++c) {
-        ax += p[(long long)(3 * c) * ns];
-        ay += p[(long long)(3 * c + 1) * ns];
-        az += p[(long long)(3 * c + 2) * ns];
-    }
-    for (int r = 0; r < r1; ++r) {
-        const long long sl = K.x + r;
+    const int ni = c1 - c0;
+    for (int q = part; q < ni + r1; q += P) {
+        const long long sl = q < ni ? c0 + q : K.x + (q - ni);
         ax += p[(3 * sl) * ns];
         ay += p[(3 * sl + 1) * ns];
         az += p[(3 * sl + 2) * ns];
@@ -867,10 +866,16 @@ struct ApplyArgs {
     int do_kick, do_kep, snapshot, kepler_mode, momentum;
 };
 
-template <int BS>
-__global__ __launch_bounds__(BS) void k_apply_kepler(ApplyArgs a)
+template <int BS, int P>
+__global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
 {
-    __shared__ double lds[BS];
+    // P threads per body share the reduction of its partial-sum slots (one
+    // body's serial sum over tens of slots is bound by memory latency): the
+    // p-th thread group of BS sums every P-th slot from the p-th for the
+    // chunk's consecutive bodies, and the P shares are added in order.  The
+    // per-body steps then run on the first BS threads.
+    __shared__ double lds[BS * P];
+    __shared__ double share[P > 1 ? P : 1][3][BS];
     __shared__ unsigned int hist[kHist];
     __shared__ unsigned int kmax;
     __shared__ unsigned long long ksum;
@@ -885,15 +890,30 @@ __global__ __launch_bounds__(BS) void k_apply_kepler(ApplyArgs a)
         ksum = 0;
         bad = 0;
     }
+    double sh[3] = {0.0, 0.0, 0.0};
+    if (P > 1 && a.do_kick) {
+        const int bt = t % BS, part = t / BS;
+        if (bt < bc.z) sum_partials(d, a.sysK, s, bc.y + bt - d.sys_off[s], part, P, sh);
+        share[part][0][bt] = sh[0];
+        share[part][1][bt] = sh[1];
+        share[part][2][bt] = sh[2];
+    }
     __syncthreads();
     double mom[3] = {0.0, 0.0, 0.0};
-    if (t < bc.z) {
+    if (t < BS && t < bc.z) {
         const int i = bc.y + t;
         double x = d.x[i], y = d.y[i], z = d.z[i];
         double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
         if (a.do_kick) {
             double acc[3];
-            sum_partials(d, a.sysK, s, i - d.sys_off[s], acc);
+            if constexpr (P > 1) {
+                for (int c = 0; c < 3; ++c) {
+                    acc[c] = share[0][c][t];
+                    for (int q = 1; q < P; ++q) acc[c] += share[q][c][t];
+                }
+            } else {
+                sum_partials(d, a.sysK, s, i - d.sys_off[s], 0, 1, acc);
+            }
             vx += a.dt_kick * acc[0];
             vy += a.dt_kick * acc[1];
             vz += a.dt_kick * acc[2];
@@ -931,7 +951,7 @@ __global__ __launch_bounds__(BS) void k_apply_kepler(ApplyArgs a)
     }
     if (a.momentum) {
         for (int k = 0; k < 3; ++k) {
-            double sm = block_sum<BS>(mom[k], lds);
+            double sm = block_sum<BS * P>(mom[k], lds);
             if (t == 0) d.pm[3 * blockIdx.x + k] = sm;
         }
     }
