@@ -1250,31 +1250,74 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     }
     const int ne = cnt;
     if (ne == 0) return;
-    int m2 = kSetsThreads;
-    while (m2 < 2 * ne) m2 <<= 1;
-    for (int k = t; k < m2; k += blockDim.x) {
-        if (k < 2 * ne) {
-            const int2 p = enc[k >> 1];
-            ep[k] = (unsigned)((k & 1) ? p.y : p.x);
-        } else {
-            ep[k] = 0xffffffffu;
+    // the bodies taking part (ascending, uq[0..nu)) and every pair as the
+    // ranks of its two bodies in that list
+    const int so = d.sys_off[sys], nsb = d.sys_off[sys + 1] - so;
+    int nu;
+    if (nsb <= 32 * kCapU) {
+        // from a bitmap of the system's bodies (in flag): the set bits in
+        // ascending order are the bodies, a body's rank is the number of set
+        // bits before it (popcount prefix over the words, in ep)
+        unsigned *bits = reinterpret_cast<unsigned *>(flag);
+        int *wpre = reinterpret_cast<int *>(ep);
+        const int nw = (nsb + 31) >> 5;
+        for (int k = t; k < nw; k += blockDim.x) bits[k] = 0u;
+        __syncthreads();
+        for (int k = t; k < ne; k += blockDim.x) {
+            const int2 p = enc[k];
+            atomicOr(&bits[(p.x - so) >> 5], 1u << ((p.x - so) & 31));
+            atomicOr(&bits[(p.y - so) >> 5], 1u << ((p.y - so) & 31));
         }
-    }
-    __syncthreads();
-    block_sort_u32(ep, m2);
-    for (int k = t; k < 2 * ne; k += blockDim.x) flag[k] = (k == 0 || ep[k] != ep[k - 1]) ? 1 : 0;
-    __syncthreads();
-    for (int k = t; k < 2 * ne; k += blockDim.x) lab[k] = (unsigned)flag[k];
-    __syncthreads();
-    const int nu = block_scan_excl(flag, 2 * ne, tmp);
-    for (int k = t; k < 2 * ne; k += blockDim.x)
-        if (lab[k]) uq[flag[k]] = ep[k];
-    __syncthreads();
-    for (int k = t; k < ne; k += blockDim.x) {
-        const int2 p = enc[k];
-        const int ri = lower_rank(uq, nu, (unsigned)p.x);
-        const int rj = lower_rank(uq, nu, (unsigned)p.y);
-        rp[k] = ((unsigned)ri << 16) | (unsigned)rj;
+        __syncthreads();
+        for (int k = t; k < nw; k += blockDim.x) wpre[k] = __popc(bits[k]);
+        __syncthreads();
+        nu = block_scan_excl(wpre, nw, tmp);
+        for (int k = t; k < nw; k += blockDim.x) {
+            unsigned w = bits[k];
+            int r = wpre[k];
+            while (w) {
+                uq[r++] = (unsigned)(so + (k << 5) + __ffs(w) - 1);
+                w &= w - 1u;
+            }
+        }
+        for (int k = t; k < ne; k += blockDim.x) {
+            const int2 p = enc[k];
+            const int bx = p.x - so, by = p.y - so;
+            const int ri = wpre[bx >> 5] + __popc(bits[bx >> 5] & ((1u << (bx & 31)) - 1u));
+            const int rj = wpre[by >> 5] + __popc(bits[by >> 5] & ((1u << (by & 31)) - 1u));
+            rp[k] = ((unsigned)ri << 16) | (unsigned)rj;
+        }
+        __syncthreads();
+    } else {
+        // larger systems: sort the endpoints, keep the first of each run,
+        // rank by binary search
+        int m2 = kSetsThreads;
+        while (m2 < 2 * ne) m2 <<= 1;
+        for (int k = t; k < m2; k += blockDim.x) {
+            if (k < 2 * ne) {
+                const int2 p = enc[k >> 1];
+                ep[k] = (unsigned)((k & 1) ? p.y : p.x);
+            } else {
+                ep[k] = 0xffffffffu;
+            }
+        }
+        __syncthreads();
+        block_sort_u32(ep, m2);
+        for (int k = t; k < 2 * ne; k += blockDim.x) flag[k] = (k == 0 || ep[k] != ep[k - 1]) ? 1 : 0;
+        __syncthreads();
+        for (int k = t; k < 2 * ne; k += blockDim.x) lab[k] = (unsigned)flag[k];
+        __syncthreads();
+        nu = block_scan_excl(flag, 2 * ne, tmp);
+        for (int k = t; k < 2 * ne; k += blockDim.x)
+            if (lab[k]) uq[flag[k]] = ep[k];
+        __syncthreads();
+        for (int k = t; k < ne; k += blockDim.x) {
+            const int2 p = enc[k];
+            const int ri = lower_rank(uq, nu, (unsigned)p.x);
+            const int rj = lower_rank(uq, nu, (unsigned)p.y);
+            rp[k] = ((unsigned)ri << 16) | (unsigned)rj;
+        }
+        __syncthreads();
     }
     for (int k = t; k < nu; k += blockDim.x) lab[k] = (unsigned)k;
     __syncthreads();
@@ -1369,7 +1412,10 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
         const unsigned root = ep[k] >> 16;
         const bool first = (k == 0) || ((ep[k - 1] >> 16) != root);
         const int sid = flag[root];
-        if (first) d.set_start[bs + sid] = bm + k;
+        if (first) {
+            d.set_start[bs + sid] = bm + k;
+            rp[sid] = (unsigned)k;   // local start (the rank pairs are done with)
+        }
         lab[k] = (unsigned)sid;
     }
     __syncthreads();
@@ -1387,23 +1433,32 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     __syncthreads();
     for (int sidx = t; sidx < nsets; sidx += blockDim.x)
         d.set_rc[bs + sidx] = a.aH * __longlong_as_double((long long)rcb[sidx]);
-    // set sizes (and the largest)
+    // set sizes from the local starts (and the largest); the work lists of
+    // the Hermite kernel: the sets' places in the small and the larger list
+    // from one scan of packed counts (small sets in the low, larger ones in
+    // the high 16 bits; nsets <= kCapE), one atomic per list for the base
+    __syncthreads();   // rcb (flag) read
     unsigned int big = 0;
-    for (int k = t; k < nu; k += blockDim.x) {
-        const bool first = (k == 0) || (lab[k - 1] != lab[k]);
-        if (first) {
-            int e = k + 1;
-            while (e < nu && lab[e] == lab[k]) ++e;
-            const int sid = bs + (int)lab[k];
-            d.set_count[sid] = e - k;
-            if ((unsigned)(e - k) > big) big = (unsigned)(e - k);
-            // work lists of the Hermite kernel (their order does not matter:
-            // every set is integrated on its own)
-            if (e - k <= kWaveMax)
-                d.set_list[(int)atomicAdd(&d.ctr[C_NSMALL], 1ull)] = sid;
-            else
-                d.set_list[d.setcap - 1 - (int)atomicAdd(&d.ctr[C_NBIG], 1ull)] = sid;
-        }
+    for (int sid = t; sid < nsets; sid += blockDim.x) {
+        const int n = (sid + 1 < nsets ? (int)rp[sid + 1] : nu) - (int)rp[sid];
+        d.set_count[bs + sid] = n;
+        if ((unsigned)n > big) big = (unsigned)n;
+        flag[sid] = n <= kWaveMax ? 1 : 0x10000;
+    }
+    __syncthreads();
+    const int tot = block_scan_excl(flag, nsets, tmp);
+    if (t == 0) {
+        base_set = (int)atomicAdd(&d.ctr[C_NSMALL], (unsigned long long)(tot & 0xffff));
+        base_mem = (int)atomicAdd(&d.ctr[C_NBIG], (unsigned long long)(tot >> 16));
+    }
+    __syncthreads();
+    for (int sid = t; sid < nsets; sid += blockDim.x) {
+        const int n = (sid + 1 < nsets ? (int)rp[sid + 1] : nu) - (int)rp[sid];
+        const int pos = flag[sid];
+        if (n <= kWaveMax)
+            d.set_list[base_set + (pos & 0xffff)] = bs + sid;
+        else
+            d.set_list[d.setcap - 1 - (base_mem + (pos >> 16))] = bs + sid;
     }
     if (big) atomicMax(&d.ctr[C_MAXSET], (unsigned long long)big);
     if (t == 0) atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);

@@ -353,6 +353,52 @@ def test_fp32_form_accuracy_and_step(Q, orc):
     ctx.close()
 
 
+def _components(pairs, n):
+    """Set id per body from the encounter pairs: connected components (plain
+    union-find), numbered in the order of their smallest member; -1 for a
+    body in no pair."""
+    parent = list(range(n))
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+
+    for i, j in pairs:
+        ri, rj = find(int(i)), find(int(j))
+        if ri != rj:
+            parent[max(ri, rj)] = min(ri, rj)
+    members = sorted({int(x) for p in pairs for x in p})
+    roots = sorted({find(x) for x in members})
+    rank = {r: k for k, r in enumerate(roots)}
+    want = np.full(n, -1, np.int32)
+    for x in members:
+        want[x] = rank[find(x)]
+    return want
+
+
+def test_sets_of_a_system_beyond_the_bitmap(Q):
+    """The set partition ranks the bodies in encounters through a bitmap of
+    the system for up to 262144 bodies and by sorting beyond that.  A
+    266004-body disk takes the sorting path: its sets must be the connected
+    components of the step's encounter pairs, numbered by smallest member."""
+    s = inputs.make_disk("disk266k", 11, 266000, 1e-10, 15.0, 40.0, "rayleigh", "rayleigh", 0.05,
+                         0.025)
+    assert s.n > 262144
+    say("sets beyond the bitmap", s.n)
+    ctx = Q.Context(s)
+    ctx.step(0.05, 1)
+    ctx.sync()
+    st = ctx.stats()
+    assert st["status"] == 0
+    pg, sid = ctx.encounters()
+    assert 0 < len(pg) <= 4096
+    assert st["n_sets"] == int(sid.max()) + 1
+    assert np.array_equal(sid, _components(pg, s.n))
+    ctx.close()
+
+
 def test_set_larger_than_lds_stage(Q, orc):
     """A body on a nearly parabolic orbit has a huge osculating semi-major
     axis, hence a huge Hill radius: every body joins its encounter set.  A set
