@@ -43,7 +43,7 @@ struct Layout {
     size_t off_swcnt = 0, off_swslot = 0, off_swrec = 0, off_swlarge = 0, off_syssw = 0,
            off_swpart = 0;
     long long sw_nb = 1;       // grid-sweep buckets
-    size_t off_hw = 0, off_ctr = 0, off_epart = 0, off_E = 0, off_guess = 0;
+    size_t off_hw = 0, off_ctr = 0, off_kstat = 0, off_epart = 0, off_E = 0, off_guess = 0;
     size_t total = 0;
     long long np = 0;          // padded body count
     long long acc_len = 0;     // doubles of kick partials
@@ -171,6 +171,7 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_syssw, (size_t)std::max(nsys, 1) * sizeof(double4));
     take(L.off_swpart, 3 * (size_t)L.nchunks * D);
     take(L.off_ctr, (size_t)C_COUNT * sizeof(unsigned long long));
+    take(L.off_kstat, (size_t)kStatStripes * kStatStride * sizeof(unsigned long long));
     take(L.off_epart, (size_t)L.n_eitems * D);
     take(L.off_E, (size_t)std::max(nsys, 1) * D);
     take(L.off_guess, (size_t)(kGuessWeights + 5) * sizeof(float));
@@ -237,6 +238,7 @@ Dev bind(char *base, const Layout &L)
     d.set_rc = (double *)(base + L.off_setrc);
     d.hw = (double *)(base + L.off_hw);
     d.ctr = (unsigned long long *)(base + L.off_ctr);
+    d.kstat = (unsigned long long *)(base + L.off_kstat);
     d.epart = (double *)(base + L.off_epart);
     d.E = (double *)(base + L.off_E);
     d.guess = (float *)(base + L.off_guess);
@@ -1089,9 +1091,23 @@ int qsym_stats(qsym_ctx *c, qsym_stats_t *out)
     out->substeps = (int64_t)h[C_SUB];
     out->total_encounters = (int64_t)h[C_TENC];
     out->total_substeps = (int64_t)h[C_TSUB];
-    out->kepler_iters = (int64_t)h[C_KIT];
-    out->kepler_max = (int64_t)h[C_KMAX];
-    for (int k = 0; k < kHist; ++k) out->kepler_hist[k] = (int64_t)h[C_HIST + k];
+    {
+        // the striped Kepler statistics, added up here
+        std::vector<unsigned long long> ks((size_t)kStatStripes * kStatStride);
+        HIPCHK(c, hipMemcpyAsync(ks.data(), c->d.kstat, sizeof(unsigned long long) * ks.size(),
+                                 hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        unsigned long long kit = 0, kmax = 0, hist[kHist] = {};
+        for (int s = 0; s < kStatStripes; ++s) {
+            const unsigned long long *k = ks.data() + (size_t)s * kStatStride;
+            for (int b = 0; b < kHist; ++b) hist[b] += k[b];
+            kit += k[kHist];
+            kmax = std::max(kmax, k[kHist + 1]);
+        }
+        out->kepler_iters = (int64_t)kit;
+        out->kepler_max = (int64_t)kmax;
+        for (int b = 0; b < kHist; ++b) out->kepler_hist[b] = (int64_t)hist[b];
+    }
     out->status = (int64_t)h[C_STATUS];
     out->whole_system = (int64_t)h[C_WHOLE];
     for (int k = 0; k < kPhases; ++k) {

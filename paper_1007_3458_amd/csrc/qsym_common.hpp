@@ -10,7 +10,14 @@ constexpr int kChunk = 256;        // bodies per workgroup of the O(N) kernels
 constexpr int kChunkK = 64;        // bodies per workgroup of the Kepler pass
 constexpr int kCapE = 4096;        // encounter pairs of one system per step (on chip)
 constexpr int kCapU = 2 * kCapE;   // bodies of one system taking part in encounters
-constexpr int kHist = 32;          // Kepler iteration histogram bins
+constexpr int kHist = 32;
+// The Kepler pass's statistics (iteration histogram, total, largest) are
+// kept in kStatStripes copies, kStatStride entries (512 B) apart: the
+// workgroups of one launch add to different copies, so their atomics spread
+// over many memory channels instead of queueing on one line; the host adds
+// the copies up when it reads the statistics.
+constexpr int kStatStripes = 64;
+constexpr int kStatStride = 64;   // entries: [0, kHist) histogram, kHist total, kHist + 1 largest          // Kepler iteration histogram bins
 constexpr int kSMax = 64;          // largest j-split of one system
 constexpr int kSetsThreads = 256;  // workgroup of the set-partition kernel
 constexpr int kHermThreads = 512;  // workgroup of the Hermite kernel
@@ -19,7 +26,8 @@ constexpr int kWaveMax = 16;       // sets up to this size run on one wave, larg
 constexpr int kGridMax = 1024;     // largest grid of the grid-wide Hermite
 constexpr double kPi = 3.14159265358979323846;
 
-// counters / status word in device memory (unsigned 64-bit for atomics)
+// counters / status word in device memory (unsigned 64-bit for atomics;
+// the Kepler statistics are striped apart, see kStatStripes)
 enum Ctr {
     C_CAND = 0,   // crude candidates of the last sweep (true count)
     C_ENC,        // fine-sweep encounter pairs of the last step (true count)
@@ -28,15 +36,12 @@ enum Ctr {
     C_SUB,        // Hermite substeps of the last step
     C_TENC,       // total encounters
     C_TSUB,       // total substeps
-    C_KIT,        // total Kepler iterations
-    C_KMAX,       // largest Kepler iteration count
     C_STEPS,      // steps taken
     C_STATUS,     // latched status bits
     C_NU,         // bodies in encounters, last step
     C_NSMALL,     // sets of at most kWaveMax members (one wave each), last step
     C_NBIG,       // larger sets (one workgroup each), last step
-    C_HIST = 16,  // kHist bins
-    C_WHOLE = C_HIST + kHist,   // systems integrated whole (all steps)
+    C_WHOLE,      // systems integrated whole (all steps)
     C_NLARGE,     // grid sweep: bodies on the large list, last step
     C_COUNT
 };
@@ -104,6 +109,7 @@ struct Dev {
     int memcap;                                 // member slots (Hermite scratch stride)
     double *hw;                                 // Hermite member scratch
     unsigned long long *ctr;                    // counters and status
+    unsigned long long *kstat;                  // [kStatStripes][kStatStride] Kepler statistics
     double *epart;                              // energy partials per item
     double *E;                                  // energies per system
     float *guess;                               // learned Kepler start: weights + scalers

@@ -957,10 +957,11 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
     }
     __syncthreads();
     if (a.do_kep) {
-        if (t < kHist && hist[t]) atomicAdd(&d.ctr[C_HIST + t], (unsigned long long)hist[t]);
+        unsigned long long *ks = d.kstat + (size_t)(blockIdx.x & (kStatStripes - 1)) * kStatStride;
+        if (t < kHist && hist[t]) atomicAdd(&ks[t], (unsigned long long)hist[t]);
         if (t == 0) {
-            atomicAdd(&d.ctr[C_KIT], ksum);
-            atomicMax(&d.ctr[C_KMAX], (unsigned long long)kmax);
+            atomicAdd(&ks[kHist], ksum);
+            atomicMax(&ks[kHist + 1], (unsigned long long)kmax);
         }
     }
     if (t == 0 && bad) latch(d.ctr, (unsigned long long)bad);
