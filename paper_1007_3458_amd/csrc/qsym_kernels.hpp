@@ -37,22 +37,6 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return r;
 }
 
-template <int BS>
-__device__ __forceinline__ double block_min(double v, double *lds)
-{
-    const int t = threadIdx.x;
-    lds[t] = v;
-    __syncthreads();
-#pragma unroll
-    for (int s = BS / 2; s > 0; s >>= 1) {
-        if (t < s) lds[t] = fmin(lds[t], lds[t + s]);
-        __syncthreads();
-    }
-    double r = lds[0];
-    __syncthreads();
-    return r;
-}
-
 // LDS written by some lanes of a wave and read by others: the wave's LDS
 // operations complete in order, so a fence and a wave barrier suffice
 __device__ __forceinline__ void wave_lds_sync()
@@ -1910,9 +1894,10 @@ __device__ void hermite_set_wave(const HermArgs &a, int sidx, const SetLds &S, i
     fail_out = fail;
 }
 
-// minimum over the workgroup of a value that is equal on the L lanes of
-// each group: a wave minimum, then the kHermThreads / 64 wave minima
-// through LDS (one barrier); every thread gets the same value
+// minimum over a workgroup of NT threads: a wave minimum, then the NT / 64
+// wave minima through LDS (one barrier); every thread gets the same value.
+// red must not be read again before the next barrier.
+template <int NT>
 __device__ __forceinline__ double block_min_waves(double v, double *red)
 {
     v = wave_min(v);
@@ -1920,7 +1905,7 @@ __device__ __forceinline__ double block_min_waves(double v, double *red)
     __syncthreads();
     double r = red[0];
 #pragma unroll
-    for (int w = 1; w < kHermThreads / 64; ++w) r = fmin(r, red[w]);
+    for (int w = 1; w < NT / 64; ++w) r = fmin(r, red[w]);
     return wave_uniform(r);
 }
 
@@ -1979,7 +1964,7 @@ __device__ void hermite_set_block(const HermArgs &a, int sidx, const SetLds &S, 
         const double hb = a.eta_s * dnorm3(A[0], A[1], A[2]) / dnorm3(J[0], J[1], J[2]);
         if (mine && hb > 0.0) hloc = hb;
     }
-    double h = block_min_waves(hloc, red);
+    double h = block_min_waves<kHermThreads>(hloc, red);
     const double sgn = a.tau >= 0.0 ? 1.0 : -1.0;
     const double T = fabs(a.tau);
     double tt = 0.0;
@@ -2010,7 +1995,7 @@ __device__ void hermite_set_block(const HermArgs &a, int sidx, const SetLds &S, 
         const double hb = herm_correct(hk, a.eta, a1, j1, xp, up, X, U, A, J);
         tt += h;
         ++nsub;
-        h = block_min_waves((mine && hb > 0.0) ? hb : INFINITY, red);
+        h = block_min_waves<kHermThreads>((mine && hb > 0.0) ? hb : INFINITY, red);
     }
     // step 7: v1 -= tau/2 * W-weighted in-set forces at q1, write back
     __syncthreads();
@@ -2254,12 +2239,14 @@ __global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
             }
         }
         {
-            const double bm = block_min<kGridThreads>(hloc, red);
+            const double bm = block_min_waves<kGridThreads>(hloc, red);
             if (t == 0) ga.hpart[par * gridDim.x + blockIdx.x] = bm;
         }
         GSYNC();
+        // the step minimum over the blocks' minima: one load per thread
         double h = INFINITY;
-        for (int b = 0; b < (int)gridDim.x; ++b) h = fmin(h, ga.hpart[par * gridDim.x + b]);
+        for (int b = t; b < (int)gridDim.x; b += kGridThreads) h = fmin(h, ga.hpart[par * gridDim.x + b]);
+        h = block_min_waves<kGridThreads>(h, red);
         par ^= 1;
         const double sgn = a.tau >= 0.0 ? 1.0 : -1.0;
         const double T = fabs(a.tau);
@@ -2317,12 +2304,14 @@ __global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
                 }
             }
             {
-                const double bm = block_min<kGridThreads>(hn, red);
+                const double bm = block_min_waves<kGridThreads>(hn, red);
                 if (t == 0) ga.hpart[par * gridDim.x + blockIdx.x] = bm;
             }
             GSYNC();
             double hnext = INFINITY;
-            for (int b = 0; b < (int)gridDim.x; ++b) hnext = fmin(hnext, ga.hpart[par * gridDim.x + b]);
+            for (int b = t; b < (int)gridDim.x; b += kGridThreads)
+                hnext = fmin(hnext, ga.hpart[par * gridDim.x + b]);
+            hnext = block_min_waves<kGridThreads>(hnext, red);
             par ^= 1;
             tt += h;
             ++nsub;
