@@ -2113,15 +2113,20 @@ struct GridArgs {
 constexpr unsigned long long kGridWaitTicks = 1000000000ull;
 
 // Grid-wide barrier over the arrivals counter (cumulative, so barrier p
-// completes at gridDim * p arrivals) and a generation word.  Every wave
-// fences at agent scope on both sides, so the stores of all blocks before
-// the barrier are visible to all blocks after it.  Returns false when the
-// wait ran out or another block aborted.
+// completes at gridDim * p arrivals) and a generation word.  The block
+// barrier first waits for the stores of all the block's waves (they are in
+// L2 then); one thread per block then fences at agent scope (L2 written back)
+// before it arrives and again after the wait (this CU's L1 and this XCD's
+// L2 invalidated, for every wave of the block), so the stores of all blocks
+// before the barrier are visible to all blocks after it.  An agent-scope
+// fence in every wave instead costs thousands of whole-L2 write-backs and
+// invalidations per barrier.  Returns false when the wait ran out or
+// another block aborted.
 __device__ bool grid_sync(const GridArgs &ga, unsigned &phase, int *s_ok)
 {
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
+        __threadfence();
         int ok = 1;
         const unsigned target = phase + 1;
         const unsigned prev =
@@ -2130,7 +2135,9 @@ __device__ bool grid_sync(const GridArgs &ga, unsigned &phase, int *s_ok)
             __hip_atomic_store(&ga.bar[1], target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-            while (__hip_atomic_load(&ga.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            // relaxed polls (an acquire load would invalidate the caches on
+            // every poll); the fence after the wait is the acquire
+            while (__hip_atomic_load(&ga.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 if (__hip_atomic_load(&ga.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
                     __builtin_amdgcn_s_memrealtime() - t0 > kGridWaitTicks) {
                     ok = 0;
@@ -2140,11 +2147,11 @@ __device__ bool grid_sync(const GridArgs &ga, unsigned &phase, int *s_ok)
             }
         }
         if (!ok) __hip_atomic_store(&ga.bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
         *s_ok = ok;
         phase = target;
     }
     __syncthreads();
-    __threadfence();
     return __builtin_amdgcn_readfirstlane(*s_ok) != 0;
 }
 
