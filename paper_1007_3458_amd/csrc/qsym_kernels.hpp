@@ -1626,18 +1626,18 @@ __device__ void set_pair_acc(const SetLds &S, int n, int a, int l, int L, double
     for (int b = l; b < n; b += L) {
         if (b == a) continue;
         const double dd0 = S.x[b] - xi, dd1 = S.y[b] - yi, dd2 = S.z[b] - zi;
-        const double s2 = dd0 * dd0 + dd1 * dd1 + dd2 * dd2;
+        const double s2 = fma(dd2, dd2, fma(dd1, dd1, dd0 * dd0));
         // beyond r_crit K = 1, K' = 0: W = 0, the pair adds exactly zero
         if (s2 == 0.0 || s2 >= tc.rc2) continue;
         double s, is;
         inv_dist(s2, s, is);
         double K, Kp, Kpp;
         transition(s, tc, K, Kp, Kpp);
-        const double W = 1.0 - K + s * Kp;
+        const double W = fma(s, Kp, 1.0 - K);
         const double fct = G * S.m[b] * W * (is * is * is);
-        out[0] += fct * dd0;
-        out[1] += fct * dd1;
-        out[2] += fct * dd2;
+        out[0] = fma(fct, dd0, out[0]);
+        out[1] = fma(fct, dd1, out[1]);
+        out[2] = fma(fct, dd2, out[2]);
     }
 }
 
@@ -1649,12 +1649,15 @@ __device__ void herm_pairs(const SetLds &S, int n, int a, int l, int L, double G
     const TransConst tc = trans_const(rc);
     const double X0 = S.x[a], X1 = S.y[a], X2 = S.z[a];
     const double U0 = S.u[a], U1 = S.v[a], U2 = S.w[a];
+    const double eps2 = eps * eps;
     for (int c = 0; c < 3; ++c) acc[c] = jrk[c] = 0.0;
+    // dot products and sums as explicit fused multiply-adds (the library
+    // contracts nothing by itself)
     for (int b = l; b < n; b += L) {
         if (b == a) continue;
         const double dd[3] = {S.x[b] - X0, S.y[b] - X1, S.z[b] - X2};
         const double w[3] = {S.u[b] - U0, S.v[b] - U1, S.w[b] - U2};
-        const double s2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2] + eps * eps;
+        const double s2 = fma(dd[2], dd[2], fma(dd[1], dd[1], fma(dd[0], dd[0], eps2)));
         // beyond r_crit W = 0 and K'' = 0: the pair adds exactly zero
         if (s2 == 0.0 || s2 >= tc.rc2) continue;
         double s, is;
@@ -1662,14 +1665,15 @@ __device__ void herm_pairs(const SetLds &S, int n, int a, int l, int L, double G
         const double is2 = is * is;
         double K, Kp, Kpp;
         transition(s, tc, K, Kp, Kpp);
-        const double W = 1.0 - K + s * Kp;
+        const double W = fma(s, Kp, 1.0 - K);
         const double gm = G * S.m[b] * (is2 * is);
         const double gmW = gm * W;
-        const double dw = dd[0] * w[0] + dd[1] * w[1] + dd[2] * w[2];
+        const double dw = fma(dd[2], w[2], fma(dd[1], w[1], dd[0] * w[0]));
         const double c3 = 3.0 * dw * is2;
+        const double dK = dw * Kpp;
         for (int c = 0; c < 3; ++c) {
-            acc[c] += gmW * dd[c];
-            jrk[c] += gm * (dw * dd[c] * Kpp + (w[c] - c3 * dd[c]) * W);
+            acc[c] = fma(gmW, dd[c], acc[c]);
+            jrk[c] = fma(gm, fma(dK, dd[c], fma(-c3, dd[c], w[c]) * W), jrk[c]);
         }
     }
 }

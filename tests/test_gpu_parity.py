@@ -130,6 +130,18 @@ def test_kepler_parity(Q, orc, mode, dt):
     # same iteration counts up to convergence-threshold ties
     hist_o = np.bincount(it, minlength=32)[:32]
     assert np.abs(np.array(st["kepler_hist"]) - hist_o).sum() <= 0.01 * s.n
+    # the statistics are kept in striped copies (79 workgroups over 64
+    # copies here) and added up on the host: total and largest agree with
+    # the histogram, and a second pass adds to all three
+    h = np.array(st["kepler_hist"])
+    assert h[-1] == 0
+    assert st["kepler_iters"] == int((np.arange(32) * h).sum())
+    assert st["kepler_max"] == int(np.nonzero(h)[0].max())
+    ctx.apply_kepler(dt)
+    st2 = ctx.stats()
+    assert sum(st2["kepler_hist"]) == 2 * s.n
+    assert st2["kepler_iters"] == int((np.arange(32) * np.array(st2["kepler_hist"])).sum())
+    assert st2["kepler_max"] >= st["kepler_max"]
     ctx.close()
 
 
