@@ -30,8 +30,8 @@ __device__ __forceinline__ void stumpff(double y, double &C, double &S)
         double cc = c[13], ss = s[13];
 #pragma unroll
         for (int k = 12; k >= 0; --k) {
-            cc = c[k] + w * cc;
-            ss = s[k] + w * ss;
+            cc = fma(w, cc, c[k]);
+            ss = fma(w, ss, s[k]);
         }
         C = cc;
         S = ss;
@@ -55,18 +55,23 @@ __device__ int kepler_iterate(double smu, double r0, double rv, double alpha, do
                               int laguerre, double &x, int &count)
 {
     const double b = 1.0 - r0 * alpha;
+    // loop invariants, and the universal Kepler equation and its
+    // derivatives as fused multiply-adds (one division per iteration)
+    const double q = rv / smu, sdt = smu * dt;
     for (int it = 1; it <= kKeplerCap; ++it) {
-        const double z = alpha * x * x;
+        const double x2 = x * x;
+        const double z = alpha * x2;
         double C, S;
         stumpff(z, C, S);
-        const double F = rv * x * x * C / smu + b * x * x * x * S + r0 * x - smu * dt;
-        const double Fp = rv * x * (1.0 - z * S) / smu + b * x * x * C + r0;
+        const double zs = fma(-z, S, 1.0);   // 1 - z S
+        const double F = fma(q * x2, C, fma(b * x2 * x, S, fma(r0, x, -sdt)));
+        const double Fp = fma(q * x, zs, fma(b * x2, C, r0));
         double dx;
         if (laguerre) {
-            const double Fpp = rv * (1.0 - z * C) / smu + b * x * (1.0 - z * S);
+            const double Fpp = fma(q, fma(-z, C, 1.0), b * x * zs);
             const double nl = 5.0;
             const double rad =
-                sqrt(fabs((nl - 1.0) * (nl - 1.0) * Fp * Fp - nl * (nl - 1.0) * F * Fpp));
+                sqrt(fabs(fma((nl - 1.0) * (nl - 1.0) * Fp, Fp, -nl * (nl - 1.0) * F * Fpp)));
             dx = nl * F / (Fp + (Fp >= 0.0 ? rad : -rad));
         } else {
             dx = F / Fp;
