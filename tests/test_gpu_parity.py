@@ -411,6 +411,44 @@ def test_sets_of_a_system_beyond_the_bitmap(Q):
     ctx.close()
 
 
+def _wide_with_parabolic(seed, n_disk):
+    """A disk of planetesimals plus one body on a nearly parabolic orbit, whose
+    huge osculating semi-major axis (hence Hill radius) pulls every body into
+    its encounter set."""
+    base = inputs.make_disk("wide%d" % seed, seed, n_disk, 1e-9, 4.5, 6.0, "uniform", "uniform", 0.05,
+                            0.01, planets=False)
+    r = np.array([5.0, 0.1, 0.0])
+    v = np.array([0.0, 0.99995 * np.sqrt(2.0 / np.linalg.norm(r)), 0.0])
+    return inputs.System("bigset%d" % seed, 1.0, 1.0, np.concatenate([base.m, [1e-6]]),
+                         np.vstack([base.q, r]), np.vstack([base.v, v]))
+
+
+def test_two_sets_on_the_grid_in_one_step(Q, orc):
+    """Two systems in one batch, each with a set of more than 256 members:
+    both sets run on the whole grid in one launch, one after the other, so
+    the grid barrier's phases carry over from the first set to the second.
+    Each system equals its own oracle step."""
+    systems = [_wide_with_parabolic(21, 420), _wide_with_parabolic(22, 300)]
+    say("two grid sets", [s.n for s in systems])
+    ctx = Q.Context(systems)
+    ctx.step(0.05, 1)
+    ctx.sync()
+    st = ctx.stats()
+    assert st["status"] == 0
+    qg, vg = ctx.get_state()
+    off = ctx.offsets
+    sizes = []
+    for k, s in enumerate(systems):
+        qo, vo, res = orc.step(orc.make_params(), 0.05, s.m, s.h, s.q, s.v)
+        assert res.rc == 0
+        sizes.append(res.stats["max_set"])
+        a, b = off[k], off[k + 1]
+        assert per_body_rel(qg[a:b], qo) < 1e-12 and per_body_rel(vg[a:b], vo) < 1e-12
+    assert min(sizes) > 256
+    assert st["max_set"] == max(sizes)
+    ctx.close()
+
+
 def test_set_larger_than_lds_stage(Q, orc):
     """A body on a nearly parabolic orbit has a huge osculating semi-major
     axis, hence a huge Hill radius: every body joins its encounter set.  A set
