@@ -1,0 +1,157 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configuration
+the benchmark uses (the tuned kick shapes), through the C ABI: sampled
+outputs the oracle computes one by one (accelerations of sampled bodies over
+all bodies, Kepler solves of sampled bodies), and a property of the whole step
+that holds at any size (total angular momentum, conserved by every operator
+of the splitting: the kicks' pair forces are central and antisymmetric, the
+drift moves every body by the same vector parallel to the total momentum,
+and the Kepler flow and the Hermite's forces are central)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1007_3458_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_1007_3458_amd import qsym
+    qsym.lib()
+    return qsym
+
+
+def per_body_rel(a, b):
+    return np.max(np.linalg.norm(a - b, axis=1) / np.maximum(np.linalg.norm(b, axis=1), 1e-300))
+
+
+def angular_momentum(m, q, v):
+    return (m[:, None] * np.cross(q, v)).sum(axis=0)
+
+
+@pytest.fixture(scope="module")
+def disk128k():
+    return inputs.disk128k()
+
+
+def test_disk128k_kick_sampled(Q, orc, disk128k):
+    """FP64 kick of the 131076-body disk (tuned shape) at 510 sampled bodies."""
+    s = disk128k
+    say("disk128k kick", s.n)
+    s0 = s.copy()
+    s0.v[:] = 0.0
+    ctx = Q.Context(s0)
+    ctx.apply_kick(1.0)
+    _, a = ctx.get_state()
+    ctx.close()
+    rows = np.arange(0, s.n, 257)
+    ao = orc.accel_rows(s.G, s.m, s.q, rows)
+    assert per_body_rel(a[rows], ao) < 1e-13
+
+
+def test_disk128k_fp32_form_kick_sampled(Q, orc, disk128k):
+    """FP32 pair terms on the 131076-body disk: the form's error bounds at
+    510 sampled bodies."""
+    s = disk128k
+    say("disk128k fp32 kick", s.n)
+    s0 = s.copy()
+    s0.v[:] = 0.0
+    ctx = Q.Context(s0, precision=1)
+    ctx.apply_kick(1.0)
+    _, a = ctx.get_state()
+    ctx.close()
+    rows = np.arange(0, s.n, 257)
+    ao = orc.accel_rows(s.G, s.m, s.q, rows)
+    rel = np.linalg.norm(a[rows] - ao, axis=1) / np.linalg.norm(ao, axis=1)
+    say("fp32 form rel err max %.3e rms %.3e" % (rel.max(), np.sqrt(np.mean(rel ** 2))))
+    assert rel.max() < 2e-6 and np.sqrt(np.mean(rel ** 2)) < 3e-7
+
+
+def test_disk128k_kepler_sampled(Q, orc, disk128k):
+    """Kepler drift of all 131076 bodies; 510 sampled bodies solved by the
+    oracle one by one."""
+    s = disk128k
+    say("disk128k kepler", s.n)
+    ctx = Q.Context(s)
+    ctx.apply_kepler(0.05)
+    q1, v1 = ctx.get_state()
+    ctx.close()
+    rows = np.arange(0, s.n, 257)
+    qo, vo, _, fails = orc.kepler(s.G * s.m0, s.q[rows], s.v[rows], 0.05, 0)
+    assert fails == 0
+    assert per_body_rel(q1[rows], qo) < 1e-13
+    assert per_body_rel(v1[rows], vo) < 1e-13
+
+
+def test_disk128k_step_conserves_angular_momentum(Q, disk128k):
+    """One whole hybrid step of the 131076-body disk, encounters and all:
+    total angular momentum conserved to rounding, energy error at the
+    integrator's level."""
+    s = disk128k
+    say("disk128k step", s.n)
+    ctx = Q.Context(s)
+    E0 = ctx.energy()[0]
+    L0 = angular_momentum(s.m, s.q, s.v)
+    ctx.step(0.05, 1)
+    ctx.sync()
+    q1, v1 = ctx.get_state()
+    E1 = ctx.energy()[0]
+    st = ctx.stats()
+    ctx.close()
+    assert st["status"] == 0 and st["n_encounters"] > 0
+    L1 = angular_momentum(s.m, q1, v1)
+    assert np.linalg.norm(L1 - L0) <= 1e-12 * np.linalg.norm(L0)
+    assert abs(E1 / E0 - 1.0) < 1e-9
+
+
+def test_batch_kick_sampled(Q, orc):
+    """FP64 kick of the 512-system batch (551,375 bodies, tuned shape): the
+    first, middle and last body of every system."""
+    systems = inputs.batch()
+    say("batch kick", len(systems), sum(b.n for b in systems))
+    zeroed = []
+    for b in systems:
+        b0 = b.copy()
+        b0.v[:] = 0.0
+        zeroed.append(b0)
+    ctx = Q.Context(zeroed)
+    ctx.apply_kick(1.0)
+    _, a = ctx.get_state()
+    off = ctx.offsets
+    ctx.close()
+    worst = 0.0
+    for k, b in enumerate(systems):
+        rows = np.unique([0, b.n // 2, b.n - 1])
+        ao = orc.accel_rows(b.G, b.m, b.q, rows)
+        worst = max(worst, per_body_rel(a[off[k] + rows], ao))
+    assert worst < 1e-13
+
+
+def test_learned_workload_kepler_sampled(Q, orc):
+    """Kepler solve of the learned-start workload (1,114,116 bodies) from the
+    packaged learned start: 1092 sampled bodies solved by the oracle (from
+    its own start; the root is the same to the solve's tolerance)."""
+    from paper_1007_3458_amd import learned_guess
+    s = inputs.learned_workload()
+    say("learned workload kepler", s.n)
+    ctx = Q.Context([s], Q.make_params(kepler_mode=2), guess=learned_guess.load())
+    ctx.apply_kepler(0.05)
+    q1, v1 = ctx.get_state()
+    st = ctx.stats()
+    ctx.close()
+    assert st["status"] == 0
+    assert sum(st["kepler_hist"]) == s.n
+    rows = np.arange(0, s.n, 1021)
+    qo, vo, _, fails = orc.kepler(s.G * s.m0, s.q[rows], s.v[rows], 0.05, 1)
+    assert fails == 0
+    assert per_body_rel(q1[rows], qo) < 1e-12
+    assert per_body_rel(v1[rows], vo) < 1e-12
