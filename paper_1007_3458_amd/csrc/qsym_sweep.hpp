@@ -34,6 +34,7 @@ namespace qsym {
 constexpr int kSweepCap = 32;        // bodies per hash bucket before overflow to the large list
 constexpr int kSweepThreads = 256;
 constexpr int kSweepLargeTile = 4096;  // bodies per work item of the large pass
+constexpr int kSweepBuf = 1024;        // candidates a workgroup gathers before one global append
 constexpr double kSweepFar = 1e6;    // cell coordinates beyond this go to the large list
 
 struct SweepArgs {
@@ -54,10 +55,19 @@ __device__ __forceinline__ unsigned sweep_hash(int s, int cx, int cy, int cz, un
     return (unsigned)h & mask;
 }
 
+// The search's candidates are gathered per workgroup in LDS and appended with
+// one atomic per workgroup: an atomic per wave with a hit, thousands on the
+// one candidate counter in a kernel of a few tens of microseconds, queue on
+// its line.  A full buffer falls back to appending directly.
+struct SweepOut {
+    int2 *buf;
+    unsigned *n;
+};
+
 // crude_exact on packed operands: the same operations in the same order, so
 // the same decision (i < j)
-__device__ __forceinline__ void crude_rec(const KickArgs &ka, int i, const SweepRec &ri, int j,
-                                          const SweepRec &rj)
+__device__ __forceinline__ void crude_rec(const KickArgs &ka, const SweepOut &o, int i,
+                                          const SweepRec &ri, int j, const SweepRec &rj)
 {
     const Dev &d = ka.d;
     const double dx = rj.x - ri.x;
@@ -71,8 +81,28 @@ __device__ __forceinline__ void crude_rec(const KickArgs &ka, int i, const Sweep
         Rup = ka.aE * (ri.h * ri.A + rj.h * rj.A);
     const double lim = ka.cs * (Rup + ka.tau_abs * (ri.cv + rj.cv));
     if (r2 < lim * lim) {
-        const unsigned long long slot = atomicAdd(&d.ctr[C_CAND], 1ull);
-        if ((long long)slot < ka.cap) d.cand[slot] = make_int2(i, j);
+        const unsigned q = atomicAdd(o.n, 1u);
+        if (q < (unsigned)kSweepBuf) {
+            o.buf[q] = make_int2(i, j);
+        } else {
+            const unsigned long long slot = atomicAdd(&d.ctr[C_CAND], 1ull);
+            if ((long long)slot < ka.cap) d.cand[slot] = make_int2(i, j);
+        }
+    }
+}
+
+// the workgroup's gathered candidates onto the list (every thread calls it)
+__device__ __forceinline__ void sweep_flush(const KickArgs &ka, const SweepOut &o,
+                                            unsigned long long *s_base)
+{
+    const Dev &d = ka.d;
+    __syncthreads();
+    const unsigned n = min(*o.n, (unsigned)kSweepBuf);
+    if (threadIdx.x == 0 && n) *s_base = atomicAdd(&d.ctr[C_CAND], (unsigned long long)n);
+    __syncthreads();
+    for (unsigned k = threadIdx.x; k < n; k += blockDim.x) {
+        const unsigned long long slot = *s_base + k;
+        if ((long long)slot < ka.cap) d.cand[slot] = o.buf[k];
     }
 }
 
@@ -158,54 +188,62 @@ __global__ __launch_bounds__(kSweepThreads) void k_sweep_search(SweepArgs a)
     const KickArgs &ka = a.ka;
     const Dev &d = ka.d;
     const int t = threadIdx.x;
+    __shared__ int2 s_buf[kSweepBuf];
+    __shared__ unsigned s_n;
+    __shared__ unsigned long long s_base;
+    if (t == 0) s_n = 0u;
+    __syncthreads();
+    const SweepOut o{s_buf, &s_n};
     if ((int)blockIdx.x < a.nsmall) {
         const long long g = (long long)blockIdx.x * kSweepThreads + t;
-        if (g >= 14ll * a.ntot) return;
         const int i = (int)(g / 14), nbr = (int)(g % 14);
-        const SweepRec ri = d.sw_rec[i];
-        if (ri.sys < 0) return;
-        const int s = ri.sys;
-        // half-shell offset number nbr - 1 of the 13 with (dz, dy, dx) > 0:
-        // codes 14..26 of 9 (dz + 1) + 3 (dy + 1) + (dx + 1)
-        const int code = nbr == 0 ? 13 : 13 + nbr;
-        const int nx = ri.cx + code % 3 - 1, ny = ri.cy + (code / 3) % 3 - 1;
-        const int nz = ri.cz + code / 9 - 1;
-        const unsigned bk = sweep_hash(s, nx, ny, nz, (unsigned)d.sw_nb - 1u);
-        const int nb = min(d.sw_cnt[bk], kSweepCap);
-        for (int k = 0; k < nb; ++k) {
-            const int j = d.sw_slot[(long long)bk * kSweepCap + k];
-            if (nbr == 0 && j <= i) continue;
-            const SweepRec rj = d.sw_rec[j];
-            // another cell or system in the same bucket
-            if (rj.cx != nx || rj.cy != ny || rj.cz != nz || rj.sys != s) continue;
-            if (i < j)
-                crude_rec(ka, i, ri, j, rj);
-            else
-                crude_rec(ka, j, rj, i, ri);
+        const bool ok = g < 14ll * a.ntot;
+        const SweepRec ri = d.sw_rec[ok ? i : 0];
+        if (ok && ri.sys >= 0) {
+            const int s = ri.sys;
+            // half-shell offset number nbr - 1 of the 13 with (dz, dy, dx) > 0:
+            // codes 14..26 of 9 (dz + 1) + 3 (dy + 1) + (dx + 1)
+            const int code = nbr == 0 ? 13 : 13 + nbr;
+            const int nx = ri.cx + code % 3 - 1, ny = ri.cy + (code / 3) % 3 - 1;
+            const int nz = ri.cz + code / 9 - 1;
+            const unsigned bk = sweep_hash(s, nx, ny, nz, (unsigned)d.sw_nb - 1u);
+            const int nb = min(d.sw_cnt[bk], kSweepCap);
+            for (int k = 0; k < nb; ++k) {
+                const int j = d.sw_slot[(long long)bk * kSweepCap + k];
+                if (nbr == 0 && j <= i) continue;
+                const SweepRec rj = d.sw_rec[j];
+                // another cell or system in the same bucket
+                if (rj.cx != nx || rj.cy != ny || rj.cz != nz || rj.sys != s) continue;
+                if (i < j)
+                    crude_rec(ka, o, i, ri, j, rj);
+                else
+                    crude_rec(ka, o, j, rj, i, ri);
+            }
         }
-        return;
-    }
-    const int nl = (int)d.ctr[C_NLARGE];
-    const int items = nl * a.tiles;
-    const int stride = gridDim.x - a.nsmall;
-    for (int it = blockIdx.x - a.nsmall; it < items; it += stride) {
-        const int L = d.sw_large[it / a.tiles];
-        const SweepRec rL = d.sw_rec[L];
-        const int s = -rL.sys - 1;
-        const int o = d.sys_off[s], n = d.sys_off[s + 1] - o;
-        const int j0 = (it % a.tiles) * kSweepLargeTile;
-        const int j1 = min(n, j0 + kSweepLargeTile);
-        for (int k = j0 + t; k < j1; k += kSweepThreads) {
-            const int j = o + k;
-            if (j == L) continue;
-            const SweepRec rj = d.sw_rec[j];
-            if (rj.sys < 0 && j > L) continue;   // a large-large pair from its higher index
-            if (L < j)
-                crude_rec(ka, L, rL, j, rj);
-            else
-                crude_rec(ka, j, rj, L, rL);
+    } else {
+        const int nl = (int)d.ctr[C_NLARGE];
+        const int items = nl * a.tiles;
+        const int stride = gridDim.x - a.nsmall;
+        for (int it = blockIdx.x - a.nsmall; it < items; it += stride) {
+            const int L = d.sw_large[it / a.tiles];
+            const SweepRec rL = d.sw_rec[L];
+            const int s = -rL.sys - 1;
+            const int o0 = d.sys_off[s], n = d.sys_off[s + 1] - o0;
+            const int j0 = (it % a.tiles) * kSweepLargeTile;
+            const int j1 = min(n, j0 + kSweepLargeTile);
+            for (int k = j0 + t; k < j1; k += kSweepThreads) {
+                const int j = o0 + k;
+                if (j == L) continue;
+                const SweepRec rj = d.sw_rec[j];
+                if (rj.sys < 0 && j > L) continue;   // a large-large pair from its higher index
+                if (L < j)
+                    crude_rec(ka, o, L, rL, j, rj);
+                else
+                    crude_rec(ka, o, j, rj, L, rL);
+            }
         }
     }
+    sweep_flush(ka, o, &s_base);
 }
 
 }  // namespace qsym
