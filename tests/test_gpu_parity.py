@@ -449,20 +449,44 @@ def test_two_sets_on_the_grid_in_one_step(Q, orc):
     ctx.close()
 
 
-def test_set_larger_than_lds_stage(Q, orc):
-    """A body on a nearly parabolic orbit has a huge osculating semi-major
-    axis, hence a huge Hill radius: every body joins its encounter set.  A set
-    of more than 1024 members is integrated from the global staging path."""
-    base = inputs.make_disk("wide", 21, 1300, 1e-9, 4.5, 6.0, "uniform", "uniform", 0.05, 0.01,
+def _with_parabolic(nbase, seed=21):
+    """A disk of nbase light bodies plus one on a nearly parabolic orbit: its
+    huge osculating semi-major axis gives it a huge Hill radius, so the disk
+    bodies join its encounter set."""
+    base = inputs.make_disk("wide", seed, nbase, 1e-9, 4.5, 6.0, "uniform", "uniform", 0.05, 0.01,
                             planets=False)
-    rng = np.random.Generator(np.random.PCG64(3))
     r = np.array([5.0, 0.1, 0.0])
     vesc = np.sqrt(2.0 / np.linalg.norm(r))
     v = np.array([0.0, 0.99995 * vesc, 0.0])
     m = np.concatenate([base.m, [1e-6]])
     q = np.vstack([base.q, r])
     vv = np.vstack([base.v, v])
-    s = inputs.System("bigset", 1.0, 1.0, m, q, vv)
+    return inputs.System(f"parabolic{nbase}", 1.0, 1.0, m, q, vv)
+
+
+@pytest.mark.parametrize("nbase", [40, 100, 150, 230])
+def test_workgroup_set_sizes(Q, orc, nbase):
+    """Sets of 17-256 members run on one workgroup, staged in LDS in tiles of
+    64: one set of one to four tiles, ragged, a whole step against the
+    oracle."""
+    s = _with_parabolic(nbase)
+    say("workgroup set", s.n)
+    ctx = Q.Context(s)
+    ctx.step(0.05, 1)
+    ctx.sync()
+    st = ctx.stats()
+    qg, vg = ctx.get_state()
+    qo, vo, res = orc.step(orc.make_params(), 0.05, s.m, s.h, s.q, s.v)
+    ctx.close()
+    assert res.rc == 0 and res.stats["max_set"] == st["max_set"]
+    assert 16 < st["max_set"] <= 256 and st["max_set"] > 0.6 * s.n
+    assert per_body_rel(qg, qo) < 1e-12 and per_body_rel(vg, vo) < 1e-12
+
+
+def test_set_larger_than_lds_stage(Q, orc):
+    """A set of more than 1024 members (every body joins the nearly parabolic
+    body's set) is integrated from the global staging path."""
+    s = _with_parabolic(1300)
     say("big set", s.n)
     ctx = Q.Context(s)
     ctx.step(0.05, 1)
