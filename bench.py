@@ -298,8 +298,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs one process on one MI355X "
-              "(the multi-GPU design is described, not built)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs as one process on one MI355X; "
+              "sharding a step over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     defaults = {"disk16k": (200, 20), "disk128k": (100, 5), "small": (1000, 50), "batch": (100, 10),
                 "learned": (50, 5)}
