@@ -338,6 +338,38 @@ def test_edge_sizes(Q, orc):
         ctx.close()
 
 
+def test_time_reversal_without_encounters(Q, orc):
+    """With the encounter switch off (a_E = 0) the step is the symmetric
+    composition of exact flows (Sec. 2): tau steps forward and then -tau
+    steps back return to the start to rounding, and a backward step equals
+    the oracle's; a zero step leaves the state unchanged."""
+    s = inputs.scaled_disk(1025, seed=14)
+    say("time reversal", s.n)
+    ctx = Q.Context(s, Q.make_params(aE=0.0))
+    ctx.step(0.05, 20)
+    ctx.sync()
+    assert ctx.stats()["n_encounters"] == 0
+    ctx.step(-0.05, 20)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    assert np.max(np.abs(qg - s.q)) < 1e-12 * np.max(np.abs(s.q))
+    assert np.max(np.abs(vg - s.v)) < 1e-12 * np.max(np.abs(s.v))
+    ctx.set_state(s.m, s.h, s.q, s.v)
+    ctx.step(-0.05, 1)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    qo, vo, r = orc.step(orc.make_params(aE=0.0), -0.05, s.m, s.h, s.q, s.v)
+    assert r.rc == 0 and r.stats["n_encounters"] == 0
+    assert per_body_rel(qg, qo) < 1e-12 and per_body_rel(vg, vo) < 1e-12
+    ctx.set_state(s.m, s.h, s.q, s.v)
+    ctx.step(0.0, 1)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    assert np.max(np.abs(qg - s.q)) <= 1e-15 * np.max(np.abs(s.q))
+    assert np.max(np.abs(vg - s.v)) <= 1e-15 * np.max(np.abs(s.v))
+    ctx.close()
+
+
 def test_fp32_form_accuracy_and_step(Q, orc):
     """Precision form: m r^-3 in FP32 on FP64 separations, FP64 sums.  Per-body
     acceleration error against the oracle at the FP32 level; the whole step
