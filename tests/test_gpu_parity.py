@@ -370,6 +370,37 @@ def test_time_reversal_without_encounters(Q, orc):
     ctx.close()
 
 
+def test_empty_systems(Q, orc):
+    """Offsets need only be non-decreasing: empty systems in a batch stay
+    empty with zero energy while the others step exactly as alone, and a
+    context whose only system is empty steps as a no-op."""
+    empty = inputs.System("empty", 1.0, 1.0, np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3)))
+    a, b = inputs.batch_system(0, 64), inputs.batch_system(1, 130)
+    say("empty systems in a batch")
+    ctx = Q.Context([a, empty, b, empty])
+    ctx.step(0.05, 3)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    off = ctx.offsets
+    E = ctx.energy()
+    st = ctx.stats()
+    ctx.close()
+    assert st["status"] == 0 and E[1] == 0.0 and E[3] == 0.0
+    for k, s in ((0, a), (2, b)):
+        q, v = s.q, s.v
+        for _ in range(3):
+            q, v, r = orc.step(orc.make_params(), 0.05, s.m, s.h, q, v)
+            assert r.rc == 0
+        assert per_body_rel(qg[off[k]:off[k + 1]], q) < 1e-12
+        assert per_body_rel(vg[off[k]:off[k + 1]], v) < 1e-12
+    say("only an empty system")
+    ctx = Q.Context([empty])
+    ctx.step(0.05, 2)
+    ctx.sync()
+    assert ctx.energy()[0] == 0.0 and ctx.stats()["status"] == 0
+    ctx.close()
+
+
 def test_fp32_form_accuracy_and_step(Q, orc):
     """Precision form: m r^-3 in FP32 on FP64 separations, FP64 sums.  Per-body
     acceleration error against the oracle at the FP32 level; the whole step
