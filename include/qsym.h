@@ -126,7 +126,9 @@ void qsym_destroy(qsym_ctx *ctx);
 
 /* Load masses m[ntot], Hill factors h[ntot] = cbrt(m / (3 m0)) (computed by
  * the caller once so every implementation uses the same bits), positions
- * and velocities (SoA [3][ntot]). */
+ * and velocities (SoA [3][ntot]).  Clears the latched device status: a
+ * non-finite state, an overflow or a solver cap reported for the previous
+ * state is not reported again. */
 int qsym_set_state(qsym_ctx *ctx, const double *m, const double *h, const double *q,
                    const double *v, int32_t where);
 int qsym_get_state(qsym_ctx *ctx, double *q, double *v, int32_t where);

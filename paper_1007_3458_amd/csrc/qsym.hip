@@ -928,6 +928,9 @@ int qsym_set_state(qsym_ctx *c, const double *m, const double *h, const double *
         }
     }
     HIPCHK(c, run_momentum(c, st));
+    // a new state starts with a clear device status (the latched bits
+    // described the state it replaces)
+    HIPCHK(c, hipMemsetAsync(c->d.ctr + C_STATUS, 0, sizeof(unsigned long long), st));
     HIPCHK(c, hipStreamSynchronize(st));
     leave(c);
     return QSYM_OK;

@@ -321,6 +321,30 @@ def test_candidate_overflow_is_reported(Q):
     ctx.close()
 
 
+def test_nonfinite_state_is_reported(Q):
+    """A NaN coordinate propagates through the step (no kernel drops it) and
+    the step reports QSYM_ENONFINITE at the next synchronisation."""
+    s = inputs.small().copy()
+    s.q[5, 1] = np.nan
+    say("non-finite state")
+    ctx = Q.Context(s)
+    ctx.step(0.05, 1)
+    with pytest.raises(Q.QsymError) as e:
+        ctx.sync()
+    assert e.value.code == -4
+    with pytest.raises(Q.QsymError) as e:   # latched: every synchronising call reports it
+        ctx.get_state()
+    assert e.value.code == -4
+    # a new state clears the status
+    c = inputs.small()
+    ctx.set_state(c.m, c.h, c.q, c.v)
+    ctx.step(0.05, 1)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    assert np.isfinite(qg).all() and np.isfinite(vg).all()
+    ctx.close()
+
+
 def test_edge_sizes(Q, orc):
     for n in (1, 2, 3, 255, 256, 257):
         s = inputs.scaled_disk(max(n - 4, 1), seed=40 + n) if n > 4 else crowded(5, n).copy()
