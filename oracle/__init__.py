@@ -88,6 +88,8 @@ def lib():
             "orc_fine_pair": (C.c_int, [pp, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, i64, i64,
                                         _dp, _dp, _dp]),
             "orc_fine": (i64, [i64, _ip, pp, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _ip, _dp, _dp]),
+            "orc_fine_brute": (i64, [i64, i64, C.POINTER(C.c_int64), pp, d, _dp, _dp, _dp, _dp,
+                                     _dp, _dp, _dp, _ip, i64]),
             "orc_sets": (i64, [i64, i64, _ip, _ip]),
             "orc_transition": (None, [d, d, _dp, _dp, _dp]),
             "orc_correct_set": (None, [i64, _ip, _dp, _dp, _dp, d, d, d]),
@@ -96,7 +98,7 @@ def lib():
             "orc_hkep_set": (d, [i64, _ip, _dp, _dp, _dp, pp, d]),
             "orc_energy": (d, [i64, d, d, _dp, _dp, _dp]),
             "orc_angmom": (None, [i64, _dp, _dp, _dp, _dp]),
-            "orc_step": (C.c_int, [i64, pp, d, _dp, _dp, _dp, _dp, i64, _ip, i64, _ip,
+            "orc_step": (C.c_int, [i64, pp, d, _dp, _dp, _dp, _dp, i64, _ip, i64, _ip, _dp,
                                    C.POINTER(Stats)]),
             "orc_guess_features": (C.c_int, [d, _dp, _dp, d, _dp, _dp, _dp]),
             "orc_guess_net": (d, [_dp, _dp, _dp, _dp]),
@@ -218,6 +220,25 @@ def fine(params: Params, tau, pairs, m, h, A, q0, v0, q1, v1):
     return flags[:k].astype(bool), lhs[:k], rhs[:k]
 
 
+def fine_brute(params: Params, tau, m, h, A, q0, v0, q1, v1, rows=None):
+    """Fine-test flags of every pair that involves a body of rows (all
+    bodies when None), without the crude sweep; returns the flagged pairs
+    (min, max), unique, lexicographically sorted."""
+    q0 = _f64(q0, (-1, 3)); n = q0.shape[0]
+    rows = np.arange(n, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, np.int64)
+    args = [_f64(x) for x in (m, h, A)] + [q0] + [_f64(x, (-1, 3)) for x in (v0, q1, v1)]
+    rp = rows.ctypes.data_as(C.POINTER(C.c_int64))
+    cnt = lib().orc_fine_brute(n, rows.shape[0], rp, C.byref(params), tau,
+                               *[_d(x) for x in args], None, 0)
+    pairs = np.zeros((max(cnt, 1), 2), np.int32)
+    lib().orc_fine_brute(n, rows.shape[0], rp, C.byref(params), tau, *[_d(x) for x in args],
+                         _i(pairs), cnt)
+    pairs = pairs[:cnt]
+    if cnt == 0:
+        return pairs
+    return np.unique(pairs, axis=0)
+
+
 def sets(n, pairs):
     pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
     label = np.empty(max(n, 1), np.int32)
@@ -273,10 +294,15 @@ def angmom(m, q, v):
 
 
 class StepResult:
-    def __init__(self, rc, pairs, label, stats):
+    """rc, encounter pairs (i < j, lexicographic), component labels (the
+    smallest member, -1 outside every set), r_crit of each set (sets in the
+    order of their smallest member) and the step's statistics."""
+
+    def __init__(self, rc, pairs, label, rcrit, stats):
         self.rc = rc
         self.pairs = pairs
         self.label = label
+        self.rcrit = rcrit
         self.stats = stats
 
 
@@ -288,11 +314,13 @@ def step(params: Params, tau, m, h, q, v, cand_cap=None, enc_cap=None):
     enc_cap = cand_cap if enc_cap is None else enc_cap
     pairs = np.zeros((max(enc_cap, 1), 2), np.int32)
     label = np.zeros(max(n, 1), np.int32)
+    rcrit = np.zeros(max(n, 1))
     st = Stats()
     rc = lib().orc_step(n, C.byref(params), tau, _d(_f64(m)), _d(_f64(h)), _d(q), _d(v), cand_cap,
-                        _i(pairs), enc_cap, _i(label), C.byref(st))
+                        _i(pairs), enc_cap, _i(label), _d(rcrit), C.byref(st))
     ne = min(st.n_encounters, enc_cap)
-    return q, v, StepResult(rc, pairs[:ne].copy(), label[:n].copy(), st.as_dict())
+    return q, v, StepResult(rc, pairs[:ne].copy(), label[:n].copy(),
+                            rcrit[:st.n_sets].copy(), st.as_dict())
 
 
 def step_swapped(params: Params, tau, m, q, v, nsteps=1):

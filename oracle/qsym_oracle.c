@@ -22,11 +22,16 @@
  * paper is silent or garbled the reading taken is stated at the function.
  *
  * Parity pins: every function is pinned by the CPU tests (closed forms,
- * invariants, brute force); see the tests for each.  The composite hybrid
- * step (orc_step) has no worked numeric example in the paper: its parity is
- * pinned only through its pinned parts and through invariants
- * (reversibility with encounters off, exact Kepler for a test particle,
- * angular-momentum conservation, second-order energy scaling).
+ * invariants, brute force); see the tests for each.  Among them: r_crit of
+ * each set against the r_crit equation of Sec. 2.2 evaluated with the
+ * semi-major axes the orbits were drawn with; the angular-momentum checker
+ * against hand values and the two-body closed form; the crude sweep against
+ * a brute-force fine test of every pair.  The composite hybrid step
+ * (orc_step) has no worked numeric example in the paper: its parity is
+ * pinned through its pinned parts, through invariants (reversibility with
+ * encounters off, exact Kepler for a test particle, angular-momentum
+ * conservation, second-order energy scaling) and through convergence to an
+ * independent integration of Newton's equations across an active set.
  */
 #include <math.h>
 #include <stdint.h>
@@ -529,6 +534,52 @@ int64_t orc_fine(int64_t npairs, const int32_t *pairs, const orc_params *p, doub
 }
 
 /* ------------------------------------------------------------------ */
+/* Brute force of Sec. 2.4's identification without the crude sweep:    */
+/* the fine test of every pair (i, j), j != i, for each i in rows[];    */
+/* pairs (min, max) are written to pairs[] (capacity cap) grouped by    */
+/* row in the order of rows[], j ascending.  Returns the count.  It is  */
+/* the reference the two-stage sweep must reproduce.                    */
+/* ------------------------------------------------------------------ */
+int64_t orc_fine_brute(int64_t n, int64_t nrows, const int64_t *rows, const orc_params *p,
+                       double tau, const double *m, const double *h, const double *A,
+                       const double *q0, const double *v0, const double *q1, const double *v1,
+                       int32_t *pairs, int64_t cap)
+{
+    int64_t *cnt = (int64_t *)calloc((size_t)(nrows + 1), sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t i = rows[r];
+        int64_t c = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const int64_t a = i < j ? i : j, b = i < j ? j : i;
+            c += orc_fine_pair(p, tau, m, h, A, q0, v0, q1, v1, a, b, NULL, NULL, NULL);
+        }
+        cnt[r + 1] = c;
+    }
+    for (int64_t r = 0; r < nrows; ++r) cnt[r + 1] += cnt[r];
+    const int64_t total = cnt[nrows];
+    if (pairs) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t r = 0; r < nrows; ++r) {
+            const int64_t i = rows[r];
+            int64_t o = cnt[r];
+            for (int64_t j = 0; j < n && o < cap; ++j) {
+                if (j == i) continue;
+                const int64_t a = i < j ? i : j, b = i < j ? j : i;
+                if (orc_fine_pair(p, tau, m, h, A, q0, v0, q1, v1, a, b, NULL, NULL, NULL)) {
+                    pairs[2 * o] = (int32_t)a;
+                    pairs[2 * o + 1] = (int32_t)b;
+                    ++o;
+                }
+            }
+        }
+    }
+    free(cnt);
+    return total;
+}
+
+/* ------------------------------------------------------------------ */
 /* Sec. 2.3 step 4 / Sec. 2.4: division of the encounter pairs into     */
 /* non-intersecting sets = connected components of the encounter graph. */
 /* label[i] = smallest body index of i's component, -1 if i is in no    */
@@ -832,13 +883,15 @@ void orc_angmom(int64_t n, const double *m, const double *q, const double *v, do
 /* 10  drift tau/2                                                      */
 /* Pairs in different sets, or with a non-member, keep K = 1.           */
 /* enc_pairs (capacity enc_cap pairs) and label (n) receive the step's  */
-/* encounter list (i<j, lexicographic) and component labels.            */
+/* encounter list (i<j, lexicographic) and component labels; rcrit_out  */
+/* (n entries) receives r_crit of every set, sets numbered by their     */
+/* smallest member.                                                     */
 /* Returns 0, or a positive code: 1 Kepler cap hit, 2 Hermite cap hit,  */
 /* 4 candidate capacity exceeded.                                       */
 /* ------------------------------------------------------------------ */
 int orc_step(int64_t n, const orc_params *p, double tau, const double *m, const double *h,
              double *q, double *v, int64_t cand_cap, int32_t *enc_pairs, int64_t enc_cap,
-             int32_t *label_out, orc_stats *st)
+             int32_t *label_out, double *rcrit_out, orc_stats *st)
 {
     int rc = 0;
     double mu = p->G * p->m0;
@@ -929,6 +982,7 @@ int orc_step(int64_t n, const orc_params *p, double tau, const double *m, const 
                 if (rh > hmax) hmax = rh;
             }
             double rcrit = s.whole_system ? rc_whole : p->aH * hmax;
+            if (rcrit_out) rcrit_out[k] = rcrit;
             /* 5 */
             orc_correct_set(nm, mk, m, q0, v0, p->G, rcrit, tau / 2.0);
             /* 6: Hermite from (q0, v0) of the members, results into (q, v) */

@@ -102,7 +102,14 @@ def test_two_stage_sweep_equals_brute_force(orc, seed):
     assert np.all(np.diff(keys) > 0)
 
 
-def test_crude_matches_brute_force_predicate(orc):
+def test_crude_predicate_reading(orc):
+    """States the reading taken of the garbled crude predicate of Sec. 2.4
+    (symmetric, conservative: |dq|^2 < (c_s (R_up + tau (ve_i + ve_j)))^2 with
+    R_up = a_E (h_i + h_j)(A_i + A_j)/2).  This documents the reading and
+    keeps it from drifting; what pins the predicate to the method is that it
+    loses no encounter: brute force over all pairs on the 104- and 16k-body
+    disks and sampled rows of the 131k-body disk, and every straight-line
+    approach within a_E mutual Hill radii (test_oracle_pins.py)."""
     s = _close_system(48, 7)
     p = orc.make_params()
     A, ve = orc.prepass(1.0, s.q, s.v)
