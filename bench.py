@@ -46,18 +46,11 @@ FLOP_CRUDE = 6               # per unordered pair (fused crude sweep)
 
 
 def workload(name):
-    from paper_1007_3458_amd import inputs
-    if name == "disk16k":
-        return [inputs.disk16k()], "4 planets + 16384 planetesimals (m=1e-8, a~U[15,40], e~Rayleigh(0.05), i~Rayleigh(0.025)), tau=0.05, aE=3 mutual Hill radii, encounters on"
-    if name == "disk128k":
-        return [inputs.disk128k()], "4 planets + 131072 planetesimals (m=2e-9, a~U[15,40], e~Rayleigh(0.05), i~Rayleigh(0.025)), tau=0.05, aE=3 mutual Hill radii, encounters on"
-    if name == "small":
-        return [inputs.small()], "4 planets + 100 planetesimals, tau=0.05"
-    if name == "batch":
-        return inputs.batch(), "512 systems, N~logU[64,4096]: 1 Jupiter-mass planet at 5.2 + planetesimals (m=1e-8, a~U[3,10]), tau=0.05, encounters on"
-    if name == "learned":
-        return [inputs.learned_workload(n_test=0)], "4 planets + 65536 planetesimals (m=1e-8, disk16k distributions, seed 6), tau=0.05, Kepler solve from the learned start (kepler_mode 2)"
-    raise SystemExit(f"unknown workload {name}")
+    from paper_1007_3458_amd import workloads
+    try:
+        return workloads.workload(name)
+    except ValueError as e:
+        raise SystemExit(str(e))
 
 
 def kernel_source_hash():
@@ -68,9 +61,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name, prec):
-    """HBM bytes per kick launch from the committed rocprofv3 counter summary,
-    when it was taken on the current kernel sources; else None."""
+def measured_traffic(name, prec, kernel):
+    """HBM bytes per launch of one kick kernel ("fused": with the crude sweep,
+    "plain": without) from the committed rocprofv3 counter summary, when it
+    was taken on the current kernel sources for that kernel; else None."""
     path = os.path.join(ROOT, "profiles", f"kick_{name}_p{prec}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -78,7 +72,7 @@ def measured_traffic(name, prec):
         t = json.load(fh)
     if t.get("source_hash") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    return (t.get(kernel) or {}).get("bytes_per_launch")
 
 
 def cpu_baseline(systems, tau, seconds, swapped=False):
@@ -278,6 +272,8 @@ def main():
     ap.add_argument("--no-graph-pass", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="precision 1: skip the FP64 run on the same initial conditions")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="precision 0: skip the FP32 form's run on the same initial conditions")
     ap.add_argument("--swapped", action="store_true",
                     help="encounter-free steps with E_Kep and E_Int swapped (one kick per step)")
     ap.add_argument("--sweep", choices=["fused", "grid"], default="fused",
@@ -349,6 +345,26 @@ def main():
             "fp64_kick_crude_us": r64["kern"].get("kick+crude"), "fp64_kick_us": r64["kern"].get("kick2"),
             "fp64_energy_error": e64, "fp64_kick_shape": shape64}
     r = timed_run(ctx, args.tau, steps, warmup, not args.no_graph_pass, swapped=args.swapped)
+    if (args.precision == 0 and not args.swapped and not args.no_forms and sweep == 0
+            and args.workload != "learned"):
+        # the FP32 pair-term form on the same initial conditions, steps and
+        # energy checkpoints: its speed and energy error against this run;
+        # its accelerations at the initial state against a fresh FP64 context
+        ctx32, shape32 = make_context(systems, 1, args.tau, args.autotune)
+        r32 = timed_run(ctx32, args.tau, steps, warmup, not args.no_graph_pass)
+        ctxa, _ = make_context(systems, 0, args.tau, False)
+        m = np.concatenate([s_.m for s_ in systems]); h = np.concatenate([s_.h for s_ in systems])
+        q0 = np.concatenate([s_.q for s_ in systems]); v0 = np.concatenate([s_.v for s_ in systems])
+        e_max, e_rms = accel_err(kick_accels(ctx32, m, h, q0, v0), kick_accels(ctxa, m, h, q0, v0))
+        ctx32.close()
+        ctxa.close()
+        extra["forms"] = {"fp32_pairs": {
+            "value": 2.0 * npairs * (r32["graph_sps"] or steps / r32["T"]),
+            "steps_per_s": r32["graph_sps"] or steps / r32["T"],
+            "energy_error": float(np.max(r32["dEmax"])),
+            "accel_rel_err_max": e_max, "accel_rel_err_rms": e_rms,
+            "kick_crude_us": r32["kern"].get("kick+crude"), "kick_us": r32["kern"].get("kick2"),
+            "kick_shape": shape32}}
     T = r["T"]
     kicks_per_step = 1.0 if args.swapped else 2.0
     value_profiled = kicks_per_step * npairs * steps / T
@@ -367,6 +383,11 @@ def main():
         e_max, e_rms = accel_err(kick_accels(ctx, m, h, qe, ve), kick_accels(ctx64, m, h, qe, ve))
         pr["accel_rel_err_max_end"], pr["accel_rel_err_rms_end"] = e_max, e_rms
         ctx64.close()
+    if "forms" in extra:
+        f32 = extra["forms"]["fp32_pairs"]
+        f32["speedup_vs_fp64"] = f32["value"] / value
+        f32["energy_error_ratio_vs_fp64"] = f32["energy_error"] / energy_err if energy_err else None
+        f32["same"] = "initial conditions, tau, steps and energy checkpoints as the FP64 run"
     if "learned_report" in extra and "step_first_order" in extra["learned_report"]:
         lr_ = extra["learned_report"]
         q2, _ = ctx.get_state()
@@ -389,7 +410,8 @@ def main():
     achieved = flops / (t_kick * 1e-6) / 1e12 if t_kick else None
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": (achieved / peak) if achieved else None,
-            "traffic": measured_traffic(args.workload, args.precision),
+            "traffic": measured_traffic(args.workload, args.precision,
+                                        "plain" if plain_roof else "fused"),
             "kernel": kick_name + (" (E_Int)" if plain_roof else " (E_Int + fused crude sweep)"),
             "flop_per_launch": flops, "avg_launch_us": t_kick,
             "pairs_per_s_kernel": (npairs / (t_kick * 1e-6)) if t_kick else None}

@@ -47,7 +47,10 @@ extern "C" {
 #define QSYM_EHIP -3       /* HIP runtime error                                */
 #define QSYM_ENONFINITE -4 /* NaN/Inf appeared in the state                    */
 #define QSYM_EKEPLER -5    /* Kepler solver reached its iteration cap          */
-#define QSYM_EOVERFLOW -6  /* candidate or encounter capacity exceeded          */
+#define QSYM_EOVERFLOW -6  /* a system's encounter pairs exceeded its segment
+                              (4 per body + 64); the state is left as it was at
+                              the start of that step, and later steps do nothing
+                              until a new state is set                        */
 #define QSYM_ETRUNC -7     /* output buffer shorter than the true count         */
 #define QSYM_EHERMITE -8   /* Hermite reached its substep cap / set too large   */
 
@@ -70,15 +73,16 @@ typedef struct qsym_params {
                             separations, accumulated in FP64 (Sec. 2 remarks
                             on single-precision forces)                        */
     int32_t max_substeps;/* Hermite substep cap per set per step (>= 1)           */
-    int64_t pair_capacity; /* crude-candidate capacity; 0 selects 8*ntot + 1024  */
+    int64_t pair_capacity; /* crude-candidate list length; 0 selects 8*ntot + 1024.
+                              A sweep that finds more candidates loses none:
+                              the fine test then runs over all pairs (counted
+                              in qsym_stats_t.fallbacks)                      */
     double planet_mass;  /* > 0: bodies at least this massive are planets; a
                             step whose encounter sets put two planets in one
                             set integrates that whole system with the Hermite
                             (Sec. 2.3, after the steps): one set of all its
                             bodies with r_crit infinite (K = 0, W = 1), so the
-                            corrections take back both half kicks.  0: off.
-                            The workspace then holds member slots for every
-                            body.                                             */
+                            corrections take back both half kicks.  0: off. */
     int32_t sweep;       /* crude sweep of Sec. 2.4: 0 fused into the first kick's
                             pair loop (all pairs); 1 on a hashed uniform grid
                             (expected O(N) tests) ahead of a plain first kick.
@@ -106,6 +110,16 @@ typedef struct qsym_stats_t {
     double phase_us[12];      /* per-kernel time when profiling is enabled     */
     int64_t phase_calls[12];  /* launches timed per kernel                     */
     int64_t whole_system;     /* all steps: systems integrated whole (planet_mass) */
+    int64_t fallbacks;        /* all steps: candidate lists that overflowed, the
+                                 fine test then taken over all pairs          */
+    int64_t overflows;        /* all steps: steps left undone because a system's
+                                 encounter pairs exceeded its segment (the state
+                                 stays at the start of the first such step)   */
+    int64_t global_sets;      /* all steps: systems with more than 4096 encounter
+                                 pairs in a step, partitioned in global memory */
+    int64_t kepler_restarts;  /* all steps: Kepler solves whose first start
+                                 reached the iteration cap (then restarted from
+                                 the first-order guess)                       */
 } qsym_stats_t;
 
 typedef struct qsym_ctx qsym_ctx;
@@ -154,16 +168,27 @@ int qsym_sync(qsym_ctx *ctx);
  * the host.  Synchronises. */
 int qsym_energy(qsym_ctx *ctx, double *E);
 
-/* Encounter pairs of the last step (global body indices, i < j,
- * lexicographically sorted) into pairs[2*cap] (host); *n_pairs receives the
+/* Encounter pairs of the last step (Sec. 2.4, the pairs the fine sweep
+ * marks; Sec. 2.3 step 4 divides them into sets) as global body indices,
+ * i < j, lexicographically sorted, into pairs[2*cap] (host); *n_pairs receives the
  * true count (QSYM_ETRUNC if above cap).  set_id (host, ntot entries, may
  * be NULL) receives each body's set index (sets ordered by their smallest
  * member) or -1.  Synchronises. */
 int qsym_encounters(qsym_ctx *ctx, int32_t *pairs, int64_t cap, int64_t *n_pairs,
                     int32_t *set_id);
 
-/* Candidate pairs of the last crude sweep (unordered, i < j) into
- * pairs[2*cap] (host); *n receives the true count.  Synchronises. */
+/* r_crit of every encounter set of the last step (Sec. 2.2, the equation for
+ * r_crit: a_H times the largest Hill radius h_i a_i of the set's members;
+ * infinite for a set that is a whole system) into rcrit[cap] (host), sets
+ * numbered as qsym_encounters numbers them (by smallest member); *n_sets
+ * receives the true count (QSYM_ETRUNC if above cap).  Synchronises. */
+int qsym_set_rcrit(qsym_ctx *ctx, double *rcrit, int64_t cap, int64_t *n_sets);
+
+/* Candidate pairs of the last crude sweep (Sec. 2.4, the first sweep;
+ * unordered, i < j) into pairs[2*cap] (host); *n receives the true count.
+ * QSYM_EOVERFLOW when the sweep found more than the list holds (the step
+ * itself then ran the fine test over all pairs and lost nothing).
+ * Synchronises. */
 int qsym_candidates(qsym_ctx *ctx, int32_t *pairs, int64_t cap, int64_t *n);
 
 int qsym_stats(qsym_ctx *ctx, qsym_stats_t *out);

@@ -39,6 +39,9 @@ struct Layout {
     size_t off_sysoff = 0, off_sysm0 = 0, off_sysS = 0, off_syspoff = 0, off_sysc0 = 0;
     size_t off_bchunk = 0, off_kchunk = 0, off_items = 0, off_eitems = 0, off_syse0 = 0, off_cand = 0;
     size_t off_enc = 0, off_syseoff = 0, off_sysecnt = 0, off_setcount = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0, off_setlist = 0;
+    size_t off_bigsys = 0, off_sysgoff = 0, off_gsa = 0, off_bk = 0;
+    long long gsa_slots = 0;   // global set-partition scratch (64-bit slots)
+    int nbigcap = 0;           // systems that may need it
     size_t off_gbar = 0, off_hpart = 0;
     size_t off_swcnt = 0, off_swslot = 0, off_swrec = 0, off_swlarge = 0, off_syssw = 0,
            off_swpart = 0;
@@ -53,13 +56,14 @@ struct Layout {
     long long n_eitems = 0;
     long long cap = 0;         // candidate capacity
     long long ecap = 0;        // encounter-pair slots (sum of per-system capacities)
+    long long setcap = 0;      // set slots
     long long memcap = 0;      // set-member slots
     long long jchunk_min = 128;
 };
 
 struct Tables {
     std::vector<int> sys_off, sys_S, sys_c0, sys_e0, sys_eoff;
-    std::vector<long long> sys_poff;
+    std::vector<long long> sys_poff, sys_goff;
     std::vector<int4> bchunk, kchunk;
     std::vector<KickItem> eitems;
     std::vector<int> body_sys;
@@ -67,11 +71,15 @@ struct Tables {
 
 int nsys_bodies(const std::vector<long long> &off, int s) { return (int)(off[s + 1] - off[s]); }
 
-// encounter pairs one system may append per step (its segment)
+// encounter pairs one system may append per step (its segment): four per
+// body, far above any disk (the benchmark disks have well under one); a
+// system with more leaves the step undone (S_ENC_OVF).  Systems whose
+// segment exceeds kCapE may need the global-memory set partition.
+constexpr long long kEncPerBody = 4;
 long long sys_enc_cap(long long n)
 {
     if (n <= 0) return 0;
-    return std::min<long long>(std::max<long long>(2 * n, 64), kCapE);
+    return std::min<long long>(kEncPerBody * n + 64, 1LL << 26);
 }
 
 long long jchunk_min_for(const std::vector<long long> &off)
@@ -119,11 +127,24 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     L.n_eitems = std::max<long long>(L.n_eitems, 1);
     L.cap = p.pair_capacity > 0 ? p.pair_capacity : 8 * ntot + 1024;
     L.ecap = 0;
-    for (int s = 0; s < nsys; ++s) L.ecap += sys_enc_cap(off[s + 1] - off[s]);
+    L.setcap = 0;
+    L.gsa_slots = 0;
+    L.nbigcap = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const long long n = off[s + 1] - off[s];
+        L.ecap += sys_enc_cap(n);
+        // a set has two members or more, or is a whole system
+        if (n > 0) L.setcap += n / 2 + 1;
+        if (sys_enc_cap(n) > kCapE) {
+            L.gsa_slots += gs_slots(n);
+            ++L.nbigcap;
+        }
+    }
     L.ecap = std::max<long long>(L.ecap, 1);
-    L.memcap = 2 * L.ecap;
-    // whole-system sets need a member slot for every body
-    if (p.planet_mass > 0.0) L.memcap += off[nsys];
+    L.setcap = std::max<long long>(L.setcap, 1);
+    L.gsa_slots = std::max<long long>(L.gsa_slots, 1);
+    // sets are disjoint: every body is a member of at most one
+    L.memcap = std::max<long long>(ntot, 1);
     size_t o = 0;
     auto take = [&](size_t &field, size_t bytes) {
         o = align_up(o, 256);
@@ -151,11 +172,15 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_enc, (size_t)L.ecap * sizeof(int2));
     take(L.off_syseoff, (size_t)(nsys + 1) * sizeof(int));
     take(L.off_sysecnt, (size_t)std::max(nsys, 1) * sizeof(int));
-    take(L.off_setstart, (size_t)L.ecap * sizeof(int));
-    take(L.off_setcount, (size_t)L.ecap * sizeof(int));
+    take(L.off_setstart, (size_t)L.setcap * sizeof(int));
+    take(L.off_setcount, (size_t)L.setcap * sizeof(int));
     take(L.off_setmem, (size_t)L.memcap * sizeof(int));
-    take(L.off_setrc, (size_t)L.ecap * D);
-    take(L.off_setlist, (size_t)L.ecap * sizeof(int));
+    take(L.off_setrc, (size_t)L.setcap * D);
+    take(L.off_setlist, (size_t)L.setcap * sizeof(int));
+    take(L.off_bigsys, (size_t)std::max(nsys, 1) * sizeof(int));
+    take(L.off_sysgoff, (size_t)std::max(nsys, 1) * sizeof(long long));
+    take(L.off_gsa, (size_t)L.gsa_slots * sizeof(unsigned long long));
+    take(L.off_bk, 6 * (size_t)L.np * D);
     take(L.off_gbar, 4 * sizeof(unsigned));
     take(L.off_hpart, 2 * (size_t)kGridMax * D);
     take(L.off_hw, (size_t)HFIELDS * L.memcap * D);
@@ -224,7 +249,11 @@ Dev bind(char *base, const Layout &L)
     d.set_list = (int *)(base + L.off_setlist);
     d.gbar = (unsigned *)(base + L.off_gbar);
     d.hpart = (double *)(base + L.off_hpart);
-    d.setcap = (int)L.ecap;
+    d.setcap = (int)L.setcap;
+    d.big_sys = (int *)(base + L.off_bigsys);
+    d.sys_goff = (long long *)(base + L.off_sysgoff);
+    d.gsa = (unsigned long long *)(base + L.off_gsa);
+    d.bk = (double *)(base + L.off_bk);
     d.sw_cnt = (int *)(base + L.off_swcnt);
     d.sw_slot = (int *)(base + L.off_swslot);
     d.sw_rec = (SweepRec *)(base + L.off_swrec);
@@ -290,6 +319,7 @@ namespace {
 // message of the last failure that had no context to hold it (creation)
 thread_local std::string g_noctx_err;
 
+
 int fail(qsym_ctx *c, int code, const std::string &msg)
 {
     if (c) c->err = msg;
@@ -311,6 +341,11 @@ int validate(const qsym_params *p, int32_t nsys, const int64_t *offsets, std::st
     for (int s = 0; s < nsys; ++s)
         if (offsets[s + 1] < offsets[s]) { msg = "offsets must be non-decreasing"; return QSYM_EINVAL; }
     if (offsets[nsys] >= (1LL << 30)) { msg = "too many bodies (>= 2^30)"; return QSYM_EINVAL; }
+    {
+        long long ecap = 0;
+        for (int s = 0; s < nsys; ++s) ecap += sys_enc_cap(offsets[s + 1] - offsets[s]);
+        if (ecap >= (1LL << 31)) { msg = "encounter capacity beyond 2^31 pairs"; return QSYM_EINVAL; }
+    }
     if (!(p->G > 0) || !(p->aE >= 0) || !(p->aH > 0) || !(p->epsH >= 0) || !(p->eta > 0) ||
         !(p->eta_s > 0) || !(p->crude_safety >= 1.0)) {
         msg = "parameter out of range (G, aH, eta, eta_s > 0; aE, epsH >= 0; crude_safety >= 1)";
@@ -332,6 +367,7 @@ void build_tables(qsym_ctx *c)
     T.sys_off.assign(nsys + 1, 0);
     T.sys_S.assign(nsys, 0);
     T.sys_poff.assign(nsys, 0);
+    T.sys_goff.assign(nsys, -1);
     T.sys_c0.assign(nsys + 1, 0);
     T.sys_e0.assign(nsys + 1, 0);
     T.sys_eoff.assign(nsys + 1, 0);
@@ -360,8 +396,15 @@ void build_tables(qsym_ctx *c)
         for (long long i = c->off[s]; i < c->off[s + 1]; ++i) T.body_sys[i] = s;
     }
     T.sys_off[nsys] = (int)c->off[nsys];
-    for (int s = 0; s < nsys; ++s)
-        T.sys_eoff[s + 1] = T.sys_eoff[s] + (int)sys_enc_cap(c->off[s + 1] - c->off[s]);
+    long long goff = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const long long n = c->off[s + 1] - c->off[s];
+        T.sys_eoff[s + 1] = T.sys_eoff[s] + (int)sys_enc_cap(n);
+        if (sys_enc_cap(n) > kCapE) {
+            T.sys_goff[s] = goff;
+            goff += gs_slots(n);
+        }
+    }
     T.sys_c0[nsys] = (int)T.bchunk.size();
     T.sys_e0[nsys] = (int)T.eitems.size();
     if (T.bchunk.empty()) T.bchunk.push_back(make_int4(0, 0, 0, 0));
@@ -540,12 +583,16 @@ struct Timer {
     }
 };
 
+// backup (first drift of a hybrid step) keeps the state at the step's
+// start; restore (its last drift) puts it back when the step could not hold
+// its encounter pairs
 hipError_t run_drift(qsym_ctx *c, double dt, int prepass, double tau_crude, int reset,
-                     hipStream_t st, int phase, int count_step = 0)
+                     hipStream_t st, int phase, int count_step = 0, int backup = 0,
+                     int restore = 0)
 {
     Timer tm(c, phase);
     DriftArgs a{c->d, dt, c->p.G, tau_crude, c->p.aE, c->p.crude_safety, prepass, c->p.hill_mode,
-                reset, count_step, prepass && c->p.sweep == 1};
+                reset, count_step, prepass && c->p.sweep == 1, backup, restore};
     hipLaunchKernelGGL(k_drift, dim3(nblocks_chunks(c)), dim3(kChunk), 0, st, a);
     return hipGetLastError();
 }
@@ -622,10 +669,13 @@ hipError_t run_kick1(qsym_ctx *c, double tau, hipStream_t st)
     return launch_kick(c, 0, st);
 }
 
+// workgroups of k_fine: enough for the candidate list, and for the
+// all-pairs tiles when the list overflows
 int fine_grid(qsym_ctx *c)
 {
-    long long g = (c->L.cap + 255) / 256;
-    return (int)std::max<long long>(1, std::min<long long>(g, 128));
+    const long long g = std::min<long long>((c->L.cap + 255) / 256, 128);
+    const long long ge = std::min<long long>((long long)c->T.eitems.size(), 1024);
+    return (int)std::max<long long>(1, std::max(g, ge));
 }
 
 // one full hybrid step (Sec. 2.3) enqueued on st
@@ -633,8 +683,9 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
 {
     hipError_t e;
     const double half = tau / 2.0;
-    // 1: drift tau/2 + per-body encounter terms, reset per-step counters
-    if ((e = run_drift(c, half, 1, tau, 1, st, P_DRIFT)) != hipSuccess) return e;
+    // 1: drift tau/2 + per-body encounter terms, reset per-step counters,
+    // copy of the state at the step's start
+    if ((e = run_drift(c, half, 1, tau, 1, st, P_DRIFT, 0, 1, 0)) != hipSuccess) return e;
     // 2: kick tau/2 with the crude sweep
     if ((e = run_kick1(c, tau, st)) != hipSuccess) return e;
     // 2-3: apply the kick, snapshot (q0, v0), Kepler tau -> (q1, v1)
@@ -643,7 +694,8 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
     // 4: fine sweep, sets, r_crit
     {
         Timer tm(c, P_FINE);
-        FineArgs fa{c->d, tau, c->p.aE, c->L.cap, c->p.hill_mode};
+        FineArgs fa{c->d, tau, c->p.aE, c->p.crude_safety, std::fabs(tau), c->L.cap,
+                    c->p.hill_mode, (int)c->T.eitems.size()};
         hipLaunchKernelGGL(k_fine, dim3(fine_grid(c)), dim3(256), 0, st, fa);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -652,6 +704,13 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
         SetsArgs sa{c->d, c->p.aH, c->p.planet_mass};
         hipLaunchKernelGGL(k_sets, dim3(c->nsys), dim3(kSetsThreads), 0, st, sa);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        // systems with more pairs than LDS holds, in global memory (only
+        // systems whose segment exceeds kCapE can have them)
+        if (c->L.nbigcap > 0) {
+            hipLaunchKernelGGL(k_sets_big, dim3(std::min(c->L.nbigcap, 128)), dim3(kSetsBigThreads), 0,
+                               st, sa);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     // 5-7: corrections and Hermite per set
     {
@@ -668,8 +727,9 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
     // 9: kick tau/2 (all pairs), applied with the momentum partials
     if ((e = run_kick(c, 0, 0.0, st, P_KICK2)) != hipSuccess) return e;
     if ((e = run_apply(c, half, 0.0, 1, 0, 0, 1, st, P_APPLY2, 0)) != hipSuccess) return e;
-    // 10: drift tau/2
-    return run_drift(c, half, 0, 0.0, 0, st, P_DRIFT2, 1);
+    // 10: drift tau/2 (or, for a step that could not hold its encounter
+    // pairs, the state at its start)
+    return run_drift(c, half, 0, 0.0, 0, st, P_DRIFT2, 1, 0, 1);
 }
 
 void enter(qsym_ctx *c)
@@ -690,7 +750,9 @@ int status_code(qsym_ctx *c, unsigned long long st)
     if (st & (S_CAND_OVF | S_ENC_OVF))
         return fail(c, QSYM_EOVERFLOW, (st & S_CAND_OVF)
                                            ? "crude-candidate capacity exceeded"
-                                           : "more encounter pairs than the set kernel holds");
+                                           : "a system had more encounter pairs than its segment "
+                                             "holds (4 per body + 64); the state is that of the "
+                                             "start of that step");
     if (st & (S_HERMITE | S_SET_BIG))
         return fail(c, QSYM_EHERMITE, "Hermite substep cap reached or set too large");
     if (st & S_KEPLER) return fail(c, QSYM_EKEPLER, "Kepler solver reached its iteration cap");
@@ -852,6 +914,9 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.sys_eoff, T.sys_eoff.data(), sizeof(int) * T.sys_eoff.size(),
                          hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.sys_goff, T.sys_goff.data(), sizeof(long long) * nsys,
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+
     ok &= hipMemcpyAsync(c->d.bchunk, T.bchunk.data(), sizeof(int4) * T.bchunk.size(),
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.kchunk, T.kchunk.data(), sizeof(int4) * T.kchunk.size(),
@@ -1060,6 +1125,37 @@ int qsym_encounters(qsym_ctx *c, int32_t *pairs, int64_t cap, int64_t *n_pairs, 
     return QSYM_OK;
 }
 
+int qsym_set_rcrit(qsym_ctx *c, double *rcrit, int64_t cap, int64_t *n_sets)
+{
+    if (!c || !n_sets || cap < 0 || (cap > 0 && !rcrit)) return fail(c, QSYM_EINVAL, "set_rcrit: bad argument");
+    unsigned long long h[C_COUNT];
+    int rc = read_ctr(c, h);
+    if (rc) return rc;
+    rc = status_code(c, h[C_STATUS]);
+    if (rc) return rc;
+    const long long ns = (long long)h[C_NSETS], nu = (long long)h[C_NU];
+    *n_sets = ns;
+    if (ns > 0 && cap > 0) {
+        hipStream_t st = c->stream;
+        std::vector<int> start(ns), mem(nu);
+        std::vector<double> rcv(ns);
+        HIPCHK(c, hipMemcpyAsync(start.data(), c->d.set_start, sizeof(int) * ns, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(mem.data(), c->d.set_mem, sizeof(int) * nu, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(rcv.data(), c->d.set_rc, sizeof(double) * ns, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        // sets numbered by their smallest member (members ascend), as in
+        // qsym_encounters
+        std::vector<long long> order(ns);
+        for (long long s = 0; s < ns; ++s) order[s] = s;
+        std::sort(order.begin(), order.end(),
+                  [&](long long a, long long b) { return mem[start[a]] < mem[start[b]]; });
+        const long long k = std::min<long long>(ns, cap);
+        for (long long r = 0; r < k; ++r) rcrit[r] = rcv[order[r]];
+    }
+    if (ns > cap) return fail(c, QSYM_ETRUNC, "r_crit buffer shorter than the set count");
+    return QSYM_OK;
+}
+
 int qsym_candidates(qsym_ctx *c, int32_t *pairs, int64_t cap, int64_t *n)
 {
     if (!c || !n || cap < 0 || (cap > 0 && !pairs)) return fail(c, QSYM_EINVAL, "candidates: bad argument");
@@ -1107,12 +1203,18 @@ int qsym_stats(qsym_ctx *c, qsym_stats_t *out)
             kit += k[kHist];
             kmax = std::max(kmax, k[kHist + 1]);
         }
+        unsigned long long krs = 0;
+        for (int s = 0; s < kStatStripes; ++s) krs += ks[(size_t)s * kStatStride + kHist + 2];
+        out->kepler_restarts = (int64_t)krs;
         out->kepler_iters = (int64_t)kit;
         out->kepler_max = (int64_t)kmax;
         for (int b = 0; b < kHist; ++b) out->kepler_hist[b] = (int64_t)hist[b];
     }
     out->status = (int64_t)h[C_STATUS];
     out->whole_system = (int64_t)h[C_WHOLE];
+    out->fallbacks = (int64_t)h[C_FALLBACK];
+    out->overflows = (int64_t)h[C_OVERFLOW];
+    out->global_sets = (int64_t)h[C_TBIGSYS];
     for (int k = 0; k < kPhases; ++k) {
         out->phase_us[k] = c->phase_us[k];
         out->phase_calls[k] = c->phase_calls[k];

@@ -8,8 +8,9 @@ namespace qsym {
 
 constexpr int kChunk = 256;        // bodies per workgroup of the O(N) kernels
 constexpr int kChunkK = 64;        // bodies per workgroup of the Kepler pass
-constexpr int kCapE = 4096;        // encounter pairs of one system per step (on chip)
-constexpr int kCapU = 2 * kCapE;   // bodies of one system taking part in encounters
+constexpr int kCapE = 4096;        // encounter pairs of one system partitioned on chip (LDS)
+constexpr int kCapU = 2 * kCapE;   // bodies of one system taking part in encounters (LDS)
+constexpr int kSetsBigThreads = 1024;   // workgroup of the global-memory set partition
 constexpr int kHist = 32;
 // The Kepler pass's statistics (iteration histogram, total, largest) are
 // kept in kStatStripes copies, kStatStride entries (512 B) apart: the
@@ -17,7 +18,8 @@ constexpr int kHist = 32;
 // over many memory channels instead of queueing on one line; the host adds
 // the copies up when it reads the statistics.
 constexpr int kStatStripes = 64;
-constexpr int kStatStride = 64;   // entries: [0, kHist) histogram, kHist total, kHist + 1 largest          // Kepler iteration histogram bins
+constexpr int kStatStride = 64;   // entries: [0, kHist) histogram, kHist total, kHist + 1 largest,
+                                  // kHist + 2 solves restarted from the first-order guess
 constexpr int kSMax = 64;          // largest j-split of one system
 constexpr int kSetsThreads = 256;  // workgroup of the set-partition kernel
 constexpr int kHermThreads = 512;  // workgroup of the Hermite kernel
@@ -43,6 +45,10 @@ enum Ctr {
     C_NBIG,       // larger sets (one workgroup each), last step
     C_WHOLE,      // systems integrated whole (all steps)
     C_NLARGE,     // grid sweep: bodies on the large list, last step
+    C_NBIGSYS,    // systems whose sets are partitioned in global memory, last step
+    C_TBIGSYS,    // the same, all steps
+    C_FALLBACK,   // steps whose candidate list overflowed: all-pairs fine sweep instead
+    C_OVERFLOW,   // steps left undone because a system's encounter pairs overflowed
     C_COUNT
 };
 
@@ -54,6 +60,27 @@ enum Status : unsigned long long {
     S_NONFINITE = 16,
     S_SET_BIG = 32,
 };
+
+// Status bits that stop the integration: a step that raises one leaves the
+// state as it was at the step's start (the first drift keeps a copy, the
+// last one puts it back), and every later step does the same until a new
+// state is set.
+constexpr unsigned long long S_FREEZE = S_ENC_OVF;
+
+// Global-memory scratch of the set partition of one system of n bodies (in
+// 64-bit slots): body bitmap, its word prefix counts, the bodies in
+// encounters, union-find labels, root flags, and the member sort keys.
+__host__ __device__ inline long long gs_words(long long n) { return (n + 31) / 32; }
+__host__ __device__ inline long long gs_pow2(long long n)
+{
+    long long p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+__host__ __device__ inline long long gs_slots(long long n)
+{
+    return 2 * ((gs_words(n) + 1) / 2) + 3 * ((n + 1) / 2) + gs_pow2(n);
+}
 
 // one workgroup of the pair kernels: i-bodies [i0, i0+ni) of system sys
 // against j-bodies [j0, j0+nj) (its j-chunk number `chunk`)
@@ -97,6 +124,10 @@ struct Dev {
     double *set_rc;                             // [setcap] r_crit per set
     int *set_list;                              // [setcap] small sets from 0 up, big from the end down
     int setcap;                                 // set slots
+    int *big_sys;                               // [nsys] systems for the global set partition
+    long long *sys_goff;                        // [nsys] their scratch offset in gsa (-1: none)
+    unsigned long long *gsa;                    // global set-partition scratch
+    double *bk;                                 // [6][np] state at the start of the step
     unsigned *gbar;                             // grid barrier of k_hermite_grid (3 words)
     double *hpart;                              // [2][kGridMax] its per-block step minima
     int *sw_cnt;                                // grid sweep: [sw_nb] bucket counts

@@ -56,9 +56,9 @@ __global__ __launch_bounds__(256) void k_kepler_solve(double mu, long long n, St
     body_terms(s, i, r0, rv, vv);
     const double smu = sqrt(mu);
     const double alpha = 2.0 / r0 - vv / mu;
-    int count = 0;
+    int count = 0, restart;
     double x;
-    const int ok = kepler_root(smu, r0, rv, alpha, h, mode, w, x, count);
+    const int ok = kepler_root(smu, r0, rv, alpha, h, mode, w, x, count, restart);
     xo[i] = x;
     if (it) it[i] = ok ? count : -count;
 }
@@ -386,6 +386,7 @@ int launch_update(qsym_guess_trainer *tr, const UpdateArgs &a)
 bool bad_state_args(long long n, const void *st, const void *dt) { return n < 0 || (n > 0 && (!st || !dt)); }
 
 }  // namespace
+
 
 extern "C" {
 

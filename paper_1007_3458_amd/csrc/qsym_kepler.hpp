@@ -196,18 +196,21 @@ __device__ __forceinline__ bool start_admissible(double mu, double r0, double rv
 //   mode 2: Newton from the learned start when it is admissible, else
 //           from the first-order guess
 // Modes 1 and 2 fall back to Laguerre from the first-order guess when Newton
-// reaches the cap.  Returns 1 when converged; adds iterations to count.
+// reaches the cap.  Returns 1 when converged; adds iterations to count and
+// sets restart when the first start reached the cap.
 // ------------------------------------------------------------------------
 __device__ __forceinline__ int kepler_root(double smu, double r0, double rv, double alpha,
                                            double dt, int mode, const float *w, double &x,
-                                           int &count)
+                                           int &count, int &restart)
 {
     const double guess = smu * dt / r0;
     int ok;
+    restart = 0;
     if (mode == 0) {
         x = r0;
         ok = kepler_iterate(smu, r0, rv, alpha, dt, 1, x, count);
         if (!ok) {
+            restart = 1;
             x = guess;
             ok = kepler_iterate(smu, r0, rv, alpha, dt, 1, x, count);
         }
@@ -219,6 +222,7 @@ __device__ __forceinline__ int kepler_root(double smu, double r0, double rv, dou
         }
         ok = kepler_iterate(smu, r0, rv, alpha, dt, 0, x, count);
         if (!ok) {
+            restart = 1;
             x = guess;
             ok = kepler_iterate(smu, r0, rv, alpha, dt, 1, x, count);
         }
@@ -227,12 +231,14 @@ __device__ __forceinline__ int kepler_root(double smu, double r0, double rv, dou
 }
 
 // Advance one body by dt about mu (Appendix A f and g functions); returns
-// iterations, sets fail when every start reached the cap.
+// iterations, sets fail when every start reached the cap and restart when
+// the first one did.
 __device__ __forceinline__ int kepler_advance(double mu, int mode, const float *w, double dt,
                                               double &x, double &y, double &z, double &vx,
-                                              double &vy, double &vz, int &fail)
+                                              double &vy, double &vz, int &fail, int &restart)
 {
     fail = 0;
+    restart = 0;
     if (dt == 0.0) return 0;
     const double r0 = sqrt(x * x + y * y + z * z);
     const double vv = vx * vx + vy * vy + vz * vz;
@@ -241,7 +247,7 @@ __device__ __forceinline__ int kepler_advance(double mu, int mode, const float *
     const double alpha = 2.0 / r0 - vv / mu;
     int count = 0;
     double xu;
-    fail = !kepler_root(smu, r0, rv, alpha, dt, mode, w, xu, count);
+    fail = !kepler_root(smu, r0, rv, alpha, dt, mode, w, xu, count, restart);
     const double zz = alpha * xu * xu;
     double C, S;
     stumpff(zz, C, S);

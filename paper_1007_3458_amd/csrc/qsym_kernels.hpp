@@ -98,6 +98,8 @@ struct DriftArgs {
     double dt, G, tau_crude, aE, cs;
     int prepass, hill_mode, reset, count_step;
     int sweep_stats;   // grid crude sweep next: per-chunk sums of (a, h or h a, ve), clear its table
+    int backup;        // first drift of a hybrid step: keep the state at the step's start
+    int restore;       // last drift of a hybrid step: put it back when the step could not be done
 };
 
 __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
@@ -106,6 +108,44 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
     const Dev &d = a.d;
     const int4 bc = d.bchunk[blockIdx.x];
     const int s = bc.x;
+    // the status is only raised by other kernels, so every workgroup reads
+    // the same word here
+    const bool frozen = (a.backup || a.restore) && (d.ctr[C_STATUS] & S_FREEZE);
+    const long long S = (long long)(d.y - d.x);   // stride of the state arrays
+    if (a.restore && frozen) {
+        // the step could not hold its encounter pairs: the state goes back to
+        // the step's start, with its momentum partials (as k_momentum)
+        const int t = threadIdx.x, i = bc.y + t;
+        double p[3] = {0.0, 0.0, 0.0};
+        if (t < bc.z) {
+            const double *bk = d.bk;
+            d.x[i] = bk[i];
+            d.y[i] = bk[S + i];
+            d.z[i] = bk[2 * S + i];
+            d.vx[i] = bk[3 * S + i];
+            d.vy[i] = bk[4 * S + i];
+            d.vz[i] = bk[5 * S + i];
+            const double mi = d.m[i];
+            p[0] = mi * d.vx[i];
+            p[1] = mi * d.vy[i];
+            p[2] = mi * d.vz[i];
+        }
+        for (int k = 0; k < 3; ++k) {
+            const double sm = block_sum<kChunk>(p[k], lds);
+            if (t == 0) d.pm[3 * blockIdx.x + k] = sm;
+        }
+        if (blockIdx.x == 0 && t == 0) d.ctr[C_OVERFLOW] += 1;
+        return;
+    }
+    if (a.backup && !frozen && (int)threadIdx.x < bc.z) {
+        const int i = bc.y + threadIdx.x;
+        d.bk[i] = d.x[i];
+        d.bk[S + i] = d.y[i];
+        d.bk[2 * S + i] = d.z[i];
+        d.bk[3 * S + i] = d.vx[i];
+        d.bk[4 * S + i] = d.vy[i];
+        d.bk[5 * S + i] = d.vz[i];
+    }
     double P[3];
     system_momentum<kChunk>(d, s, lds, P);
     if (a.reset && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -118,6 +158,7 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
         d.ctr[C_NSMALL] = 0;
         d.ctr[C_NBIG] = 0;
         d.ctr[C_NLARGE] = 0;
+        d.ctr[C_NBIGSYS] = 0;
         d.gbar[0] = 0u;
         d.gbar[1] = 0u;
         d.gbar[2] = 0u;
@@ -213,21 +254,29 @@ __device__ __forceinline__ double wave_max(double v)
 // Crude sweep, exact form (Sec. 2.4 reading): evaluated only for the pairs
 // that passed the per-tile bound; same operands and operation order as the
 // definition:  |Q_j-Q_i|^2 < (c_s (R_up + |tau| (ve_i + ve_j)))^2.
+// X, Y, Z: the positions the sweep runs at (the kick's, or their snapshot).
+__device__ __forceinline__ bool crude_pass(const Dev &d, const double *X, const double *Y,
+                                           const double *Z, int hill_mode, double aE, double cs,
+                                           double tau_abs, int i, int j)
+{
+    const double dx = X[j] - X[i];
+    const double dy = Y[j] - Y[i];
+    const double dz = Z[j] - Z[i];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    double Rup;
+    if (hill_mode == 0)
+        Rup = aE * (d.h[i] + d.h[j]) * (d.A[i] + d.A[j]) / 2.0;
+    else
+        Rup = aE * (d.h[i] * d.A[i] + d.h[j] * d.A[j]);
+    const double lim = cs * (Rup + tau_abs * (d.cv[i] + d.cv[j]));
+    return r2 < lim * lim;
+}
+
 __device__ __forceinline__ void crude_exact(const KickArgs &ka, int i, int j)
 {
     const Dev &d = ka.d;
     if (j <= i) return;
-    const double dx = d.x[j] - d.x[i];
-    const double dy = d.y[j] - d.y[i];
-    const double dz = d.z[j] - d.z[i];
-    const double r2 = dx * dx + dy * dy + dz * dz;
-    double Rup;
-    if (ka.hill_mode == 0)
-        Rup = ka.aE * (d.h[i] + d.h[j]) * (d.A[i] + d.A[j]) / 2.0;
-    else
-        Rup = ka.aE * (d.h[i] * d.A[i] + d.h[j] * d.A[j]);
-    const double lim = ka.cs * (Rup + ka.tau_abs * (d.cv[i] + d.cv[j]));
-    if (r2 < lim * lim) {
+    if (crude_pass(d, d.x, d.y, d.z, ka.hill_mode, ka.aE, ka.cs, ka.tau_abs, i, j)) {
         const unsigned long long slot = atomicAdd(&d.ctr[C_CAND], 1ull);
         if ((long long)slot < ka.cap) d.cand[slot] = make_int2(i, j);
     }
@@ -310,6 +359,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
     int b = blockIdx.x;
     if (ka.remap) b = xcd_item(b, gridDim.x);
     if (b >= ka.nitems) return;
+    if (d.ctr[C_STATUS] & S_FREEZE) return;   // a step left undone: nothing to compute
     const KickItem it = ka.items[b];
     constexpr int NW = BS / 64;
 
@@ -630,6 +680,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
     int b = blockIdx.x;
     if (ka.remap) b = xcd_item(b, gridDim.x);
     if (b >= ka.nitems) return;
+    if (d.ctr[C_STATUS] & S_FREEZE) return;   // a step left undone: nothing to compute
     const KickItem it = ka.items[b];
     constexpr int NW = BS / 64;
     constexpr int BI = BS * IPL;
@@ -861,7 +912,7 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
     __shared__ double lds[BS * P];
     __shared__ double share[P > 1 ? P : 1][3][BS];
     __shared__ unsigned int hist[kHist];
-    __shared__ unsigned int kmax;
+    __shared__ unsigned int kmax, krestart;
     __shared__ unsigned long long ksum;
     __shared__ int bad;
     const Dev &d = a.d;
@@ -871,6 +922,7 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
     if (t < kHist) hist[t] = 0;
     if (t == 0) {
         kmax = 0;
+        krestart = 0;
         ksum = 0;
         bad = 0;
     }
@@ -911,12 +963,13 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
             d.vz0[i] = vz;
         }
         if (a.do_kep) {
-            int fail;
+            int fail, restart;
             const int it = kepler_advance(a.G * d.sys_m0[s], a.kepler_mode, d.guess, a.dt_kep, x, y,
-                                          z, vx, vy, vz, fail);
+                                          z, vx, vy, vz, fail, restart);
             atomicAdd(&hist[it < kHist ? it : kHist - 1], 1u);
             atomicMax(&kmax, (unsigned)it);
             atomicAdd(&ksum, (unsigned long long)it);
+            if (restart) atomicAdd(&krestart, 1u);
             if (fail) atomicOr(&bad, (int)S_KEPLER);
         }
         if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) &&
@@ -946,6 +999,7 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
         if (t == 0) {
             atomicAdd(&ks[kHist], ksum);
             atomicMax(&ks[kHist + 1], (unsigned long long)kmax);
+            if (krestart) atomicAdd(&ks[kHist + 2], (unsigned long long)krestart);
         }
     }
     if (t == 0 && bad) latch(d.ctr, (unsigned long long)bad);
@@ -1011,33 +1065,60 @@ __device__ int fine_pair(int hill_mode, double aE, double m0, double tau, double
 
 struct FineArgs {
     Dev d;
-    double tau, aE;
+    double tau, aE, cs, tau_abs;
     long long cap;
     int hill_mode;
+    int n_eitems;   // all-pairs tiles (the energy items) for the overflow sweep
 };
 
+// fine test of candidate (i, j), i < j, appended to its system's segment
+// when it is an encounter (the count is kept even past the segment's end)
+__device__ __forceinline__ void fine_one(const FineArgs &a, int i, int j)
+{
+    const Dev &d = a.d;
+    const double a0[3] = {d.x0[j] - d.x0[i], d.y0[j] - d.y0[i], d.z0[j] - d.z0[i]};
+    const double b0[3] = {d.vx0[j] - d.vx0[i], d.vy0[j] - d.vy0[i], d.vz0[j] - d.vz0[i]};
+    const double a1[3] = {d.x[j] - d.x[i], d.y[j] - d.y[i], d.z[j] - d.z[i]};
+    const double b1[3] = {d.vx[j] - d.vx[i], d.vy[j] - d.vy[i], d.vz[j] - d.vz[i]};
+    double lhs, rhs;
+    const int f = fine_pair(a.hill_mode, a.aE, d.sys_m0[d.body_sys[i]], a.tau, d.m[i], d.m[j],
+                            d.h[i], d.h[j], d.A[i], d.A[j], a0, b0, a1, b1, lhs, rhs);
+    if (f) {
+        atomicAdd(&d.ctr[C_ENC], 1ull);
+        const int s = d.body_sys[i];
+        const int slot = atomicAdd(&d.sys_ecnt[s], 1);
+        if (slot < d.sys_eoff[s + 1] - d.sys_eoff[s]) d.enc[d.sys_eoff[s] + slot] = make_int2(i, j);
+    }
+}
+
+// The candidates of the crude sweep, or, when more candidates were found
+// than the list holds, every pair i < j of every system: the crude test of
+// the definition at the snapshot positions (the first kick's positions, so
+// the same decisions the sweep took) and the fine test for those passing.
+// Either way no encounter is lost; the second way costs one all-pairs pass
+// and is counted in C_FALLBACK.
 __global__ __launch_bounds__(256) void k_fine(FineArgs a)
 {
     const Dev &d = a.d;
+    if (d.ctr[C_STATUS] & S_FREEZE) return;
     const unsigned long long cnt = d.ctr[C_CAND];
-    const long long n = (long long)cnt < a.cap ? (long long)cnt : a.cap;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && (long long)cnt > a.cap) latch(d.ctr, S_CAND_OVF);
-    for (long long k = blockIdx.x * 256ll + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
-        const int2 p = d.cand[k];
-        const int i = p.x, j = p.y;
-        const double a0[3] = {d.x0[j] - d.x0[i], d.y0[j] - d.y0[i], d.z0[j] - d.z0[i]};
-        const double b0[3] = {d.vx0[j] - d.vx0[i], d.vy0[j] - d.vy0[i], d.vz0[j] - d.vz0[i]};
-        const double a1[3] = {d.x[j] - d.x[i], d.y[j] - d.y[i], d.z[j] - d.z[i]};
-        const double b1[3] = {d.vx[j] - d.vx[i], d.vy[j] - d.vy[i], d.vz[j] - d.vz[i]};
-        double lhs, rhs;
-        const int f = fine_pair(a.hill_mode, a.aE, d.sys_m0[d.body_sys[i]], a.tau, d.m[i], d.m[j],
-                                d.h[i], d.h[j], d.A[i], d.A[j], a0, b0, a1, b1, lhs, rhs);
-        if (f) {
-            atomicAdd(&d.ctr[C_ENC], 1ull);
-            const int s = d.body_sys[i];
-            const int slot = atomicAdd(&d.sys_ecnt[s], 1);
-            if (slot < d.sys_eoff[s + 1] - d.sys_eoff[s]) d.enc[d.sys_eoff[s] + slot] = make_int2(i, j);
+    if ((long long)cnt <= a.cap) {
+        const long long n = (long long)cnt;
+        for (long long k = blockIdx.x * 256ll + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+            const int2 p = d.cand[k];
+            fine_one(a, p.x, p.y);
         }
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.ctr[C_FALLBACK] += 1;
+    for (int it = blockIdx.x; it < a.n_eitems; it += gridDim.x) {
+        const KickItem e = d.eitems[it];
+        if ((int)threadIdx.x >= e.ni) continue;
+        const int i = e.i0 + threadIdx.x;
+        const int jhi = e.j0 + e.nj;
+        for (int j = max(e.j0, i + 1); j < jhi; ++j)
+            if (crude_pass(d, d.x0, d.y0, d.z0, a.hill_mode, a.aE, a.cs, a.tau_abs, i, j))
+                fine_one(a, i, j);
     }
 }
 
@@ -1229,8 +1310,15 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     const int sys = blockIdx.x;
     const int cnt = d.sys_ecnt[sys];
     const int2 *enc = d.enc + d.sys_eoff[sys];
-    if (cnt > d.sys_eoff[sys + 1] - d.sys_eoff[sys] || cnt > kCapE) {
+    if (d.ctr[C_STATUS] & S_FREEZE) return;
+    if (cnt > d.sys_eoff[sys + 1] - d.sys_eoff[sys]) {
+        // more pairs than the system's segment holds: the step is left undone
         if (t == 0) latch(d.ctr, S_ENC_OVF);
+        return;
+    }
+    if (cnt > kCapE) {
+        // beyond LDS: k_sets_big partitions this system in global memory
+        if (t == 0) d.big_sys[(int)atomicAdd(&d.ctr[C_NBIGSYS], 1ull)] = sys;
         return;
     }
     const int ne = cnt;
@@ -1447,6 +1535,229 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     }
     if (big) atomicMax(&d.ctr[C_MAXSET], (unsigned long long)big);
     if (t == 0) atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
+}
+
+// ------------------------------------------------------------------------
+// Set partition of the systems with more encounter pairs than LDS holds
+// (Sec. 2.3 step 4, the same result as k_sets): one 1024-thread workgroup
+// per system, everything in the system's global scratch -- the bodies in
+// encounters from a bitmap of the system (ascending, ranked by popcount
+// prefixes), union-find with union by minimum, roots numbered in ascending
+// order, members sorted by (root, body) with a bitonic sort, r_crit =
+// a_H max h_i a_i per set (Sec. 2.2), the Hermite work lists.  Words that
+// atomics change are read back with atomic loads: atomics act in the L2,
+// plain loads may be served by the compute unit's L1.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ unsigned ld_u32(const unsigned *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int ld_i32(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kSetsBigThreads) void k_sets_big(SetsArgs a)
+{
+    const Dev &d = a.d;
+    constexpr int T = kSetsBigThreads;
+    __shared__ int tmp[T / 64 + 1];
+    __shared__ int base_set, base_mem, s_whole;
+    const int t = threadIdx.x;
+    const int nbs = (int)d.ctr[C_NBIGSYS];
+    for (int q = blockIdx.x; q < nbs; q += gridDim.x) {
+        const int sys = d.big_sys[q];
+        const int ne = d.sys_ecnt[sys];
+        const int2 *enc = d.enc + d.sys_eoff[sys];
+        const int so = d.sys_off[sys], nsb = d.sys_off[sys + 1] - so;
+        // scratch of gs_slots(nsb) 64-bit slots (see qsym_common.hpp)
+        unsigned long long *g = d.gsa + d.sys_goff[sys];
+        const int nw = (int)gs_words(nsb);
+        const long long wh = (gs_words(nsb) + 1) / 2, nh = (nsb + 1) / 2;
+        unsigned *bits = reinterpret_cast<unsigned *>(g);
+        int *wpre = reinterpret_cast<int *>(g + wh);
+        int *uq = reinterpret_cast<int *>(g + 2 * wh);
+        int *lab = reinterpret_cast<int *>(g + 2 * wh + nh);
+        int *root = reinterpret_cast<int *>(g + 2 * wh + 2 * nh);
+        unsigned long long *key = g + 2 * wh + 3 * nh;
+        // the bodies taking part: set bits of the system's bitmap; a body's
+        // rank is the number of set bits before it
+        for (int k = t; k < nw; k += T) bits[k] = 0u;
+        __syncthreads();
+        for (int k = t; k < ne; k += T) {
+            const int2 p = enc[k];
+            atomicOr(&bits[(p.x - so) >> 5], 1u << ((p.x - so) & 31));
+            atomicOr(&bits[(p.y - so) >> 5], 1u << ((p.y - so) & 31));
+        }
+        __syncthreads();
+        for (int k = t; k < nw; k += T) wpre[k] = __popc(ld_u32(&bits[k]));
+        __syncthreads();
+        const int nu = block_scan_excl(wpre, nw, tmp);
+        for (int k = t; k < nw; k += T) {
+            unsigned w = ld_u32(&bits[k]);
+            int r = wpre[k];
+            while (w) {
+                uq[r++] = so + (k << 5) + __ffs(w) - 1;
+                w &= w - 1u;
+            }
+        }
+        for (int k = t; k < nu; k += T) lab[k] = k;
+        __syncthreads();
+        // union-find with union by minimum: every component ends rooted at
+        // its smallest rank whatever the order of the links
+        for (int k = t; k < ne; k += T) {
+            const int2 p = enc[k];
+            const int bx = p.x - so, by = p.y - so;
+            int x = wpre[bx >> 5] + __popc(ld_u32(&bits[bx >> 5]) & ((1u << (bx & 31)) - 1u));
+            int y = wpre[by >> 5] + __popc(ld_u32(&bits[by >> 5]) & ((1u << (by & 31)) - 1u));
+            for (;;) {
+                for (int px; (px = ld_i32(&lab[x])) != x;) x = px;
+                for (int py; (py = ld_i32(&lab[y])) != y;) y = py;
+                if (x == y) break;
+                if (x > y) {
+                    const int w = x;
+                    x = y;
+                    y = w;
+                }
+                const int old = atomicCAS(&lab[y], y, x);
+                if (old == y) break;
+                y = old;
+            }
+        }
+        __syncthreads();
+        for (int k = t; k < nu; k += T) {
+            int x = k;
+            for (int px; (px = ld_i32(&lab[x])) != x;) x = px;
+            root[k] = x;
+        }
+        __syncthreads();
+        // roots numbered in ascending order: lab[r] = set id of root r
+        for (int k = t; k < nu; k += T) lab[k] = root[k] == k ? 1 : 0;
+        __syncthreads();
+        const int nsets = block_scan_excl(lab, nu, tmp);
+        // Sec. 2.3, after the steps: a set holding two planets makes the
+        // whole system one set with r_crit infinite (as in k_sets); the
+        // planet counts use the key space, which holds nothing yet
+        if (a.planet_mass > 0.0) {
+            int *pc = reinterpret_cast<int *>(key);
+            for (int k = t; k < nsets; k += T) pc[k] = 0;
+            if (t == 0) s_whole = 0;
+            __syncthreads();
+            for (int k = t; k < nu; k += T)
+                if (d.m[uq[k]] >= a.planet_mass && atomicAdd(&pc[lab[root[k]]], 1) >= 1) s_whole = 1;
+            __syncthreads();
+            if (s_whole) {
+                if (t == 0) {
+                    base_set = (int)atomicAdd(&d.ctr[C_NSETS], 1ull);
+                    base_mem = (int)atomicAdd(&d.ctr[C_NU], (unsigned long long)nsb);
+                }
+                __syncthreads();
+                const int bs = base_set, bm = base_mem;
+                for (int k = t; k < nsb; k += T) d.set_mem[bm + k] = so + k;
+                if (t == 0) {
+                    d.set_start[bs] = bm;
+                    d.set_count[bs] = nsb;
+                    d.set_rc[bs] = INFINITY;
+                    if (nsb <= kWaveMax)
+                        d.set_list[(int)atomicAdd(&d.ctr[C_NSMALL], 1ull)] = bs;
+                    else
+                        d.set_list[d.setcap - 1 - (int)atomicAdd(&d.ctr[C_NBIG], 1ull)] = bs;
+                    atomicMax(&d.ctr[C_MAXSET], (unsigned long long)nsb);
+                    atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
+                    atomicAdd(&d.ctr[C_WHOLE], 1ull);
+                    atomicAdd(&d.ctr[C_TBIGSYS], 1ull);
+                }
+                __syncthreads();
+                continue;
+            }
+        }
+        // members sorted by (root rank, rank)
+        const int u2 = (int)gs_pow2(nu);
+        for (int k = t; k < u2; k += T)
+            key[k] = k < nu ? (((unsigned long long)root[k] << 32) | (unsigned)k) : ~0ull;
+        __syncthreads();
+        for (int kk = 2; kk <= u2; kk <<= 1)
+            for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int i = t; i < u2; i += T) {
+                    const int ixj = i ^ jj;
+                    if (ixj > i) {
+                        const unsigned long long x = key[i], y = key[ixj];
+                        const bool asc = (i & kk) == 0;
+                        if ((x > y) == asc) {
+                            key[i] = y;
+                            key[ixj] = x;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        if (t == 0) {
+            base_set = (int)atomicAdd(&d.ctr[C_NSETS], (unsigned long long)nsets);
+            base_mem = (int)atomicAdd(&d.ctr[C_NU], (unsigned long long)nu);
+        }
+        __syncthreads();
+        const int bs = base_set, bm = base_mem;
+        int *ls = root;   // local start of each set (the roots now ride in the keys)
+        for (int k = t; k < nu; k += T) {
+            const unsigned long long kv = key[k];
+            const int rt = (int)(kv >> 32);
+            d.set_mem[bm + k] = uq[(int)(kv & 0xffffffffull)];
+            if (k == 0 || (int)(key[k - 1] >> 32) != rt) {
+                const int sid = lab[rt];
+                d.set_start[bs + sid] = bm + k;
+                ls[sid] = k;
+            }
+        }
+        __syncthreads();
+        // r_crit = a_H max_{i in S} h_i a_i: maxima of the bit patterns
+        // (non-negative doubles order as integers), in the space of uq
+        unsigned long long *rcb = reinterpret_cast<unsigned long long *>(uq);
+        for (int k = t; k < nsets; k += T) rcb[k] = 0ull;
+        __syncthreads();
+        for (int k = t; k < nu; k += T) {
+            const int i = d.set_mem[bm + k];
+            const double rh = d.h[i] * d.A[i];
+            atomicMax(&rcb[lab[(int)(key[k] >> 32)]], (unsigned long long)__double_as_longlong(rh));
+        }
+        __syncthreads();
+        // set sizes and the Hermite work lists (small sets from the front,
+        // larger ones from the back), places from two scans
+        int *smallf = lab;                                // root ids are done with
+        int *bigf = reinterpret_cast<int *>(key);         // so are the keys
+        int big = 0;
+        for (int sid = t; sid < nsets; sid += T) {
+            const unsigned long long rb =
+                __hip_atomic_load(&rcb[sid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            d.set_rc[bs + sid] = a.aH * __longlong_as_double((long long)rb);
+            const int n = (sid + 1 < nsets ? ls[sid + 1] : nu) - ls[sid];
+            d.set_count[bs + sid] = n;
+            big = max(big, n);
+            smallf[sid] = n <= kWaveMax ? 1 : 0;
+            bigf[sid] = n <= kWaveMax ? 0 : 1;
+        }
+        __syncthreads();
+        const int nsm = block_scan_excl(smallf, nsets, tmp);
+        const int nbg = block_scan_excl(bigf, nsets, tmp);
+        if (t == 0) {
+            base_set = (int)atomicAdd(&d.ctr[C_NSMALL], (unsigned long long)nsm);
+            base_mem = (int)atomicAdd(&d.ctr[C_NBIG], (unsigned long long)nbg);
+        }
+        __syncthreads();
+        for (int sid = t; sid < nsets; sid += T) {
+            const int n = (sid + 1 < nsets ? ls[sid + 1] : nu) - ls[sid];
+            if (n <= kWaveMax)
+                d.set_list[base_set + smallf[sid]] = bs + sid;
+            else
+                d.set_list[d.setcap - 1 - (base_mem + bigf[sid])] = bs + sid;
+        }
+        if (big) atomicMax(&d.ctr[C_MAXSET], (unsigned long long)big);
+        if (t == 0) {
+            atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
+            atomicAdd(&d.ctr[C_TBIGSYS], 1ull);
+        }
+        __syncthreads();   // the LDS words serve the next system
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -2044,6 +2355,7 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
     __shared__ double lds[kHermThreads / 64];
     const int t = threadIdx.x;
     const int nwg = gridDim.x, wpb = kHermThreads / 64;
+    if (d.ctr[C_STATUS] & S_FREEZE) return;   // a step left undone
     const int nbig = (int)d.ctr[C_NBIG];
     // Sets are assigned statically, with no work-queue counter: thousands
     // of atomics on one counter congest its L2 channel, and every wave with
@@ -2181,6 +2493,8 @@ __global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
     const long long fs = d.memcap;
     unsigned phase = 0;
     int par = 0;
+    // every block reads the same status word (no kernel raises it meanwhile)
+    if (d.ctr[C_STATUS] & S_FREEZE) return;
     const int nbig = (int)d.ctr[C_NBIG];
     for (int q = 0; q < nbig; ++q) {
         const int sidx = d.set_list[d.setcap - 1 - q];

@@ -45,7 +45,8 @@ class Stats(C.Structure):
                 ("kepler_iters", C.c_int64), ("kepler_max", C.c_int64),
                 ("kepler_hist", C.c_int64 * 32), ("status", C.c_int64),
                 ("phase_us", C.c_double * 12), ("phase_calls", C.c_int64 * 12),
-                ("whole_system", C.c_int64)]
+                ("whole_system", C.c_int64), ("fallbacks", C.c_int64), ("overflows", C.c_int64),
+                ("global_sets", C.c_int64), ("kepler_restarts", C.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -94,6 +95,7 @@ SIGNATURES = {
     "qsym_sync": (C.c_int, [C.c_void_p]),
     "qsym_energy": (C.c_int, [C.c_void_p, _dp]),
     "qsym_encounters": (C.c_int, [C.c_void_p, _ip, C.c_int64, _lp, _ip]),
+    "qsym_set_rcrit": (C.c_int, [C.c_void_p, _dp, C.c_int64, _lp]),
     "qsym_candidates": (C.c_int, [C.c_void_p, _ip, C.c_int64, _lp]),
     "qsym_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "qsym_last_error": (C.c_char_p, [C.c_void_p]),
@@ -264,9 +266,13 @@ class Context:
         self._c(lib().qsym_set_state(self.ctx, m.data_ptr(), h.data_ptr(), q.data_ptr(),
                                      v.data_ptr(), QSYM_DEVICE))
 
-    def get_state(self):
+    def get_state(self, check=True):
+        """Positions and velocities (n, 3).  check=False returns them even when
+        the device status reports an error (they are copied first)."""
         qs = np.empty((3, self.n)); vs = np.empty((3, self.n))
-        self._c(lib().qsym_get_state(self.ctx, qs.ctypes.data, vs.ctypes.data, QSYM_HOST))
+        rc = lib().qsym_get_state(self.ctx, qs.ctypes.data, vs.ctypes.data, QSYM_HOST)
+        if check or rc in (-1, -3):
+            self._c(rc)
         return qs.T.copy(), vs.T.copy()
 
     # ------------------------------------------------------------- steps
@@ -285,13 +291,25 @@ class Context:
         self._c(lib().qsym_energy(self.ctx, E.ctypes.data_as(_dp)))
         return E
 
-    def encounters(self, cap: int = 1 << 16):
+    def encounters(self, cap: int | None = None):
+        """Encounter pairs of the last step (sorted) and each body's set id."""
+        if cap is None:
+            cap = max(int(self.stats()["n_encounters"]), 1)
         pairs = np.zeros((cap, 2), np.int32)
         n = C.c_int64()
         sid = np.zeros(self.n, np.int32)
         self._c(lib().qsym_encounters(self.ctx, pairs.ctypes.data_as(_ip), cap, C.byref(n),
                                       sid.ctypes.data_as(_ip)))
         return pairs[: n.value].copy(), sid
+
+    def set_rcrit(self) -> np.ndarray:
+        """r_crit of each encounter set of the last step, sets numbered by
+        their smallest member (as encounters() numbers them)."""
+        n = C.c_int64()
+        cap = max(int(self.stats()["n_sets"]), 1)
+        out = np.zeros(cap)
+        self._c(lib().qsym_set_rcrit(self.ctx, out.ctypes.data_as(_dp), cap, C.byref(n)))
+        return out[: n.value].copy()
 
     def candidates(self, cap: int | None = None):
         cap = cap if cap is not None else 8 * self.n + 1024

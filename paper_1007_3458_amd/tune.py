@@ -45,10 +45,8 @@ def main():
     ap.add_argument("--tau", type=float, default=0.05)
     ap.add_argument("--copy-to", default=None)
     args = ap.parse_args()
-    import sys
-    sys.path.insert(0, os.path.dirname(HERE))
-    from bench import workload  # the benchmark's workload definitions
     from paper_1007_3458_amd import qsym
+    from paper_1007_3458_amd.workloads import workload
     systems, _ = workload(args.workload)
     ctx = qsym.Context(systems, precision=args.precision, shapes=None)
     us = ctx.autotune(args.tau)

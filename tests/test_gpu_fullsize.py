@@ -113,6 +113,138 @@ def test_disk128k_step_conserves_angular_momentum(Q, disk128k):
     assert abs(E1 / E0 - 1.0) < 1e-9
 
 
+@pytest.fixture(scope="module")
+def disk128k_oracle_step(orc, disk128k):
+    """The oracle's hybrid step of the 131076-body disk (all host cores)."""
+    s = disk128k
+    say("oracle step of disk128k (host cores: %d)" % orc.num_threads())
+    return orc.step(orc.make_params(), 0.05, s.m, s.h, s.q, s.v)
+
+
+def _sid_from_labels(label):
+    roots = sorted({int(x) for x in label if x >= 0})
+    rank = {r: k for k, r in enumerate(roots)}
+    return np.array([rank[int(x)] if x >= 0 else -1 for x in label], np.int32)
+
+
+def test_disk128k_step_lockstep(Q, disk128k, disk128k_oracle_step):
+    """One whole hybrid step of the 131076-body disk in the benchmark's launch
+    configuration against the oracle's: every position and velocity to
+    1e-12, the encounter list, set ids and r_crit exact."""
+    s = disk128k
+    qo, vo, r = disk128k_oracle_step
+    say("disk128k lockstep", s.n, len(r.pairs), "pairs")
+    ctx = Q.Context(s)
+    ctx.step(0.05, 1)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    pg, sid = ctx.encounters()
+    rc = ctx.set_rcrit()
+    st = ctx.stats()
+    ctx.close()
+    assert r.rc == 0 and st["status"] == 0 and len(r.pairs) > 1000
+    assert np.array_equal(pg, r.pairs)
+    assert np.array_equal(sid, _sid_from_labels(r.label))
+    assert np.array_equal(rc, r.rcrit)
+    assert per_body_rel(qg, qo) < 1e-12
+    assert per_body_rel(vg, vo) < 1e-12
+
+
+def test_disk128k_fp32_form_step(Q, orc, disk128k, disk128k_oracle_step):
+    """The FP32 form's step of the same disk: within the form's bounds of the
+    FP64 oracle step, and the FP64 encounter list but for pairs within the
+    form's error of the threshold."""
+    s = disk128k
+    qo, vo, r = disk128k_oracle_step
+    say("disk128k fp32 form step", s.n)
+    ctx = Q.Context(s, precision=1)
+    ctx.step(0.05, 1)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    pg, _ = ctx.encounters()
+    ctx.close()
+    assert per_body_rel(qg, qo) < 1e-9 and per_body_rel(vg, vo) < 1e-7
+    eg, eo = {tuple(x) for x in pg}, {tuple(x) for x in r.pairs}
+    diff = np.array(sorted(eg ^ eo), np.int32).reshape(-1, 2)
+    say("  %d pairs, %d differ" % (len(eo), len(diff)))
+    assert len(diff) <= max(3, len(eo) // 100)
+    if len(diff):
+        po = orc.make_params()
+        q0 = orc.drift(s.m0, s.m, s.q, s.v, 0.025)
+        A, _ = orc.prepass(1.0, q0, s.v)
+        # v0 of the differing pairs' bodies only: their accelerations over all bodies
+        rows = np.unique(diff.ravel())
+        v0 = s.v.copy()
+        v0[rows] += 0.025 * orc.accel_rows(s.G, s.m, q0, rows)
+        q1, v1, _, _ = orc.kepler(1.0, q0[rows], v0[rows], 0.05, 0)
+        loc = {int(b): k for k, b in enumerate(rows)}
+        dl = np.array([[loc[int(a)], loc[int(b)]] for a, b in diff], np.int32)
+        _, lhs, rhs = orc.fine(po, 0.05, dl, s.m[rows], s.h[rows], A[rows], q0[rows], v0[rows], q1,
+                               v1)
+        assert np.all(np.abs(lhs / rhs - 1.0) < 1e-5), lhs / rhs
+
+
+def test_disk128k_runs_its_100_steps(Q, disk128k):
+    """The precision form's workload for its stated 100 steps (FP64): a clean
+    status, no step left undone, energy error at the integrator's level."""
+    s = disk128k
+    say("disk128k 100 steps")
+    ctx = Q.Context(s)
+    E0 = ctx.energy()[0]
+    for k in range(10):
+        ctx.step(0.05, 10)
+        ctx.sync()
+        st = ctx.stats()
+        say("  after %d steps: %d pairs, largest set %d" % (10 * (k + 1), st["n_encounters"],
+                                                            st["max_set"]))
+    E1 = ctx.energy()[0]
+    st = ctx.stats()
+    ctx.close()
+    assert st["status"] == 0 and st["steps"] == 100 and st["overflows"] == 0
+    assert abs(E1 / E0 - 1.0) < 1e-9
+
+
+def test_batch_step_per_system(Q, orc):
+    """One hybrid step of the 512-system batch (launch shapes of the benchmark):
+    20 systems -- the largest, every system with a set above 256 members (the
+    grid Hermite), and seeded others -- each equal to its own oracle step:
+    positions and velocities to 1e-12, encounter pairs exact."""
+    systems = inputs.batch()
+    say("batch step", len(systems))
+    ctx = Q.Context(systems)
+    ctx.step(0.05, 1)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    pg, sid = ctx.encounters()
+    st = ctx.stats()
+    off = ctx.offsets
+    ctx.close()
+    assert st["status"] == 0
+    sizes = np.array([b.n for b in systems])
+    pick = {int(np.argmax(sizes))}
+    for k in range(len(systems)):
+        ids = sid[off[k]:off[k + 1]]
+        ids = ids[ids >= 0]
+        if len(ids) and np.bincount(ids - ids.min()).max() > 256:
+            pick.add(k)
+    say("  systems with a set above 256 members:", sorted(pick))
+    rng = np.random.Generator(np.random.PCG64(17))
+    for k in rng.permutation(len(systems)):
+        if len(pick) >= 20:
+            break
+        pick.add(int(k))
+    p = orc.make_params()
+    for k in sorted(pick):
+        b = systems[k]
+        qo, vo, r = orc.step(p, 0.05, b.m, b.h, b.q, b.v)
+        sl = slice(off[k], off[k + 1])
+        assert r.rc == 0
+        assert per_body_rel(qg[sl], qo) < 1e-12, k
+        assert per_body_rel(vg[sl], vo) < 1e-12, k
+        mine = pg[(pg[:, 0] >= off[k]) & (pg[:, 0] < off[k + 1])] - off[k]
+        assert np.array_equal(mine, r.pairs), k
+
+
 def test_batch_kick_sampled(Q, orc):
     """FP64 kick of the 512-system batch (551,375 bodies, tuned shape): the
     first, middle and last body of every system."""

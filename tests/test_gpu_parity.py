@@ -198,6 +198,9 @@ def _lockstep(Q, orc, s, nsteps, tau=0.05, **kw):
         want = np.array([roots.index(x) if x >= 0 else -1 for x in lab])
         if not border:
             assert np.array_equal(sid, want)
+            # r_crit of every set (Sec. 2.2): the same operations on the same
+            # inputs, so the same bits
+            assert np.array_equal(ctx.set_rcrit(), r.rcrit), (k, ctx.set_rcrit(), r.rcrit)
         q, v = qo, vo
     ctx.close()
     return tot_enc, border
@@ -240,14 +243,17 @@ def test_full_size_step_disk16k(Q, orc):
     ctx.step(0.05, 1)
     ctx.sync()
     qg, vg = ctx.get_state()
-    pg, _ = ctx.encounters()
+    pg, sid = ctx.encounters()
     qo, vo, r = orc.step(orc.make_params(), 0.05, s.m, s.h, s.q, s.v)
     assert per_body_rel(qg, qo) < 1e-12
     assert per_body_rel(vg, vo) < 1e-12
-    assert {tuple(x) for x in pg} == {tuple(x) for x in r.pairs}
+    assert np.array_equal(pg, r.pairs)
     st = ctx.stats()
     assert st["n_encounters"] == r.stats["n_encounters"] > 0
     assert st["n_sets"] == r.stats["n_sets"]
+    roots = sorted({x for x in r.label if x >= 0})
+    assert np.array_equal(sid, np.array([roots.index(x) if x >= 0 else -1 for x in r.label]))
+    assert np.array_equal(ctx.set_rcrit(), r.rcrit)
     ctx.close()
 
 
@@ -262,6 +268,8 @@ def test_batched_equals_single(Q, orc):
     E = ctx.energy()
     off = ctx.offsets
     p = orc.make_params()
+    pg, _ = ctx.encounters()
+    want = []
     for k, s in enumerate(systems):
         q, v = s.q, s.v
         for _ in range(3):
@@ -270,6 +278,10 @@ def test_batched_equals_single(Q, orc):
         assert per_body_rel(qg[sl], q) < 1e-12
         assert per_body_rel(vg[sl], v) < 1e-12
         assert abs(E[k] - orc.energy(s.G, s.m0, s.m, q, v)) <= 1e-12 * abs(E[k])
+        want += [(int(a) + off[k], int(b) + off[k]) for a, b in r.pairs]
+    # the last step's encounter pairs of every system, in global indices
+    assert len(want) > 0
+    assert np.array_equal(pg, np.array(sorted(want), np.int32).reshape(-1, 2))
     ctx.close()
 
 
@@ -310,14 +322,27 @@ def test_autotune_keeps_results(Q, orc):
     ctx.close()
 
 
-def test_candidate_overflow_is_reported(Q):
+def test_candidate_overflow_loses_no_encounter(Q, orc):
+    """A candidate list of 2 pairs: the sweep finds hundreds, the fine test
+    then runs over all pairs, and the step equals the oracle's (encounter
+    list, sets and r_crit exact) with a clean status."""
     s = crowded(300, 7)
-    say("overflow path")
+    say("candidate overflow path")
     ctx = Q.Context(s, pair_capacity=2)
     ctx.step(0.05, 1)
+    ctx.sync()
+    qg, vg = ctx.get_state()
+    pg, sid = ctx.encounters()
+    st = ctx.stats()
+    assert st["status"] == 0 and st["fallbacks"] == 1 and st["n_candidates"] > 2
     with pytest.raises(Q.QsymError) as e:
-        ctx.sync()
+        ctx.candidates(cap=10)   # the list itself was cut short
     assert e.value.code == -6
+    qo, vo, r = orc.step(orc.make_params(), 0.05, s.m, s.h, s.q, s.v)
+    assert r.rc == 0 and len(r.pairs) > 0
+    assert np.array_equal(pg, r.pairs)
+    assert per_body_rel(qg, qo) < 1e-12 and per_body_rel(vg, vo) < 1e-12
+    assert np.array_equal(ctx.set_rcrit(), r.rcrit)
     ctx.close()
 
 
@@ -447,8 +472,22 @@ def test_fp32_form_accuracy_and_step(Q, orc):
     ctx.sync()
     qg, vg = ctx.get_state()
     pg, _ = ctx.encounters()
-    qo, vo, r = orc.step(orc.make_params(), 0.05, s.m, s.h, s.q, s.v)
+    po = orc.make_params()
+    qo, vo, r = orc.step(po, 0.05, s.m, s.h, s.q, s.v)
     assert per_body_rel(qg, qo) < 1e-9 and per_body_rel(vg, vo) < 1e-7
+    # the encounter list is the FP64 one but for pairs within the FP32
+    # form's error of the threshold (Dm^3 vs T^6 M^2 within 1e-5)
+    eg, eo = {tuple(x) for x in pg}, {tuple(x) for x in r.pairs}
+    assert len(eo) > 0
+    diff = np.array(sorted(eg ^ eo), np.int32).reshape(-1, 2)
+    if len(diff):
+        q0 = orc.drift(s.m0, s.m, s.q, s.v, 0.025)
+        A, _ = orc.prepass(1.0, q0, s.v)
+        v0 = orc.kick(1.0, s.m, q0, s.v, 0.025)
+        q1, v1, _, _ = orc.kepler(1.0, q0, v0, 0.05, 0)
+        _, lhs, rhs = orc.fine(po, 0.05, diff, s.m, s.h, A, q0, v0, q1, v1)
+        assert np.all(np.abs(lhs / rhs - 1.0) < 1e-5), (diff, lhs / rhs)
+    print("fp32 form step: %d encounter pairs, %d within the FP32 margin differ" % (len(eo), len(diff)))
     ctx.close()
 
 
@@ -477,7 +516,7 @@ def _components(pairs, n):
     return want
 
 
-def test_sets_of_a_system_beyond_the_bitmap(Q):
+def test_sets_of_a_system_beyond_the_bitmap(Q, orc):
     """The set partition ranks the bodies in encounters through a bitmap of
     the system for up to 262144 bodies and by sorting beyond that.  A
     266004-body disk takes the sorting path: its sets must be the connected
@@ -495,6 +534,12 @@ def test_sets_of_a_system_beyond_the_bitmap(Q):
     assert 0 < len(pg) <= 4096
     assert st["n_sets"] == int(sid.max()) + 1
     assert np.array_equal(sid, _components(pg, s.n))
+    # the oracle's partition of the same pairs (labels = smallest member)
+    lab, ns = orc.sets(s.n, pg)
+    roots = sorted({int(x) for x in lab if x >= 0})
+    rank = {r: k for k, r in enumerate(roots)}
+    assert ns == st["n_sets"]
+    assert np.array_equal(sid, np.array([rank[int(x)] if x >= 0 else -1 for x in lab]))
     ctx.close()
 
 
