@@ -311,6 +311,23 @@ int qsym_guess_fit_scalers(qsym_guess_trainer *tr, const float *feat, int64_t ld
  * and then the stream is synchronised. */
 int qsym_guess_grad(qsym_guess_trainer *tr, const float *weights, const float *feat, int64_t ld,
                     int64_t n, float *grad, double *loss);
+/* qsym_guess_grad without allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving or training
+ * loops, harnesses that forbid it): no trainer; the partial sums of its
+ * waves and the loss accumulator live in a static device array of
+ * 1.28 MB that each GPU holds from the first call on it until the process
+ * ends.  weights (device, QSYM_GUESS_WEIGHTS floats), feat (device, rows of
+ * ld floats as for qsym_guess_grad) and grad (device [1249], output) belong
+ * to the caller; loss (host, may be NULL) receives L and then the stream is
+ * synchronised.  n must be 1 .. QSYM_GUESS_STATIC_MAX, else QSYM_EINVAL
+ * (message in qsym_last_error(NULL)).  Results are those of qsym_guess_grad
+ * with the same n (same kernels, same partial layout).  All calls on one GPU
+ * share its array: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  Enqueued on
+ * `stream`. */
+#define QSYM_GUESS_STATIC_MAX 16384
+int qsym_guess_grad_static(const float *weights, const float *feat, int64_t ld, int64_t n,
+                           float *grad, double *loss, void *stream);
 /* one Adam update (Kingma & Ba 2015, Alg. 1) of weights[0..1248] from grad */
 int qsym_guess_adam(qsym_guess_trainer *tr, float *weights, const float *grad, double lr,
                     double b1, double b2, double eps);

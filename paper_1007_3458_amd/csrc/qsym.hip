@@ -319,6 +319,13 @@ namespace {
 // message of the last failure that had no context to hold it (creation)
 thread_local std::string g_noctx_err;
 
+}  // namespace
+
+// the same, set from the context-free entry points of other files
+void qsym_noctx_error(const char *msg) { g_noctx_err = msg ? msg : ""; }
+
+namespace {
+
 
 int fail(qsym_ctx *c, int code, const std::string &msg)
 {

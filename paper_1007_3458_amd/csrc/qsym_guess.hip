@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "qsym_kepler.hpp"
@@ -387,6 +388,52 @@ bool bad_state_args(long long n, const void *st, const void *dt) { return n < 0 
 
 }  // namespace
 
+// ------------------------------------------------------------------------
+// Scratch of the allocation-free loss gradient (qsym_guess_grad_static):
+// the per-wave partial sums of up to kStaticParts waves (64 samples each)
+// and the loss accumulator, in one file-scope device array.  Every device
+// the library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress gives on that
+// device (the array's name is a host-side stand-in).
+// ------------------------------------------------------------------------
+constexpr int kStaticParts = QSYM_GUESS_STATIC_MAX / 64;
+constexpr size_t kStaticPartBytes = (size_t)kStaticParts * kGPart * sizeof(float);
+constexpr size_t kStaticScratchBytes = kStaticPartBytes + 256;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+void qsym_noctx_error(const char *msg);
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's scratch, looked up once per device (with
+// that device current) and kept
+int static_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        qsym_noctx_error("guess_grad_static: no current HIP device");
+        return QSYM_EHIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            qsym_noctx_error((std::string("guess_grad_static: hipGetSymbolAddress: ") +
+                              hipGetErrorString(e)).c_str());
+            return QSYM_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QSYM_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -524,6 +571,45 @@ int qsym_guess_grad(qsym_guess_trainer *tr, const float *weights, const float *f
     if (loss) {
         TCHK(tr, hipMemcpyAsync(loss, tr->loss, sizeof(double), hipMemcpyDeviceToHost, tr->stream));
         TCHK(tr, hipStreamSynchronize(tr->stream));
+    }
+    return QSYM_OK;
+}
+
+int qsym_guess_grad_static(const float *weights, const float *feat, int64_t ld, int64_t n,
+                           float *grad, double *loss, void *stream)
+{
+    if (n < 1 || n > QSYM_GUESS_STATIC_MAX || ld < n || !weights || !feat || !grad) {
+        qsym_noctx_error("guess_grad_static: need 1 <= n <= QSYM_GUESS_STATIC_MAX (16384), "
+                         "ld >= n and non-null weights, feat, grad");
+        return QSYM_EINVAL;
+    }
+    void *base = nullptr;
+    if (int rc = static_scratch(&base)) return rc;
+    float *part = (float *)base;
+    double *lacc = (double *)((char *)base + kStaticPartBytes);
+    hipStream_t st = (hipStream_t)stream;
+    // the same launches as qsym_guess_grad: one wave per 64 samples (every
+    // partial row is written whole), the loss accumulator cleared by a kernel
+    const int nparts = (int)((n + 63) / 64);
+    hipLaunchKernelGGL(k_guess_grad, dim3(nparts), dim3(64), 0, st, weights, feat, (long long)ld,
+                       (long long)n, part);
+    if (hipGetLastError() != hipSuccess) return QSYM_EHIP;
+    hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(256), 0, st, lacc, 1);
+    if (hipGetLastError() != hipSuccess) return QSYM_EHIP;
+    UpdateArgs a{};
+    a.gsrc = part;
+    a.nparts = nparts;
+    a.stride = kGPart;
+    a.gscale = 2.0 / (double)n;
+    a.lscale = 1.0 / (double)n;
+    a.gout = grad;
+    a.loss_acc = lacc;
+    hipLaunchKernelGGL(k_guess_update, dim3(grid_of(kGuessParams + 1, 256)), dim3(256), 0, st, a);
+    if (hipGetLastError() != hipSuccess) return QSYM_EHIP;
+    if (loss) {
+        if (hipMemcpyAsync(loss, lacc, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return QSYM_EHIP;
     }
     return QSYM_OK;
 }

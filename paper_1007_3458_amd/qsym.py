@@ -125,6 +125,8 @@ SIGNATURES = {
                                          C.c_void_p]),
     "qsym_guess_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
                                   C.c_void_p, _dp]),
+    "qsym_guess_grad_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
+                                         C.c_void_p, _dp, C.c_void_p]),
     "qsym_guess_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
                                   C.c_double, C.c_double]),
     "qsym_guess_train": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64,
@@ -483,6 +485,27 @@ def kepler_guess(mu, state, dt, weights, device="cuda:0"):
     if rc != 0:
         raise QsymError(rc, "qsym_kepler_guess failed")
     return x[:n]
+
+
+GUESS_STATIC_MAX = 16384
+
+
+def guess_grad_static(weights, feat, n=None, offset=0):
+    """The learned start's loss gradient without a trainer and without any
+    allocation by the library (its scratch is a static device array): returns
+    (dL/dw device [1249], L) over samples [offset, offset + n) of feat."""
+    torch = _torch()
+    n = feat.shape[1] - offset if n is None else n
+    g = torch.empty(GUESS_PARAMS, dtype=torch.float32, device=feat.device)
+    loss = C.c_double()
+    st = torch.cuda.current_stream(feat.device)
+    rc = lib().qsym_guess_grad_static(C.c_void_p(weights.data_ptr()),
+                                      C.c_void_p(feat.data_ptr() + 4 * offset), feat.shape[1], n,
+                                      C.c_void_p(g.data_ptr()), C.byref(loss),
+                                      C.c_void_p(st.cuda_stream))
+    if rc != 0:
+        raise QsymError(rc, lib().qsym_last_error(None).decode())
+    return g, loss.value
 
 
 class GuessTrainer:
