@@ -229,7 +229,11 @@ int qsym_fine_test(const qsym_params *p, double m0, double tau, int64_t n, const
  * block*ipl bodies per work item, jchunk a multiple of block*ipl; the
  * j-side partial sums need at most min(ceil(n/128), 128) slots, so a shape
  * whose i-ranges of sym*block*ipl bodies exceed that fails with
- * QSYM_EINVAL).  qsym_autotune times every candidate shape of both kicks on
+ * QSYM_EINVAL), or 16 for the symmetric kick over balanced rows: rows of
+ * block*ipl bodies, each cut along j into work items of equal pair count,
+ * as many items as the device holds resident workgroups of the kernel, so
+ * that all of them run in one round and finish together (jchunk unused
+ * beyond the checks; remap should be 0).  qsym_autotune times every candidate shape of both kicks on
  * the current state (without moving it), each launch followed by the
  * reduction of its partial sums, keeps the fastest, and writes those two
  * times (kick + reduction) in microseconds to us[0] (plain) and us[1]

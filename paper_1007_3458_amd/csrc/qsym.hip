@@ -25,12 +25,17 @@ enum Phase {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// sym: 0 full-matrix kick; 1, 2, 4, 8 symmetric kick with this many
+// i-blocks per work item over j-chunks of jchunk bodies; kSymRows symmetric
+// kick over balanced rows (see build_items)
+constexpr int kSymRows = 16;
+
 struct Shape {
     int ipl = 2;
     int block = 256;
     long long jchunk = 1024;
     int remap = 1;
-    int sym = 0;   // > 0: symmetric kick with this many i-blocks per work item
+    int sym = 0;
 };
 
 // workspace layout: byte offsets of every array
@@ -39,14 +44,17 @@ struct Layout {
     size_t off_sysoff = 0, off_sysm0 = 0, off_sysS = 0, off_syspoff = 0, off_sysc0 = 0;
     size_t off_bchunk = 0, off_kchunk = 0, off_items = 0, off_eitems = 0, off_syse0 = 0, off_cand = 0;
     size_t off_enc = 0, off_syseoff = 0, off_sysecnt = 0, off_setcount = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0, off_setlist = 0;
-    size_t off_bigsys = 0, off_sysgoff = 0, off_gsa = 0, off_bk = 0;
+    size_t off_bigsys = 0, off_sysgoff = 0, off_gsa = 0, off_bk = 0, off_krow = 0;
+    long long krow_cap = 1;    // rows of the balanced-row kick shape, per kick
     long long gsa_slots = 0;   // global set-partition scratch (64-bit slots)
     int nbigcap = 0;           // systems that may need it
     size_t off_gbar = 0, off_hpart = 0;
     size_t off_swcnt = 0, off_swslot = 0, off_swrec = 0, off_swlarge = 0, off_syssw = 0,
            off_swpart = 0;
     long long sw_nb = 1;       // grid-sweep buckets
-    size_t off_hw = 0, off_ctr = 0, off_kstat = 0, off_epart = 0, off_E = 0, off_guess = 0;
+    size_t off_hw = 0, off_ctr = 0, off_kstat = 0, off_E = 0, off_guess = 0;
+    size_t off_erec = 0, off_ewcol = 0, off_ewrec = 0, off_sysu0 = 0, off_sysr0 = 0;
+    int e_waves = 4;           // waves of k_energy_pairs (a multiple of 4)
     size_t total = 0;
     long long np = 0;          // padded body count
     long long acc_len = 0;     // doubles of kick partials
@@ -64,6 +72,8 @@ struct Layout {
 struct Tables {
     std::vector<int> sys_off, sys_S, sys_c0, sys_e0, sys_eoff;
     std::vector<long long> sys_poff, sys_goff;
+    std::vector<long long> sys_u0, e_wcol;   // energy units per system, columns per wave
+    std::vector<int> e_wrec, sys_r0;         // energy records per wave and per system
     std::vector<int4> bchunk, kchunk;
     std::vector<KickItem> eitems;
     std::vector<int> body_sys;
@@ -80,6 +90,23 @@ long long sys_enc_cap(long long n)
 {
     if (n <= 0) return 0;
     return std::min<long long>(kEncPerBody * n + 64, 1LL << 26);
+}
+
+// energy pair sum: units of 64 i x 64 j over each system's upper triangle,
+// 64 columns each; at least 8 units per wave where the work allows, at most
+// 4096 waves (16 per compute unit)
+long long energy_units(long long n)
+{
+    const long long nb = (n + 63) / 64;
+    return nb * (nb + 1) / 2;
+}
+
+int energy_waves(const std::vector<long long> &off)
+{
+    long long units = 0;
+    for (size_t s = 0; s + 1 < off.size(); ++s) units += energy_units(off[s + 1] - off[s]);
+    const long long w = std::max<long long>(1, std::min<long long>((units + 7) / 8, 4096));
+    return (int)((w + 3) / 4 * 4);
 }
 
 long long jchunk_min_for(const std::vector<long long> &off)
@@ -181,6 +208,9 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_sysgoff, (size_t)std::max(nsys, 1) * sizeof(long long));
     take(L.off_gsa, (size_t)L.gsa_slots * sizeof(unsigned long long));
     take(L.off_bk, 6 * (size_t)L.np * D);
+    L.krow_cap = 1;
+    for (int s = 0; s < nsys; ++s) L.krow_cap += (off[s + 1] - off[s] + 127) / 128;
+    take(L.off_krow, 2 * (size_t)L.krow_cap * sizeof(int));
     take(L.off_gbar, 4 * sizeof(unsigned));
     take(L.off_hpart, 2 * (size_t)kGridMax * D);
     take(L.off_hw, (size_t)HFIELDS * L.memcap * D);
@@ -197,7 +227,12 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_swpart, 3 * (size_t)L.nchunks * D);
     take(L.off_ctr, (size_t)C_COUNT * sizeof(unsigned long long));
     take(L.off_kstat, (size_t)kStatStripes * kStatStride * sizeof(unsigned long long));
-    take(L.off_epart, (size_t)L.n_eitems * D);
+    L.e_waves = energy_waves(off);
+    take(L.off_erec, (size_t)kERec * (L.e_waves + nsys) * D);
+    take(L.off_ewcol, (size_t)(L.e_waves + 1) * sizeof(long long));
+    take(L.off_ewrec, (size_t)L.e_waves * sizeof(int));
+    take(L.off_sysu0, (size_t)(nsys + 1) * sizeof(long long));
+    take(L.off_sysr0, (size_t)(nsys + 1) * sizeof(int));
     take(L.off_E, (size_t)std::max(nsys, 1) * D);
     take(L.off_guess, (size_t)(kGuessWeights + 5) * sizeof(float));
     L.total = align_up(o, 256);
@@ -254,6 +289,7 @@ Dev bind(char *base, const Layout &L)
     d.sys_goff = (long long *)(base + L.off_sysgoff);
     d.gsa = (unsigned long long *)(base + L.off_gsa);
     d.bk = (double *)(base + L.off_bk);
+    d.krow = (int *)(base + L.off_krow);
     d.sw_cnt = (int *)(base + L.off_swcnt);
     d.sw_slot = (int *)(base + L.off_swslot);
     d.sw_rec = (SweepRec *)(base + L.off_swrec);
@@ -268,7 +304,11 @@ Dev bind(char *base, const Layout &L)
     d.hw = (double *)(base + L.off_hw);
     d.ctr = (unsigned long long *)(base + L.off_ctr);
     d.kstat = (unsigned long long *)(base + L.off_kstat);
-    d.epart = (double *)(base + L.off_epart);
+    d.erec = (double *)(base + L.off_erec);
+    d.e_wcol = (long long *)(base + L.off_ewcol);
+    d.e_wrec = (int *)(base + L.off_ewrec);
+    d.sys_u0 = (long long *)(base + L.off_sysu0);
+    d.sys_r0 = (int *)(base + L.off_sysr0);
     d.E = (double *)(base + L.off_E);
     d.guess = (float *)(base + L.off_guess);
     return d;
@@ -309,6 +349,7 @@ struct qsym_ctx {
     long long phase_calls[kPhases] = {};
     bool guess_loaded = false;
     int grid_blocks = 256;   // workgroups of k_hermite_grid: the device's compute units
+    int cus = 256;           // the device's compute units
     int apply_parts = 1;     // threads per body of the partial-sum reduction (1 or 4)
     double tau_crude = 0.0;  // |tau| of the crude sweep being enqueued
     std::string err;
@@ -325,7 +366,6 @@ thread_local std::string g_noctx_err;
 void qsym_noctx_error(const char *msg) { g_noctx_err = msg ? msg : ""; }
 
 namespace {
-
 
 int fail(qsym_ctx *c, int code, const std::string &msg)
 {
@@ -414,19 +454,150 @@ void build_tables(qsym_ctx *c)
     }
     T.sys_c0[nsys] = (int)T.bchunk.size();
     T.sys_e0[nsys] = (int)T.eitems.size();
+    // energy schedule: every wave the same number of pair columns (64 per
+    // unit), and the records (one per wave and system it touches) in system
+    // order, so each system's records are one contiguous run
+    T.sys_u0.assign(nsys + 1, 0);
+    for (int s = 0; s < nsys; ++s) T.sys_u0[s + 1] = T.sys_u0[s] + energy_units(c->off[s + 1] - c->off[s]);
+    const int W = c->L.e_waves;
+    const long long Ctot = 64 * T.sys_u0[nsys];
+    T.e_wcol.assign(W + 1, 0);
+    for (int w = 0; w <= W; ++w) T.e_wcol[w] = (long long)((__int128)Ctot * w / W);
+    auto sys_of = [&](long long U) {   // system holding unit U (one with units)
+        return (int)(std::upper_bound(T.sys_u0.begin(), T.sys_u0.end(), U) - T.sys_u0.begin()) - 1;
+    };
+    T.e_wrec.assign(W, 0);
+    std::vector<int> r_first(nsys, -1);
+    int rec = 0;
+    for (int w = 0; w < W; ++w) {
+        T.e_wrec[w] = rec;
+        if (T.e_wcol[w] >= T.e_wcol[w + 1]) continue;
+        const int sa = sys_of(T.e_wcol[w] / 64), sb = sys_of((T.e_wcol[w + 1] - 1) / 64);
+        for (int s = sa; s <= sb; ++s) {
+            if (T.sys_u0[s + 1] == T.sys_u0[s]) continue;
+            if (r_first[s] < 0) r_first[s] = rec;
+            ++rec;
+        }
+    }
+    T.sys_r0.assign(nsys + 1, rec);
+    for (int s = nsys - 1; s >= 0; --s) T.sys_r0[s] = r_first[s] >= 0 ? r_first[s] : T.sys_r0[s + 1];
     if (T.bchunk.empty()) T.bchunk.push_back(make_int4(0, 0, 0, 0));
     if (T.kchunk.empty()) T.kchunk.push_back(make_int4(0, 0, 0, 0));
     if (T.eitems.empty()) T.eitems.push_back(KickItem{0, 0, 0, 0, 0, 0});
 }
 
+// pairs (i, j), i < j, of the rows' bodies [i0, i0 + ni) with j < j_end
+// (local indices; j_end >= i0)
+double row_area(long long i0, long long ni, long long j_end)
+{
+    const long long m = j_end - i0;
+    if (m <= ni) return 0.5 * (double)m * (double)(m - 1);
+    return 0.5 * (double)ni * (double)(ni - 1) + (double)ni * (double)(m - ni);
+}
+
+// the smallest j_end whose row_area reaches `target`
+long long row_end_for(long long i0, long long ni, double target)
+{
+    const double tri = 0.5 * (double)ni * (double)(ni - 1);
+    long long j;
+    if (target <= tri)
+        j = i0 + (long long)std::ceil(0.5 * (1.0 + std::sqrt(1.0 + 8.0 * target)));
+    else
+        j = i0 + ni + (long long)std::ceil((target - tri) / (double)ni);
+    while (j > i0 + 1 && row_area(i0, ni, j - 1) >= target) --j;
+    while (row_area(i0, ni, j) < target) ++j;
+    return j;
+}
+
+// Balanced rows (kSymRows): each system's upper triangle in rows of BI
+// bodies, each row cut along j into items of about equal pair count, so
+// that all items fit in one round of the `slots` resident workgroups and
+// finish together.  The first item of a row holds its diagonal block.
+// Item t of row r writes its i-side partials to slot t and its reactions
+// to slot KX + r (KX = the system's largest row item count); krow holds the
+// item count of every row.  Returns false when the items do not fit.
+bool build_rows(qsym_ctx *c, const Shape &sh, int slots, std::vector<KickItem> &items,
+                std::vector<int4> &sysK, std::vector<int> &krow, int krow_base)
+{
+    const long long BI = (long long)sh.block * sh.ipl;
+    // row item counts for a target item area A (at least one item per row,
+    // items at least 64 columns wide)
+    auto counts = [&](double A, std::vector<std::vector<int>> *out) {
+        long long tot = 0;
+        for (int s = 0; s < c->nsys; ++s) {
+            const long long n = nsys_bodies(c->off, s);
+            if (out) (*out)[s].clear();
+            // the partial-slot budget: KX i-side slots + one per row
+            const long long rows = (n + BI - 1) / BI;
+            const long long kcap = std::max<long long>(1, partial_slots(n, c->L.jchunk_min) - rows);
+            for (long long i0 = 0; i0 < n; i0 += BI) {
+                const long long ni = std::min(BI, n - i0);
+                const double area = row_area(i0, ni, n);
+                const long long kmax = std::min(kcap, std::max<long long>(1, (n - i0 - ni) / 64 + 1));
+                const long long k = std::min<long long>(kmax, std::max<long long>(1, (long long)std::ceil(area / A)));
+                tot += k;
+                if (out) (*out)[s].push_back((int)k);
+            }
+        }
+        return tot;
+    };
+    double P = 0.0;
+    for (int s = 0; s < c->nsys; ++s) {
+        const double n = (double)nsys_bodies(c->off, s);
+        P += 0.5 * n * (n - 1.0);
+    }
+    double lo = std::max(P / std::max(slots, 1), 1.0), hi = std::max(P, 1.0);
+    if (counts(lo, nullptr) > slots) {
+        for (int it = 0; it < 100; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (counts(mid, nullptr) > slots) lo = mid; else hi = mid;
+        }
+        lo = hi;
+    }
+    std::vector<std::vector<int>> K(c->nsys);
+    counts(lo, &K);
+    int kb = krow_base;
+    for (int s = 0; s < c->nsys; ++s) {
+        const long long n = nsys_bodies(c->off, s);
+        const long long o = c->off[s];
+        int KX = 0;
+        for (int k : K[s]) KX = std::max(KX, k);
+        sysK[s] = make_int4(KX, (int)BI, kb, 2);
+        int r = 0;
+        for (long long i0 = 0; i0 < n; i0 += BI, ++r) {
+            const long long ni = std::min(BI, n - i0);
+            const int k = K[s][r];
+            krow.push_back(k);
+            const double area = row_area(i0, ni, n);
+            long long ja = i0;
+            for (int t = 0; t < k; ++t) {
+                long long jb = t + 1 == k ? n : row_end_for(i0, ni, area * (t + 1) / k);
+                if (t == 0) jb = std::max(jb, i0 + ni);          // the whole diagonal block
+                jb = std::min(std::max(jb, ja + 1), n - (k - 1 - t));
+                items.push_back(KickItem{s, (int)(o + i0), (int)ni, (int)(o + ja), (int)(jb - ja), t,
+                                         KX + r});
+                ja = jb;
+            }
+        }
+        kb += r;
+    }
+    return true;
+}
+
 // kick work items for a launch shape; systems largest first, each system's
 // items j-chunk major (consecutive items share j data)
-int build_items(qsym_ctx *c, const Shape &sh, std::vector<KickItem> &items, std::vector<int4> &sysK)
+int build_items(qsym_ctx *c, const Shape &sh, std::vector<KickItem> &items, std::vector<int4> &sysK,
+                int slots, std::vector<int> &krow, int krow_base)
 {
     const long long BI = (long long)sh.block * sh.ipl;
     const long long JC = sh.jchunk;
     items.clear();
     sysK.assign(c->nsys, make_int4(0, 0, 0, 0));
+    krow.clear();
+    if (sh.sym == kSymRows) {
+        build_rows(c, sh, slots, items, sysK, krow, krow_base);
+        return (int)items.size();
+    }
     std::vector<int> order(c->nsys);
     for (int s = 0; s < c->nsys; ++s) order[s] = s;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -463,20 +634,38 @@ int build_items(qsym_ctx *c, const Shape &sh, std::vector<KickItem> &items, std:
     return (int)items.size();
 }
 
+int kick_occupancy(qsym_ctx *c, int which, const Shape &sh);
+
 int upload_shape(qsym_ctx *c, int which)
 {
     std::vector<KickItem> items;
     std::vector<int4> sysK;
-    const int n = build_items(c, c->shape[which], items, sysK);
+    std::vector<int> krow;
+    const Shape &sh = c->shape[which];
+    const int slots = sh.sym == kSymRows ? c->cus * kick_occupancy(c, which, sh) : 0;
+    const int krow_base = which * (int)c->L.krow_cap;
+    const int n = build_items(c, sh, items, sysK, slots, krow, krow_base);
     if ((long long)n > c->L.max_items)
         return fail(c, QSYM_EINVAL, "kick shape needs more work items than the workspace holds");
+    if ((long long)krow.size() > c->L.krow_cap)
+        return fail(c, QSYM_EINVAL, "kick shape has more rows than the workspace holds");
     for (int s = 0; s < c->nsys; ++s) {
         const long long ns = nsys_bodies(c->off, s);
+        if (sysK[s].w == 2) {
+            // balanced rows: KX i-side slots + one j-side slot per row
+            const long long rows = (ns + sysK[s].y - 1) / sysK[s].y;
+            if (sysK[s].x + rows > partial_slots(ns, c->L.jchunk_min))
+                return fail(c, QSYM_EINVAL, "balanced rows need more partial slots than the workspace holds");
+            continue;
+        }
         const long long Smax = (ns + c->L.jchunk_min - 1) / c->L.jchunk_min;
         const long long slots = sysK[s].x + (sysK[s].z > 0 ? (ns + sysK[s].z - 1) / sysK[s].z : 0);
         if (sysK[s].x > Smax || slots > partial_slots(ns, c->L.jchunk_min))
             return fail(c, QSYM_EINVAL, "j-chunk smaller than the workspace allows");
     }
+    if (!krow.empty())
+        HIPCHK(c, hipMemcpyAsync(c->d.krow + krow_base, krow.data(), sizeof(int) * krow.size(),
+                                 hipMemcpyHostToDevice, c->stream));
     c->nitems[which] = n;
     c->grid_kick[which] = std::max(8, (n + 7) / 8 * 8);
     if (n > 0)
@@ -541,6 +730,33 @@ hipError_t launch_kick(qsym_ctx *c, int mode, hipStream_t st)
     if (ipl == 1) return launch_kick_bs<128, 1>(c, mode, prec, st);
     if (ipl == 2) return launch_kick_bs<128, 2>(c, mode, prec, st);
     return launch_kick_bs<128, 4>(c, mode, prec, st);
+}
+
+// resident workgroups per compute unit of the kick kernel a shape launches
+template <int BS, int IPL>
+int occ_bs(int mode, int prec)
+{
+    int occ = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if constexpr (IPL <= 2) {
+        if (prec == 0) {
+            if (mode == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_kick_sym<BS, IPL, 0, 0>, BS, 0);
+            else if (mode == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_kick_sym<BS, IPL, 1, 0>, BS, 0);
+            else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_kick_sym<BS, IPL, 2, 0>, BS, 0);
+        } else {
+            if (mode == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_kick_sym<BS, IPL, 0, 1>, BS, 0);
+            else if (mode == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_kick_sym<BS, IPL, 1, 1>, BS, 0);
+            else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_kick_sym<BS, IPL, 2, 1>, BS, 0);
+        }
+    }
+    return (e == hipSuccess && occ > 0) ? occ : 1;
+}
+
+int kick_occupancy(qsym_ctx *c, int which, const Shape &sh)
+{
+    const int mode = which ? 1 + c->p.hill_mode : 0;
+    if (sh.block == 256) return sh.ipl == 1 ? occ_bs<256, 1>(mode, c->p.precision) : occ_bs<256, 2>(mode, c->p.precision);
+    return sh.ipl == 1 ? occ_bs<128, 1>(mode, c->p.precision) : occ_bs<128, 2>(mode, c->p.precision);
 }
 
 int nblocks_chunks(qsym_ctx *c) { return (int)c->T.bchunk.size(); }
@@ -892,6 +1108,7 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return bail(QSYM_EHIP, "hipDeviceGetAttribute");
         c->grid_blocks = std::max(1, std::min(cus, kGridMax));
+        c->cus = std::max(1, cus);
     }
     if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess)
         return bail(QSYM_EHIP, "hipEventCreateWithFlags");
@@ -923,7 +1140,14 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.sys_goff, T.sys_goff.data(), sizeof(long long) * nsys,
                          hipMemcpyHostToDevice, st) == hipSuccess;
-
+    ok &= hipMemcpyAsync(c->d.sys_u0, T.sys_u0.data(), sizeof(long long) * T.sys_u0.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.e_wcol, T.e_wcol.data(), sizeof(long long) * T.e_wcol.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.e_wrec, T.e_wrec.data(), sizeof(int) * T.e_wrec.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.sys_r0, T.sys_r0.data(), sizeof(int) * T.sys_r0.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.bchunk, T.bchunk.data(), sizeof(int4) * T.bchunk.size(),
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.kchunk, T.kchunk.data(), sizeof(int4) * T.kchunk.size(),
@@ -1062,9 +1286,9 @@ int qsym_energy(qsym_ctx *c, double *E)
     hipStream_t st = c->stream;
     {
         Timer tm(c, P_ENERGY);
-        hipLaunchKernelGGL(k_energy_pairs, dim3((unsigned)c->T.eitems.size()), dim3(256), 0, st, c->d);
+        EnergyArgs ea{c->d, c->p.G, c->nsys};
+        hipLaunchKernelGGL(k_energy_pairs, dim3((unsigned)(c->L.e_waves / 4)), dim3(256), 0, st, ea);
         HIPCHK(c, hipGetLastError());
-        EnergyArgs ea{c->d, c->p.G};
         hipLaunchKernelGGL(k_energy_final, dim3(c->nsys), dim3(256), 0, st, ea);
         HIPCHK(c, hipGetLastError());
     }
@@ -1292,7 +1516,7 @@ int qsym_set_kick_shape(qsym_ctx *c, int32_t which, int32_t ipl, int32_t block, 
     if ((which < -1 || which > 1) || (ipl != 1 && ipl != 2 && ipl != 4) ||
         (block != 128 && block != 256) || jchunk <= 0 || jchunk % block ||
         jchunk < c->L.jchunk_min || (remap != 0 && remap != 1) ||
-        (sym != 0 && sym != 1 && sym != 2 && sym != 4 && sym != 8) ||
+        (sym != 0 && sym != 1 && sym != 2 && sym != 4 && sym != 8 && sym != kSymRows) ||
         (sym && (ipl > 2 || jchunk % ((long long)block * ipl))))
         return fail(c, QSYM_EINVAL, "kick shape out of range");
     for (int w = 0; w < 2; ++w) {
@@ -1358,6 +1582,13 @@ int qsym_autotune(qsym_ctx *c, double tau, double *us)
                             for (int rm = 0; rm < 2; ++rm)
                                 cand.push_back(Shape{ipls[ii], blocks[bi], jcs, rm, sy});
                 }
+        // balanced rows (the j-chunk plays no part: the smallest allowed)
+        for (int bi = 0; bi < 2; ++bi)
+            for (int ii = 0; ii < 2; ++ii) {
+                const long long BI = (long long)blocks[bi] * ipls[ii];
+                const long long jcs = (c->L.jchunk_min + BI - 1) / BI * BI;
+                cand.push_back(Shape{ipls[ii], blocks[bi], jcs, 0, kSymRows});
+            }
         for (const Shape &sh : cand) {
             c->shape[w] = sh;
             if (upload_shape(c, w) != QSYM_OK) continue;

@@ -128,6 +128,7 @@ struct Dev {
     long long *sys_goff;                        // [nsys] their scratch offset in gsa (-1: none)
     unsigned long long *gsa;                    // global set-partition scratch
     double *bk;                                 // [6][np] state at the start of the step
+    int *krow;                                  // [2][rows] items per row (balanced-row kick)
     unsigned *gbar;                             // grid barrier of k_hermite_grid (3 words)
     double *hpart;                              // [2][kGridMax] its per-block step minima
     int *sw_cnt;                                // grid sweep: [sw_nb] bucket counts
@@ -141,7 +142,11 @@ struct Dev {
     double *hw;                                 // Hermite member scratch
     unsigned long long *ctr;                    // counters and status
     unsigned long long *kstat;                  // [kStatStripes][kStatStride] Kepler statistics
-    double *epart;                              // energy partials per item
+    double *erec;                               // energy records [record][6] (k_energy_pairs)
+    long long *e_wcol;                          // [waves+1] first pair column of each wave
+    int *e_wrec;                                // [waves] first record of each wave
+    long long *sys_u0;                          // [nsys+1] first energy unit of each system
+    int *sys_r0;                                // [nsys+1] first energy record of each system
     double *E;                                  // energies per system
     float *guess;                               // learned Kepler start: weights + scalers
 };

@@ -870,6 +870,23 @@ __device__ __forceinline__ void sum_partials(const Dev &d, const int4 *sysK, int
     const int4 K = sysK[s];
     const double *p = d.acc + d.sys_poff[s] + il;
     double ax = 0.0, ay = 0.0, az = 0.0;
+    if (K.w == 2) {
+        // balanced rows (K = {KX, BI, row table, 2}): the i-side slots of
+        // the items of il's row, then the reaction slots of the rows up to
+        // and including its own
+        const int r = il / K.y;
+        const int kr = d.krow[K.z + r];
+        for (int q = part; q < kr + r + 1; q += P) {
+            const long long sl = q < kr ? q : K.x + (q - kr);
+            ax += p[(3 * sl) * ns];
+            ay += p[(3 * sl + 1) * ns];
+            az += p[(3 * sl + 2) * ns];
+        }
+        a[0] = ax;
+        a[1] = ay;
+        a[2] = az;
+        return;
+    }
     int c0 = 0, c1 = K.x, r1 = 0;
     if (K.z > 0) {
         const int cx = il / K.y;
@@ -2679,68 +2696,198 @@ __global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
 // Energy (Sec. 2, H = H_Dft + H_Kep + H_Int): pair potentials over i < j
 // per work item, then per system the O(N) terms and a fixed-order sum.
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_energy_pairs(Dev d)
-{
-    __shared__ double lds[256];
-    __shared__ double4 sj[256];
-    const KickItem it = d.eitems[blockIdx.x];
-    const int t = threadIdx.x;
-    const int i = it.i0 + t;
-    const bool ok = t < it.ni;
-    const double xi = ok ? d.x[i] : 0.0, yi = ok ? d.y[i] : 0.0, zi = ok ? d.z[i] : 0.0;
-    const double mi = ok ? d.m[i] : 0.0;
-    double s = 0.0;
-    const int jend = it.j0 + it.nj;
-    for (int jt = it.j0; jt < jend; jt += 256) {
-        const int j = jt + t;
-        __syncthreads();
-        sj[t] = (j < jend) ? make_double4(d.x[j], d.y[j], d.z[j], d.m[j]) : make_double4(0, 0, 0, 0);
-        __syncthreads();
-        const int nj = min(256, jend - jt);
-        if (jt + nj - 1 <= it.i0) continue;   // all j <= every i of this item
-        for (int jj = 0; jj < nj; ++jj) {
-            const double4 pj = sj[jj];
-            const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
-            const double r = sqrt(dx * dx + dy * dy + dz * dz);
-            if (jt + jj > i && r > 0.0) s += pj.w / r;
-        }
-    }
-    const double tot = block_sum<256>(mi * s, lds);
-    if (t == 0) d.epart[blockIdx.x] = tot;
-}
+// ------------------------------------------------------------------------
+// Energy (Sec. 2: H = H_Dft + H_Kep + H_Int).  The pair sum takes every
+// pair i < j of a system once, m_j / r_ij with r^-1 from the hardware
+// reciprocal square root refined by the binomial series of (1 - e)^(-1/2),
+// e = 1 - r^2 y0^2 (exact to FP64 rounding, as the kick's r^-3).  The
+// pairs are cut into units of 64 i (one per lane) x 64 j (staged in the
+// wave's own LDS slice, so no workgroup barrier) over the upper triangle of
+// every system, and the units' 64 columns are dealt to the waves in equal
+// contiguous ranges that may begin or end inside a unit: every wave gets
+// the same number of pair columns.  A wave adds its sums per system into a
+// record -- the kinetic, central-potential and momentum terms of the
+// bodies whose diagonal unit begins in its range, and the pair sum -- and
+// k_energy_final adds each system's records in order (deterministic).  A
+// coincident pair (r = 0, which the definition leaves out) makes a lane's
+// unit sum NaN through rsq(0) = inf: that lane sums the unit again with
+// every pair tested.
+// ------------------------------------------------------------------------
+constexpr int kERec = 6;            // kinetic, central potential, px, py, pz, pair sum
+constexpr double kFarI = -1e18;     // padding lanes: far apart from padding j (kFar)
 
 struct EnergyArgs {
     Dev d;
     double G;
+    int nsys;
 };
 
+// sum over the unit's columns [c0, c1) of m_j / r for the lane's i;
+// MASK: every pair tested (j > i on the diagonal unit, r > 0)
+template <bool MASK>
+__device__ __forceinline__ double energy_cols(const double *sx, const double *sy,
+                                              const double *sz, const double *sm, int c0, int c1,
+                                              double xi, double yi, double zi, int lane,
+                                              bool diag)
+{
+    double acc = 0.0;
+    if constexpr (!MASK) {
+#pragma unroll 8
+        for (int k = c0; k < c1; ++k) {
+            const double dx = sx[k] - xi, dy = sy[k] - yi, dz = sz[k] - zi;
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            const double y0 = __builtin_amdgcn_rsq(r2);
+            const double e = fma(-r2, y0 * y0, 1.0);
+            const double w = fma(e, fma(e, 0.375, 0.5), 1.0);
+            acc = fma(sm[k] * y0, w, acc);
+        }
+    } else {
+        for (int k = c0; k < c1; ++k) {
+            const double dx = sx[k] - xi, dy = sy[k] - yi, dz = sz[k] - zi;
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            const bool keep = r2 > 0.0 && (!diag || k > lane);
+            const double rk = keep ? r2 : 1.0;
+            const double y0 = __builtin_amdgcn_rsq(rk);
+            const double e = fma(-rk, y0 * y0, 1.0);
+            const double w = fma(e, fma(e, 0.375, 0.5), 1.0);
+            acc = fma(keep ? sm[k] * y0 : 0.0, w, acc);
+        }
+    }
+    return acc;
+}
+
+// sum over the wave, the same bits on every lane (lane 0's butterfly)
+__device__ __forceinline__ double wave_sum0(double v)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    return wave_uniform(v);
+}
+
+__global__ __launch_bounds__(256) void k_energy_pairs(EnergyArgs a)
+{
+    const Dev &d = a.d;
+    __shared__ double lds[4][4][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w = blockIdx.x * 4 + wv;
+    const long long C0 = d.e_wcol[w], C1 = d.e_wcol[w + 1];
+    if (C0 >= C1) return;   // (waves only; no workgroup barrier follows)
+    double *sx = lds[wv][0], *sy = lds[wv][1], *sz = lds[wv][2], *sm = lds[wv][3];
+    // the system and unit (b, t) of the first column: systems by binary
+    // search of their first units, (b, t) from the row starts
+    // S(b) = b nb - b (b - 1) / 2 of the system's upper triangle
+    long long U = C0 >> 6;
+    int lo = 0, hi = a.nsys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d.sys_u0[mid] <= U) lo = mid; else hi = mid - 1;
+    }
+    int s = lo;
+    while (d.sys_u0[s + 1] <= U) ++s;   // systems without units
+    int so = d.sys_off[s], n = d.sys_off[s + 1] - so, nb = (n + 63) >> 6;
+    const long long v = U - d.sys_u0[s];
+    int b = (int)((2.0 * nb + 1.0 - sqrt((2.0 * nb + 1.0) * (2.0 * nb + 1.0) - 8.0 * (double)v)) / 2.0);
+    b = max(0, min(b, nb - 1));
+    while (b > 0 && (long long)b * nb - (long long)b * (b - 1) / 2 > v) --b;
+    while (b + 1 < nb && (long long)(b + 1) * nb - (long long)(b + 1) * b / 2 <= v) ++b;
+    int t = b + (int)(v - ((long long)b * nb - (long long)b * (b - 1) / 2));
+    int rec = d.e_wrec[w];
+    double R[kERec] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const double G = a.G;
+    int cur_b = -1;
+    double xi = kFarI, yi = kFarI, zi = kFarI, mi = 0.0;
+    bool iok = false;
+    long long C = C0;
+    for (;;) {
+        const long long ubase = C & ~63LL;
+        const int c0 = (int)(C - ubase);
+        const int c1 = C1 - ubase < 64 ? (int)(C1 - ubase) : 64;
+        if (b != cur_b) {
+            const int i = so + 64 * b + lane;
+            iok = 64 * b + lane < n;
+            xi = iok ? d.x[i] : kFarI;
+            yi = iok ? d.y[i] : kFarI;
+            zi = iok ? d.z[i] : kFarI;
+            mi = iok ? d.m[i] : 0.0;
+            cur_b = b;
+        }
+        {
+            const int j = so + 64 * t + lane;
+            const bool jok = 64 * t + lane < n;
+            sx[lane] = jok ? d.x[j] : kFar;
+            sy[lane] = jok ? d.y[j] : kFar;
+            sz[lane] = jok ? d.z[j] : kFar;
+            sm[lane] = jok ? d.m[j] : 0.0;
+        }
+        wave_lds_sync();
+        const bool diag = t == b;
+        double acc;
+        if (diag) {
+            acc = energy_cols<true>(sx, sy, sz, sm, c0, c1, xi, yi, zi, lane, true);
+            if (c0 == 0 && iok) {
+                // the bodies of this i-block: kinetic, central and momentum
+                // terms (once: in the range holding the block's diagonal unit)
+                const int i = so + 64 * b + lane;
+                const double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
+                R[0] += 0.5 * mi * (vx * vx + vy * vy + vz * vz);
+                R[1] += G * d.sys_m0[s] * mi / dnorm3(xi, yi, zi);
+                R[2] += mi * vx;
+                R[3] += mi * vy;
+                R[4] += mi * vz;
+            }
+        } else {
+            acc = energy_cols<false>(sx, sy, sz, sm, c0, c1, xi, yi, zi, lane, false);
+            if (isnan(acc)) acc = energy_cols<true>(sx, sy, sz, sm, c0, c1, xi, yi, zi, lane, false);
+        }
+        R[5] = fma(mi, acc, R[5]);
+        wave_lds_sync();   // the slice is restaged for the next unit
+        C = ubase + c1;
+        if (C >= C1) break;
+        // next unit: the next tile of the row, the next row, the next system
+        if (++t == nb) {
+            if (++b == nb) {
+#pragma unroll
+                for (int k = 0; k < kERec; ++k) {
+                    const double r = wave_sum0(R[k]);
+                    if (lane == 0) d.erec[(long long)kERec * rec + k] = r;
+                    R[k] = 0.0;
+                }
+                ++rec;
+                do {
+                    ++s;
+                } while (d.sys_u0[s + 1] == d.sys_u0[s]);
+                so = d.sys_off[s];
+                n = d.sys_off[s + 1] - so;
+                nb = (n + 63) >> 6;
+                b = 0;
+                cur_b = -1;
+            }
+            t = b;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kERec; ++k) {
+        const double r = wave_sum0(R[k]);
+        if (lane == 0) d.erec[(long long)kERec * rec + k] = r;
+    }
+}
+
+// E of each system from its records, added in order
 __global__ __launch_bounds__(256) void k_energy_final(EnergyArgs a)
 {
     __shared__ double lds[256];
     const Dev &d = a.d;
     const int s = blockIdx.x;
-    const int i0 = d.sys_off[s], i1 = d.sys_off[s + 1];
     const double m0 = d.sys_m0[s];
-    double kin = 0.0, pot0 = 0.0, px = 0.0, py = 0.0, pz = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += 256) {
-        const double mi = d.m[i];
-        const double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
-        kin += 0.5 * mi * (vx * vx + vy * vy + vz * vz);
-        px += mi * vx;
-        py += mi * vy;
-        pz += mi * vz;
-        pot0 += a.G * m0 * mi / dnorm3(d.x[i], d.y[i], d.z[i]);
-    }
-    double pp = 0.0;
-    for (int e = d.sys_e0[s] + threadIdx.x; e < d.sys_e0[s + 1]; e += 256) pp += d.epart[e];
-    kin = block_sum<256>(kin, lds);
-    pot0 = block_sum<256>(pot0, lds);
-    px = block_sum<256>(px, lds);
-    py = block_sum<256>(py, lds);
-    pz = block_sum<256>(pz, lds);
-    pp = block_sum<256>(pp, lds);
+    double r[kERec] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int q = d.sys_r0[s] + threadIdx.x; q < d.sys_r0[s + 1]; q += 256)
+#pragma unroll
+        for (int k = 0; k < kERec; ++k) r[k] += d.erec[(long long)kERec * q + k];
+#pragma unroll
+    for (int k = 0; k < kERec; ++k) r[k] = block_sum<256>(r[k], lds);
     if (threadIdx.x == 0)
-        d.E[s] = kin + (px * px + py * py + pz * pz) / (2.0 * m0) - pot0 - a.G * pp;
+        d.E[s] = r[0] + (r[2] * r[2] + r[3] * r[3] + r[4] * r[4]) / (2.0 * m0) - r[1] - a.G * r[5];
 }
 
 

@@ -60,7 +60,11 @@ SHAPES = [dict(ipl=1, block=128, jchunk=128, remap=0), dict(ipl=2, block=256, jc
           dict(ipl=2, block=128, jchunk=256, remap=1, sym=2),
           dict(ipl=1, block=256, jchunk=1024, remap=1, sym=1),
           dict(ipl=2, block=256, jchunk=512, remap=0, sym=1),
-          dict(ipl=1, block=128, jchunk=512, remap=0, sym=4)]
+          dict(ipl=1, block=128, jchunk=512, remap=0, sym=4),
+          # balanced rows: every row cut along j into items of equal pair count
+          dict(ipl=1, block=256, jchunk=256, remap=0, sym=16),
+          dict(ipl=2, block=256, jchunk=512, remap=0, sym=16),
+          dict(ipl=1, block=128, jchunk=128, remap=0, sym=16)]
 
 
 @pytest.mark.parametrize("name", list(SYSTEMS))
@@ -232,6 +236,37 @@ def test_energy_parity(Q, orc):
         Eo = orc.energy(s.G, s.m0, s.m, s.q, s.v)
         assert abs(E - Eo) <= 1e-13 * abs(Eo)
         ctx.close()
+
+
+def test_energy_full_size_batch_and_coincident(Q, orc):
+    """The energy (Sec. 2, H) of the 16388-body disk and of a batch of uneven
+    systems (ragged pair tiles, systems of one and two bodies, an empty one)
+    to 1e-13; and of a system holding two coincident bodies, whose pair the
+    definition leaves out (r = 0), as the oracle does."""
+    s = inputs.disk16k()
+    say("energy disk16k")
+    ctx = Q.Context(s)
+    E = ctx.energy()[0]
+    ctx.close()
+    assert abs(E / orc.energy(s.G, s.m0, s.m, s.q, s.v) - 1.0) <= 1e-13
+    sizes = [64, 1, 300, 0, 2, 777, 65, 130]
+    systems = [inputs.batch_system(k, n) if n > 0 else inputs.System("empty", 1.0, 1.0,
+               np.zeros(0), np.zeros((0, 3)), np.zeros((0, 3))) for k, n in enumerate(sizes)]
+    say("energy batch", sizes)
+    ctx = Q.Context(systems)
+    E = ctx.energy()
+    ctx.close()
+    for k, b in enumerate(systems):
+        Eo = orc.energy(b.G, b.m0, b.m, b.q, b.v) if b.n else 0.0
+        assert abs(E[k] - Eo) <= 1e-13 * abs(Eo), (k, E[k], Eo)
+    c = crowded(300, 8).copy()
+    c.q[17] = c.q[201]
+    say("energy with a coincident pair")
+    ctx = Q.Context(c)
+    E = ctx.energy()[0]
+    ctx.close()
+    Eo = orc.energy(c.G, c.m0, c.m, c.q, c.v)
+    assert np.isfinite(E) and abs(E / Eo - 1.0) <= 1e-13
 
 
 def test_full_size_step_disk16k(Q, orc):
@@ -632,7 +667,7 @@ def test_set_larger_than_lds_stage(Q, orc):
     ctx.close()
 
 
-@pytest.mark.parametrize("sym", [1, 2])
+@pytest.mark.parametrize("sym", [1, 2, 16])
 def test_symmetric_kick_lockstep_steps(Q, orc, sym):
     """Whole hybrid steps with the symmetric kick for both kicks equal the
     oracle steps (the step never depends on the kick shape beyond rounding)."""
@@ -660,24 +695,28 @@ def test_symmetric_kick_full_size_and_batched(Q, orc):
     say("symmetric kick disk16k")
     s0 = s.copy()
     s0.v[:] = 0.0
-    ctx = Q.Context(s0)
-    ctx.set_kick_shape(2, 256, 1024, 1, sym=1)
-    ctx.apply_kick(1.0)
-    _, a = ctx.get_state()
     rows = np.arange(0, s.n, 97)
     ao = orc.accel_rows(s.G, s.m, s.q, rows)
-    assert per_body_rel(a[rows], ao) < 1e-13
-    ctx.close()
+    for sh in (dict(ipl=2, block=256, jchunk=1024, remap=1, sym=1),
+               dict(ipl=1, block=256, jchunk=512, remap=0, sym=16),
+               dict(ipl=2, block=256, jchunk=512, remap=0, sym=16)):
+        ctx = Q.Context(s0)
+        ctx.set_kick_shape(**sh)
+        ctx.apply_kick(1.0)
+        _, a = ctx.get_state()
+        assert per_body_rel(a[rows], ao) < 1e-13, sh
+        ctx.close()
     sizes = [64, 300, 1, 2, 777, 130]
     systems = [inputs.batch_system(k, n) for k, n in enumerate(sizes)]
     for b in systems:
         b.v[:] = 0.0
-    ctx = Q.Context(systems)
-    ctx.set_kick_shape(1, 128, 128, 0, sym=2)
-    ctx.apply_kick(1.0)
-    _, a = ctx.get_state()
-    off = ctx.offsets
-    for k, b in enumerate(systems):
-        sl = slice(off[k], off[k + 1])
-        assert per_body_rel(a[sl], orc.accel(b.G, b.m, b.q)) < 1e-13
-    ctx.close()
+    for sym in (2, 16):
+        ctx = Q.Context(systems)
+        ctx.set_kick_shape(1, 128, 128, 0, sym=sym)
+        ctx.apply_kick(1.0)
+        _, a = ctx.get_state()
+        off = ctx.offsets
+        for k, b in enumerate(systems):
+            sl = slice(off[k], off[k + 1])
+            assert per_body_rel(a[sl], orc.accel(b.G, b.m, b.q)) < 1e-13, (sym, k)
+        ctx.close()
