@@ -43,6 +43,7 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3     # MI355X FP32 vector
 FLOP_PAIR = 20               # per ordered pair (sub 3, r^2 5, rsqrt 2, m/r^3 4, fma 6)
 FLOP_CRUDE = 6               # per unordered pair (fused crude sweep)
+FLOP_ENERGY_PAIR = 12        # per pair potential (sub 3, r^2 5, rsqrt 2, m/r 2)
 
 
 def workload(name):
@@ -169,6 +170,8 @@ def timed_run(ctx, tau, steps, warmup, graph_pass, checkpoints=10, swapped=False
     for k, name in enumerate(qsym.PHASES):
         if st["phase_calls"][k] and name != "energy":
             kern[name] = st["phase_us"][k] / st["phase_calls"][k]
+    ke = qsym.PHASES.index("energy")
+    energy_us = st["phase_us"][ke] / st["phase_calls"][ke] if st["phase_calls"][ke] else None
     E1 = E
     graph_sps = None
     if graph_pass:
@@ -180,7 +183,7 @@ def timed_run(ctx, tau, steps, warmup, graph_pass, checkpoints=10, swapped=False
         graph_sps = steps / (time.perf_counter() - g0)
     st2 = ctx.stats()
     return {"T": T, "kern": kern, "E0": E0, "E1": E1, "dEmax": dEmax, "graph_sps": graph_sps,
-            "st": st, "st2": st2}
+            "st": st, "st2": st2, "energy_us": energy_us}
 
 
 def kick_accels(ctx, m, h, q, v):
@@ -448,6 +451,15 @@ def main():
         "kernel_avg_us": kern,
         "roofline": roof,
     }
+    if r["energy_us"]:
+        # the energy evaluation (between segments, outside the timed steps):
+        # N(N-1)/2 pair potentials of 12 flop each per system
+        ep = sum(float(s_.n) * (s_.n - 1) / 2 for s_ in systems)
+        out["energy_eval"] = {"avg_us": r["energy_us"], "pair_potentials": ep,
+                              "flop_per_pair": FLOP_ENERGY_PAIR,
+                              "achieved_tflops": ep * FLOP_ENERGY_PAIR / (r["energy_us"] * 1e-6) / 1e12,
+                              "frac_fp64_peak": ep * FLOP_ENERGY_PAIR / (r["energy_us"] * 1e-6) / 1e12
+                              / FP64_PEAK_TFLOPS}
     out.update(extra)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(systems, args.tau, args.cpu_seconds, args.swapped)

@@ -607,7 +607,7 @@ enum { SYM_FULL = 0, SYM_DIAG = 1, SYM_SKIP = 2 };
 // 64 rotation steps of one wave over one sub-tile; lane group u (i_u =
 // u-th i of the lane) meets it as M0 (u = 0) / M1 (u = 1).  s* point at
 // the doubled sub-tile (x, y, z, G m rows of 128).  Crude-sweep hits are
-// queued as (i - ib) << 16 | (j - jt).
+// queued as body pairs (ib + lt, jsub + j offset) in qi, qj.
 template <int MODE, int PREC, int IPL, int M0, int M1>
 __device__ __forceinline__ void sym_subtile(const double *sx, const double *sy, const double *sz,
                                             const double *sm, int lane, const double *xi,
@@ -615,7 +615,8 @@ __device__ __forceinline__ void sym_subtile(const double *sx, const double *sy, 
                                             const float *mif, const double *th2, const int *lt,
                                             double seed, double c158, double c32, double *ax,
                                             double *ay, double *az, double &fx, double &fy,
-                                            double &fz, unsigned *qbuf, unsigned *qn, int jsub)
+                                            double &fz, int *qi, int *qj, unsigned *qn, int ib,
+                                            int jsub)
 {
     // the crude test's queue pushes split the loop body into blocks, and a
     // deep unroll then keeps too many values live: unroll less with it
@@ -638,8 +639,10 @@ __device__ __forceinline__ void sym_subtile(const double *sx, const double *sy, 
             if constexpr (MODE != 0) {
                 if (keep && r2 < th2[u]) {
                     const unsigned q = atomicAdd(qn, 1u);
-                    if (q < (unsigned)kCrudeQ)
-                        qbuf[q] = ((unsigned)lt[u] << 16) | (unsigned)(jsub + ((lane + k) & 63));
+                    if (q < (unsigned)kCrudeQ) {
+                        qi[q] = ib + lt[u];
+                        qj[q] = jsub + ((lane + k) & 63);
+                    }
                 }
             }
         }
@@ -649,25 +652,45 @@ __device__ __forceinline__ void sym_subtile(const double *sx, const double *sy, 
     }
 }
 
-// exact crude test of the queued pairs of one tile (or, after a queue
-// overflow, of every pair of the tile with j > i)
-template <int BS, int IPL>
-__device__ void sym_drain(const KickArgs &ka, int ib, int jt, int jend, const int *iu,
-                          const bool *oku, const unsigned *qbuf, unsigned n)
+// The queued pairs of the item so far (absolute body indices, n <=
+// kCrudeQ): the exact crude test of the definition, the passing pairs
+// gathered in LDS and appended to the candidate list with one atomic for
+// the workgroup (a counter every workgroup hits once per flush, not once per
+// candidate).  Called by the whole workgroup.
+template <int BS>
+__device__ void sym_flush(const KickArgs &ka, const int *qi, const int *qj, unsigned n, int2 *cl,
+                          unsigned *cn, int *cbase)
 {
+    const Dev &d = ka.d;
     const int tid = threadIdx.x;
-    if (n <= (unsigned)kCrudeQ) {
-        for (unsigned e = tid; e < n; e += BS) {
-            const unsigned v = qbuf[e];
-            crude_exact(ka, ib + (int)(v >> 16), jt + (int)(v & 0xffffu));
+    for (unsigned e = tid; e < n; e += BS) {
+        const int i = qi[e], j = qj[e];
+        if (j > i && crude_pass(d, d.x, d.y, d.z, ka.hill_mode, ka.aE, ka.cs, ka.tau_abs, i, j)) {
+            const unsigned k = atomicAdd(cn, 1u);
+            cl[k] = make_int2(i, j);
         }
-    } else {
-        const int je = min(jt + BS, jend);
-#pragma unroll
-        for (int u = 0; u < IPL; ++u)
-            if (oku[u])
-                for (int j = jt; j < je; ++j) crude_exact(ka, iu[u], j);
     }
+    __syncthreads();
+    const unsigned c = *cn;
+    if (c) {
+        if (tid == 0) *cbase = (int)atomicAdd(&d.ctr[C_CAND], (unsigned long long)c);
+        __syncthreads();
+        const long long b0 = *cbase;
+        for (unsigned k = tid; k < c; k += BS)
+            if (b0 + k < ka.cap) d.cand[b0 + k] = cl[k];
+    }
+}
+
+// a tile whose hits overflowed the queue: the exact test of every pair of
+// the tile with j > i (appended one by one; rare)
+template <int BS, int IPL>
+__device__ void sym_tile_exact(const KickArgs &ka, int jt, int jend, const int *iu, const bool *oku)
+{
+    const int je = min(jt + BS, jend);
+#pragma unroll
+    for (int u = 0; u < IPL; ++u)
+        if (oku[u])
+            for (int j = jt; j < je; ++j) crude_exact(ka, iu[u], j);
 }
 
 template <int BS, int IPL, int MODE, int PREC>
@@ -689,8 +712,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
     __shared__ double tx[NW][128], ty[NW][128], tz[NW][128], tm[NW][128];
     __shared__ double wpart[NW][3][BS];
     __shared__ double smax[3][NW];
-    __shared__ unsigned qbuf[MODE ? kCrudeQ : 1];
-    __shared__ unsigned qn;
+    // crude sweep: pairs under the tile bound, queued over the tiles of the
+    // item (flushed when half full and at the item's end), and the pairs
+    // passing the exact test before their one append
+    __shared__ int qi[MODE ? kCrudeQ : 1], qj[MODE ? kCrudeQ : 1];
+    __shared__ int2 cl[MODE ? kCrudeQ : 1];
+    __shared__ unsigned qn, cn;
+    __shared__ int cbase;
 
     const int s = it.sys;
     const int so = d.sys_off[s];
@@ -708,9 +736,17 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
         rj[ns + it.j0 + k] = 0.0;
         rj[2 * ns + it.j0 + k] = 0.0;
     }
-    if (MODE && tid == 0) qn = 0u;
+    if (MODE && tid == 0) {
+        qn = 0u;
+        cn = 0u;
+    }
+    unsigned qstart = 0;   // queue entries left by earlier tiles of the item (uniform)
     const double G = ka.G;
-    const double seed = ka.r2seed, c158 = ka.c158, c32 = ka.c32;
+    const double seed = ka.r2seed, c158 = ka.c158;
+    // 3/2 in a vector register: the correction's inner fma would otherwise
+    // take two scalar operands and cost a move per pair
+    double c32;
+    asm volatile("v_mov_b64 %0, %1" : "=v"(c32) : "s"(ka.c32));
     for (int ib = it.i0; ib < it.i0 + it.ni; ib += BI) {
         const bool first_ib = ib == it.i0;
         const int nib = min(BI, it.i0 + it.ni - ib);
@@ -808,15 +844,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
                 } else if (rel >= 64 * IPL) {
                     sym_subtile<MODE, PREC, IPL, SYM_FULL, SYM_FULL>(
                         px, py, pz, pm, lane, xi, yi, zi, gmi, mif, th2, lt, seed, c158, c32, ax, ay,
-                        az, fx, fy, fz, qbuf, &qn, 64 * sub);
+                        az, fx, fy, fz, qi, qj, &qn, ib, jt + 64 * sub);
                 } else if (IPL == 2 && rel == 64) {
                     sym_subtile<MODE, PREC, IPL, SYM_FULL, SYM_DIAG>(
                         px, py, pz, pm, lane, xi, yi, zi, gmi, mif, th2, lt, seed, c158, c32, ax, ay,
-                        az, fx, fy, fz, qbuf, &qn, 64 * sub);
+                        az, fx, fy, fz, qi, qj, &qn, ib, jt + 64 * sub);
                 } else {   // rel == 0
                     sym_subtile<MODE, PREC, IPL, SYM_DIAG, SYM_SKIP>(
                         px, py, pz, pm, lane, xi, yi, zi, gmi, mif, th2, lt, seed, c158, c32, ax, ay,
-                        az, fx, fy, fz, qbuf, &qn, 64 * sub);
+                        az, fx, fy, fz, qi, qj, &qn, ib, jt + 64 * sub);
                 }
                 wpart[wv][0][64 * sub + lane] = fx;
                 wpart[wv][1][64 * sub + lane] = fy;
@@ -834,10 +870,25 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
                 }
             }
             if constexpr (MODE != 0) {
+                // qn is final (the barrier above follows every push)
                 const unsigned nq = qn;
-                if (nq) sym_drain<BS, IPL>(ka, ib, jt, jend, iu, oku, qbuf, nq);
-                __syncthreads();
-                if (tid == 0) qn = 0u;
+                unsigned keep = nq;
+                if (nq > (unsigned)kCrudeQ) {
+                    // this tile's pushes overflowed: drop them, test the tile
+                    sym_tile_exact<BS, IPL>(ka, jt, jend, iu, oku);
+                    keep = qstart;
+                }
+                const bool last = ib + BI >= it.i0 + it.ni && jt + BS >= jend;
+                if (keep > (unsigned)kCrudeQ / 2 || (last && keep > 0)) {
+                    sym_flush<BS>(ka, qi, qj, keep, cl, &cn, &cbase);
+                    keep = 0;
+                }
+                __syncthreads();   // every thread has read qn and cn
+                if (tid == 0) {
+                    qn = keep;
+                    cn = 0u;
+                }
+                qstart = keep;
             }
         }
         // forces on this i-block: i-side slot `chunk`
@@ -851,6 +902,11 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
                 d.acc[pb + 2 * ns + il] = az[u];
             }
         }
+    }
+    if constexpr (MODE != 0) {
+        // the last tile flushes the queue; an item whose last i-block met
+        // no tile would leave pairs here
+        if (qstart > 0) sym_flush<BS>(ka, qi, qj, qstart, cl, &cn, &cbase);
     }
 }
 
