@@ -51,15 +51,32 @@ __device__ __forceinline__ void latch(unsigned long long *ctr, unsigned long lon
     atomicOr(&ctr[C_STATUS], bits);
 }
 
-// Momentum of system s summed from its chunk partials in a fixed order.
-template <int BS>
-__device__ void system_momentum(const Dev &d, int s, double *lds, double P[3])
+// Momentum of system s summed from its chunk partials in a fixed order:
+// each wave on its own (lane-strided sums, then a butterfly whose lane-0
+// result every lane takes), so no workgroup barrier and the same bits in
+// every wave of every workgroup.
+__device__ void system_momentum(const Dev &d, int s, double P[3])
 {
     const int c0 = d.sys_c0[s], c1 = d.sys_c0[s + 1];
+    const int lane = threadIdx.x & 63;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int c = c0 + lane; c < c1; c += 64) {
+        a[0] += d.pm[3 * c];
+        a[1] += d.pm[3 * c + 1];
+        a[2] += d.pm[3 * c + 2];
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        a[0] += __shfl_xor(a[0], o, 64);
+        a[1] += __shfl_xor(a[1], o, 64);
+        a[2] += __shfl_xor(a[2], o, 64);
+    }
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double acc = 0.0;
-        for (int c = c0 + (int)threadIdx.x; c < c1; c += BS) acc += d.pm[3 * c + k];
-        P[k] = block_sum<BS>(acc, lds);
+        const long long b = __double_as_longlong(a[k]);
+        const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+        const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+        P[k] = __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
     }
 }
 
@@ -147,7 +164,7 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
         d.bk[5 * S + i] = d.vz[i];
     }
     double P[3];
-    system_momentum<kChunk>(d, s, lds, P);
+    system_momentum(d, s, P);
     if (a.reset && blockIdx.x == 0 && threadIdx.x == 0) {
         d.ctr[C_CAND] = 0;
         d.ctr[C_ENC] = 0;
@@ -1145,7 +1162,10 @@ struct FineArgs {
 };
 
 // fine test of candidate (i, j), i < j, appended to its system's segment
-// when it is an encounter (the count is kept even past the segment's end)
+// when it is an encounter (the count is kept even past the segment's end;
+// k_sets adds the systems' counts into C_ENC).  The lanes of a wave that
+// append to the same system as its first appending lane share one atomic
+// (a counter hit once per pair serialises in its L2 channel).
 __device__ __forceinline__ void fine_one(const FineArgs &a, int i, int j)
 {
     const Dev &d = a.d;
@@ -1154,14 +1174,21 @@ __device__ __forceinline__ void fine_one(const FineArgs &a, int i, int j)
     const double a1[3] = {d.x[j] - d.x[i], d.y[j] - d.y[i], d.z[j] - d.z[i]};
     const double b1[3] = {d.vx[j] - d.vx[i], d.vy[j] - d.vy[i], d.vz[j] - d.vz[i]};
     double lhs, rhs;
-    const int f = fine_pair(a.hill_mode, a.aE, d.sys_m0[d.body_sys[i]], a.tau, d.m[i], d.m[j],
-                            d.h[i], d.h[j], d.A[i], d.A[j], a0, b0, a1, b1, lhs, rhs);
-    if (f) {
-        atomicAdd(&d.ctr[C_ENC], 1ull);
-        const int s = d.body_sys[i];
-        const int slot = atomicAdd(&d.sys_ecnt[s], 1);
-        if (slot < d.sys_eoff[s + 1] - d.sys_eoff[s]) d.enc[d.sys_eoff[s] + slot] = make_int2(i, j);
-    }
+    const int s = d.body_sys[i];
+    const int f = fine_pair(a.hill_mode, a.aE, d.sys_m0[s], a.tau, d.m[i], d.m[j], d.h[i], d.h[j],
+                            d.A[i], d.A[j], a0, b0, a1, b1, lhs, rhs);
+    const unsigned long long m = __ballot(f);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)m) - 1;
+    const int sl = __shfl(s, leader, 64);
+    const unsigned long long same = __ballot(f && s == sl);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&d.sys_ecnt[sl], __popcll(same));
+    base = __shfl(base, leader, 64);
+    if (!f) return;
+    const int slot = s == sl ? base + __popcll(same & __lanemask_lt()) : atomicAdd(&d.sys_ecnt[s], 1);
+    if (slot < d.sys_eoff[s + 1] - d.sys_eoff[s]) d.enc[d.sys_eoff[s] + slot] = make_int2(i, j);
 }
 
 // The candidates of the crude sweep, or, when more candidates were found
@@ -1384,6 +1411,7 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
     const int cnt = d.sys_ecnt[sys];
     const int2 *enc = d.enc + d.sys_eoff[sys];
     if (d.ctr[C_STATUS] & S_FREEZE) return;
+    if (t == 0 && cnt > 0) atomicAdd(&d.ctr[C_ENC], (unsigned long long)cnt);
     if (cnt > d.sys_eoff[sys + 1] - d.sys_eoff[sys]) {
         // more pairs than the system's segment holds: the step is left undone
         if (t == 0) latch(d.ctr, S_ENC_OVF);
@@ -2851,32 +2879,64 @@ __global__ __launch_bounds__(256) void k_energy_pairs(EnergyArgs a)
     int rec = d.e_wrec[w];
     double R[kERec] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double G = a.G;
-    int cur_b = -1;
-    double xi = kFarI, yi = kFarI, zi = kFarI, mi = 0.0;
-    bool iok = false;
+    // operands of this lane's i and j: loaded one unit ahead, so the loads
+    // of the next unit are in flight during the pairs of this one
+    double xi, yi, zi, mi;
+    bool iok;
+    auto load_i = [&](int so_, int n_, int b_, double &x, double &y, double &z, double &m, bool &ok) {
+        const int i = so_ + 64 * b_ + lane;
+        ok = 64 * b_ + lane < n_;
+        x = ok ? d.x[i] : kFarI;
+        y = ok ? d.y[i] : kFarI;
+        z = ok ? d.z[i] : kFarI;
+        m = ok ? d.m[i] : 0.0;
+    };
+    auto load_j = [&](int so_, int n_, int t_, double &x, double &y, double &z, double &m) {
+        const int j = so_ + 64 * t_ + lane;
+        const bool ok = 64 * t_ + lane < n_;
+        x = ok ? d.x[j] : kFar;
+        y = ok ? d.y[j] : kFar;
+        z = ok ? d.z[j] : kFar;
+        m = ok ? d.m[j] : 0.0;
+    };
+    load_i(so, n, b, xi, yi, zi, mi, iok);
+    double jx, jy, jz, jm;
+    load_j(so, n, t, jx, jy, jz, jm);
     long long C = C0;
     for (;;) {
         const long long ubase = C & ~63LL;
         const int c0 = (int)(C - ubase);
         const int c1 = C1 - ubase < 64 ? (int)(C1 - ubase) : 64;
-        if (b != cur_b) {
-            const int i = so + 64 * b + lane;
-            iok = 64 * b + lane < n;
-            xi = iok ? d.x[i] : kFarI;
-            yi = iok ? d.y[i] : kFarI;
-            zi = iok ? d.z[i] : kFarI;
-            mi = iok ? d.m[i] : 0.0;
-            cur_b = b;
-        }
-        {
-            const int j = so + 64 * t + lane;
-            const bool jok = 64 * t + lane < n;
-            sx[lane] = jok ? d.x[j] : kFar;
-            sy[lane] = jok ? d.y[j] : kFar;
-            sz[lane] = jok ? d.z[j] : kFar;
-            sm[lane] = jok ? d.m[j] : 0.0;
-        }
+        sx[lane] = jx;
+        sy[lane] = jy;
+        sz[lane] = jz;
+        sm[lane] = jm;
         wave_lds_sync();
+        // the next unit: the next tile of the row, the next row, the next
+        // system with units; its operands requested now
+        const bool more = ubase + c1 < C1;
+        int s2 = s, so2 = so, n2 = n, nb2 = nb, b2 = b, t2 = t + 1;
+        bool newsys = false;
+        double pxi = 0.0, pyi = 0.0, pzi = 0.0, pmi = 0.0;
+        bool piok = false;
+        if (more) {
+            if (t2 == nb2) {
+                b2 = b + 1;
+                if (b2 == nb2) {
+                    newsys = true;
+                    do {
+                        ++s2;
+                    } while (d.sys_u0[s2 + 1] == d.sys_u0[s2]);
+                    so2 = d.sys_off[s2];
+                    n2 = d.sys_off[s2 + 1] - so2;
+                    nb2 = (n2 + 63) >> 6;
+                    b2 = 0;
+                }
+                t2 = b2;
+                load_i(so2, n2, b2, pxi, pyi, pzi, pmi, piok);
+            }
+            load_j(so2, n2, t2, jx, jy, jz, jm);
+        }
         const bool diag = t == b;
         double acc;
         if (diag) {
@@ -2898,29 +2958,30 @@ __global__ __launch_bounds__(256) void k_energy_pairs(EnergyArgs a)
         }
         R[5] = fma(mi, acc, R[5]);
         wave_lds_sync();   // the slice is restaged for the next unit
-        C = ubase + c1;
-        if (C >= C1) break;
-        // next unit: the next tile of the row, the next row, the next system
-        if (++t == nb) {
-            if (++b == nb) {
+        if (!more) break;
+        if (newsys) {
 #pragma unroll
-                for (int k = 0; k < kERec; ++k) {
-                    const double r = wave_sum0(R[k]);
-                    if (lane == 0) d.erec[(long long)kERec * rec + k] = r;
-                    R[k] = 0.0;
-                }
-                ++rec;
-                do {
-                    ++s;
-                } while (d.sys_u0[s + 1] == d.sys_u0[s]);
-                so = d.sys_off[s];
-                n = d.sys_off[s + 1] - so;
-                nb = (n + 63) >> 6;
-                b = 0;
-                cur_b = -1;
+            for (int k = 0; k < kERec; ++k) {
+                const double r = wave_sum0(R[k]);
+                if (lane == 0) d.erec[(long long)kERec * rec + k] = r;
+                R[k] = 0.0;
             }
-            t = b;
+            ++rec;
         }
+        if (b2 != b || newsys) {
+            xi = pxi;
+            yi = pyi;
+            zi = pzi;
+            mi = pmi;
+            iok = piok;
+        }
+        s = s2;
+        so = so2;
+        n = n2;
+        nb = nb2;
+        b = b2;
+        t = t2;
+        C = ubase + c1;
     }
 #pragma unroll
     for (int k = 0; k < kERec; ++k) {
