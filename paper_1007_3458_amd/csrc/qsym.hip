@@ -1107,6 +1107,12 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return bail(QSYM_EHIP, "hipDeviceGetAttribute");
+        // k_hermite_grid's barriers need every workgroup resident at once:
+        // one per compute unit, and only if the kernel fits one per unit
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_hermite_grid, kGridThreads, 0) !=
+                hipSuccess || occ < 1)
+            return bail(QSYM_EHIP, "k_hermite_grid does not fit a compute unit");
         c->grid_blocks = std::max(1, std::min(cus, kGridMax));
         c->cus = std::max(1, cus);
     }
