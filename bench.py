@@ -186,6 +186,49 @@ def timed_run(ctx, tau, steps, warmup, graph_pass, checkpoints=10, swapped=False
             "st": st, "st2": st2, "energy_us": energy_us}
 
 
+def balance_report(ctx, tau, steps, swapped=False):
+    """Load balance of the kick and Hermite launches over `steps` further
+    steps profiled with workgroup records: per launch the busy time of each
+    compute unit (the union of its workgroups' intervals), the busiest
+    unit's against the mean over all the device's units."""
+    stepper = ctx.step_swapped if swapped else ctx.step
+    ctx.profile(True, records=True)
+    stepper(tau, steps)
+    ctx.sync()
+    st = ctx.stats()
+    ctx.profile(False)
+    out = {}
+    for name, ph in (("kick+crude", 1), ("hermite (k_hermite)", 5), ("kick2", 6)):
+        n = st["busy_calls"][ph]
+        if n and st["busy_mean_us"][ph] > 0:
+            out[name] = {"max_over_mean": st["busy_max_us"][ph] / st["busy_mean_us"][ph],
+                         "busy_max_us": st["busy_max_us"][ph] / n,
+                         "busy_mean_us": st["busy_mean_us"][ph] / n,
+                         "event_us": st["phase_us"][ph] / st["phase_calls"][ph], "launches": n}
+    out["compute_units_seen"] = st["busy_units"]
+    out["steps"] = steps
+    return out
+
+
+def oracle_energy_report(systems, tau, warmup, steps, dE):
+    """The batch's per-system energy errors against the oracle's, integrated
+    system by system under the same protocol (stored beside the tests)."""
+    path = os.path.join(ROOT, "tests", "golden", "batch_energy_oracle.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    if (g["n"] != [s_.n for s_ in systems] or g["tau"] != tau or g["warmup_steps"] != warmup
+            or g["steps"] != steps or g["energy_every"] != max(1, steps // 10)):
+        return None
+    dE_o = np.array([float.fromhex(x) for x in g["dE_max"]])
+    dE = np.asarray(dE, dtype=np.float64)
+    return {"worst_system": int(np.argmax(dE)), "energy_error": float(dE.max()),
+            "oracle_worst_system": int(np.argmax(dE_o)), "oracle_energy_error": float(dE_o.max()),
+            "max_rel_diff": float(np.max(np.abs(dE - dE_o) / dE_o)),
+            "source": "tests/golden/batch_energy_oracle.json (oracle, each system on its own, "
+                      "same steps and energy checkpoints)"}
+
+
 def kick_accels(ctx, m, h, q, v):
     """Accelerations at positions q through the library's kick (velocities
     zeroed so that v = a exactly), state (q, v) restored afterwards."""
@@ -460,6 +503,12 @@ def main():
                               "achieved_tflops": ep * FLOP_ENERGY_PAIR / (r["energy_us"] * 1e-6) / 1e12,
                               "frac_fp64_peak": ep * FLOP_ENERGY_PAIR / (r["energy_us"] * 1e-6) / 1e12
                               / FP64_PEAK_TFLOPS}
+    out["load_balance"] = balance_report(ctx, args.tau, 10 if args.workload != "disk128k" else 4,
+                                         args.swapped)
+    if args.workload == "batch" and not args.swapped:
+        rep = oracle_energy_report(systems, args.tau, warmup, steps, r["dEmax"])
+        if rep:
+            out["energy_error_vs_oracle"] = rep
     out.update(extra)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(systems, args.tau, args.cpu_seconds, args.swapped)

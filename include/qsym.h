@@ -120,6 +120,18 @@ typedef struct qsym_stats_t {
     int64_t kepler_restarts;  /* all steps: Kepler solves whose first start
                                  reached the iteration cap (then restarted from
                                  the first-order guess)                       */
+    /* Load balance while profiling, per phase as phase_us: the kick launches
+     * and the set-per-workgroup Hermite launch (k_hermite; not the grid
+     * Hermite) record each workgroup's compute unit and start and end time.
+     * A compute unit's busy time in a launch is the union of its workgroups'
+     * intervals; busy_max_us sums the largest over units, busy_mean_us the
+     * mean over all the device's units (idle ones count as zero), over
+     * busy_calls launches.  busy_max_us / busy_mean_us is the max/mean busy
+     * ratio (1 for a perfectly balanced launch).                              */
+    double busy_max_us[12];
+    double busy_mean_us[12];
+    int64_t busy_calls[12];
+    int64_t busy_units;       /* most compute units seen in one launch         */
 } qsym_stats_t;
 
 typedef struct qsym_ctx qsym_ctx;
@@ -248,7 +260,11 @@ int qsym_autotune(qsym_ctx *ctx, double tau, double *us);
  * with HIP events around each launch, accumulating per-kernel time into
  * qsym_stats_t.phase_us.  Kernel index order: 0 drift+prepass, 1 kick with
  * crude sweep, 2 kick apply + Kepler, 3 fine sweep, 4 sets, 5 Hermite,
- * 6 second kick, 7 kick apply + momentum, 8 final drift, 9 energy. */
+ * 6 second kick, 7 kick apply + momentum, 8 final drift, 9 energy.
+ * enable = 2 also records workgroups for the busy_* load-balance figures
+ * (the symmetric kick then runs its recording variant, and the records are
+ * read back every 64 recorded launches, which synchronises the stream);
+ * 0 turns profiling off.  Enabling clears the accumulated figures. */
 int qsym_profile(qsym_ctx *ctx, int32_t enable);
 
 /* ------------------------------------------------------------------------

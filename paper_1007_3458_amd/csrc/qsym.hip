@@ -4,6 +4,7 @@
 #include "qsym.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -339,7 +340,7 @@ struct qsym_ctx {
         double tau = 0.0;
         bool valid = false;
     } g[2];
-    bool profile = false;
+    int profile = 0;   // 1: kernel timings, 2: and workgroup records
     // profiling: event pairs recorded around launches without waiting; the
     // pending pairs are read (and the events recycled) at the next flush
     std::vector<hipEvent_t> pool;
@@ -347,6 +348,16 @@ struct qsym_ctx {
     size_t pool_used = 0;
     double phase_us[kPhases] = {};
     long long phase_calls[kPhases] = {};
+    int cur_phase = P_OTHER;   // phase of the Timer open around the current launch
+    // workgroup records of the kick and k_hermite launches (profiling): a
+    // device ring of kRecLaunches slots of rec_wg records, read at the flush
+    unsigned long long *rec = nullptr;
+    int rec_wg = 0;
+    std::vector<std::pair<int, int>> rec_pend;   // (phase, workgroups) per used slot
+    double busy_max_us[kPhases] = {};
+    double busy_mean_us[kPhases] = {};
+    long long busy_calls[kPhases] = {};
+    int busy_units = 0;
     bool guess_loaded = false;
     int grid_blocks = 256;   // workgroups of k_hermite_grid: the device's compute units
     int cus = 256;           // the device's compute units
@@ -679,6 +690,8 @@ int upload_shape(qsym_ctx *c, int which)
 }
 
 // ---------------------------------------------------------------- launches
+unsigned long long *rec_slot(qsym_ctx *c, int nwg, hipStream_t st);
+
 template <int BS, int IPL>
 hipError_t launch_kick_bs(qsym_ctx *c, int mode, int prec, hipStream_t st)
 {
@@ -687,9 +700,23 @@ hipError_t launch_kick_bs(qsym_ctx *c, int mode, int prec, hipStream_t st)
                 c->shape[w].remap, c->p.hill_mode, c->p.aE, c->p.crude_safety, c->tau_crude, 1e-200,
                 1.875, 1.5};
     const dim3 g(c->shape[w].remap ? c->grid_kick[w] : std::max(c->nitems[w], 1)), b(BS);
+    // workgroup records only for the symmetric kick (its recording variant)
+    if (c->shape[w].sym) ka.rec = rec_slot(c, (int)g.x, st);
     if (c->shape[w].sym) {
         // one or two i per lane (the shape check admits no other)
         if constexpr (IPL <= 2) {
+            if (ka.rec) {
+                if (prec == 0) {
+                    if (mode == 0) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 0, 0, true>), g, b, 0, st, ka);
+                    else if (mode == 1) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 1, 0, true>), g, b, 0, st, ka);
+                    else hipLaunchKernelGGL((k_kick_sym<BS, IPL, 2, 0, true>), g, b, 0, st, ka);
+                } else {
+                    if (mode == 0) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 0, 1, true>), g, b, 0, st, ka);
+                    else if (mode == 1) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 1, 1, true>), g, b, 0, st, ka);
+                    else hipLaunchKernelGGL((k_kick_sym<BS, IPL, 2, 1, true>), g, b, 0, st, ka);
+                }
+                return hipGetLastError();
+            }
             if (prec == 0) {
                 if (mode == 0) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 0, 0>), g, b, 0, st, ka);
                 else if (mode == 1) hipLaunchKernelGGL((k_kick_sym<BS, IPL, 1, 0>), g, b, 0, st, ka);
@@ -761,7 +788,64 @@ int kick_occupancy(qsym_ctx *c, int which, const Shape &sh)
 
 int nblocks_chunks(qsym_ctx *c) { return (int)c->T.bchunk.size(); }
 
-// accumulate the timings of all pending event pairs (waits for them)
+constexpr int kRecLaunches = 64;
+
+// Busy time of each compute unit in one recorded launch: the union of the
+// [start, end] intervals of the workgroups it ran (workgroups resident
+// together count once).  Adds the largest and the mean over the device's
+// compute units (idle ones count as zero) to the phase's sums.
+void busy_launch(qsym_ctx *c, int ph, const unsigned long long *r, int nwg)
+{
+    std::vector<std::array<unsigned long long, 3>> v;
+    v.reserve(nwg);
+    for (int k = 0; k < nwg; ++k)
+        if (r[3 * k] != 0 && r[3 * k + 2] >= r[3 * k + 1]) v.push_back({r[3 * k], r[3 * k + 1], r[3 * k + 2]});
+    if (v.empty()) return;
+    std::sort(v.begin(), v.end());
+    unsigned long long total = 0, most = 0;
+    int units = 0;
+    for (size_t a = 0; a < v.size();) {
+        size_t b = a;
+        unsigned long long busy = 0, lo = v[a][1], hi = v[a][2];
+        for (; b < v.size() && v[b][0] == v[a][0]; ++b) {
+            if (v[b][1] > hi) {
+                busy += hi - lo;
+                lo = v[b][1];
+                hi = v[b][2];
+            } else {
+                hi = std::max(hi, v[b][2]);
+            }
+        }
+        busy += hi - lo;
+        total += busy;
+        most = std::max(most, busy);
+        ++units;
+        a = b;
+    }
+    // ticks of the 100 MHz real-time clock: 0.01 us each
+    c->busy_max_us[ph] += 0.01 * (double)most;
+    c->busy_mean_us[ph] += 0.01 * (double)total / std::max(c->cus, units);
+    c->busy_calls[ph] += 1;
+    c->busy_units = std::max(c->busy_units, units);
+}
+
+// the busy figures of the pending workgroup records (waits for the stream)
+void flush_records(qsym_ctx *c)
+{
+    if (c->rec_pend.empty()) return;
+    const size_t words = 3 * (size_t)c->rec_wg;
+    std::vector<unsigned long long> h(words * c->rec_pend.size());
+    if (hipStreamSynchronize(c->stream) == hipSuccess &&
+        hipMemcpy(h.data(), c->rec, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost) ==
+            hipSuccess) {
+        for (size_t k = 0; k < c->rec_pend.size(); ++k)
+            busy_launch(c, c->rec_pend[k].first, h.data() + words * k, c->rec_pend[k].second);
+    }
+    c->rec_pend.clear();
+}
+
+// accumulate the timings of all pending event pairs (waits for them) and
+// the busy figures of the pending workgroup records
 void flush_profile(qsym_ctx *c)
 {
     for (size_t k = 0; k < c->pend_phase.size(); ++k) {
@@ -774,6 +858,34 @@ void flush_profile(qsym_ctx *c)
     }
     c->pend_phase.clear();
     c->pool_used = 0;
+    flush_records(c);
+}
+
+// record slot for a launch of nwg workgroups in the current phase (cleared
+// on st), or null when not profiling or no memory for the records.  Called
+// inside the launch's Timer: only the records are flushed here, the Timer's
+// own event pair stays pending.
+unsigned long long *rec_slot(qsym_ctx *c, int nwg, hipStream_t st)
+{
+    if (c->profile < 2 || nwg <= 0) return nullptr;
+    if ((int)c->rec_pend.size() == kRecLaunches || nwg > c->rec_wg) flush_records(c);
+    if (nwg > c->rec_wg) {
+        if (c->rec) (void)hipFree(c->rec);
+        c->rec = nullptr;
+        c->rec_wg = 0;
+        const int w = std::max(nwg, 1024);
+        if (hipMalloc((void **)&c->rec, sizeof(unsigned long long) * 3 * (size_t)w * kRecLaunches) !=
+            hipSuccess) {
+            c->rec = nullptr;
+            return nullptr;
+        }
+        c->rec_wg = w;
+    }
+    unsigned long long *r = c->rec + 3 * (size_t)c->rec_wg * c->rec_pend.size();
+    if (hipMemsetAsync(r, 0, sizeof(unsigned long long) * 3 * (size_t)nwg, st) != hipSuccess)
+        return nullptr;
+    c->rec_pend.push_back({c->cur_phase, nwg});
+    return r;
 }
 
 hipEvent_t pool_event(qsym_ctx *c)
@@ -798,6 +910,7 @@ struct Timer {
         e1 = pool_event(c);
         if (!e0 || !e1) { e1 = nullptr; return; }
         c->pend_phase.push_back(ph);
+        c->cur_phase = ph;
         (void)hipEventRecord(e0, c->stream);
     }
     ~Timer()
@@ -938,11 +1051,13 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
     // 5-7: corrections and Hermite per set
     {
         Timer tm(c, P_HERMITE);
-        HermArgs ha{c->d, tau, c->p.G, c->p.epsH, c->p.eta, c->p.eta_s, c->p.max_substeps};
+        HermArgs ha{c->d, tau, c->p.G, c->p.epsH, c->p.eta, c->p.eta_s, c->p.max_substeps,
+                    rec_slot(c, 256, st)};
         hipLaunchKernelGGL(k_hermite, dim3(256), dim3(kHermThreads), 0, st, ha);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // sets above kCoopMin members: the whole grid on one set at a time
         // (one workgroup per compute unit, so every workgroup is resident)
+        ha.rec = nullptr;
         GridArgs ga{ha, c->d.gbar, c->d.hpart};
         hipLaunchKernelGGL(k_hermite_grid, dim3(c->grid_blocks), dim3(kGridThreads), 0, st, ga);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1203,6 +1318,7 @@ void qsym_destroy(qsym_ctx *c)
         if (g.graph) hipGraphDestroy(g.graph);
     }
     for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    if (c->rec) (void)hipFree(c->rec);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
     if (c->stream) hipStreamDestroy(c->stream);
@@ -1455,7 +1571,11 @@ int qsym_stats(qsym_ctx *c, qsym_stats_t *out)
     for (int k = 0; k < kPhases; ++k) {
         out->phase_us[k] = c->phase_us[k];
         out->phase_calls[k] = c->phase_calls[k];
+        out->busy_max_us[k] = c->busy_max_us[k];
+        out->busy_mean_us[k] = c->busy_mean_us[k];
+        out->busy_calls[k] = c->busy_calls[k];
     }
+    out->busy_units = c->busy_units;
     return QSYM_OK;
 }
 
@@ -1638,12 +1758,15 @@ int qsym_profile(qsym_ctx *c, int32_t enable)
     if (!c) return QSYM_EINVAL;
     (void)hipStreamSynchronize(c->stream);
     flush_profile(c);
-    c->profile = enable != 0;
+    c->profile = enable < 0 ? 0 : std::min(enable, 2);
     if (enable) {
         for (int k = 0; k < kPhases; ++k) {
             c->phase_us[k] = 0.0;
             c->phase_calls[k] = 0;
+            c->busy_max_us[k] = c->busy_mean_us[k] = 0.0;
+            c->busy_calls[k] = 0;
         }
+        c->busy_units = 0;
     }
     return QSYM_OK;
 }

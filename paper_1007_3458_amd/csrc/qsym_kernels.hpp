@@ -51,6 +51,31 @@ __device__ __forceinline__ void latch(unsigned long long *ctr, unsigned long lon
     atomicOr(&ctr[C_STATUS], bits);
 }
 
+// Workgroup records for the load-balance figure (profiling only; rec is
+// null otherwise): three words per workgroup of the launch, written by
+// thread 0: at the workgroup's start 1 + the compute unit (XCC id << 8 |
+// SE, SH and CU ids of HW_ID) and the 100 MHz real-time clock, after its
+// last barrier the clock again.  A workgroup that returns early leaves its
+// end (cleared) at zero.
+__device__ __forceinline__ void wg_start(unsigned long long *rec)
+{
+    if (rec == nullptr || threadIdx.x != 0) return;
+    // s_getreg operands: register id | offset << 6 | (bits - 1) << 11
+    const unsigned hw = __builtin_amdgcn_s_getreg(4 | (31 << 11));    // HW_ID
+    const unsigned xcc = __builtin_amdgcn_s_getreg(20 | (3 << 11));   // XCC_ID[3:0]
+    unsigned long long *r = rec + 3ull * blockIdx.x;
+    r[0] = 1ull + ((xcc << 8) | ((hw >> 8) & 0xffu));
+    r[1] = __builtin_amdgcn_s_memrealtime();
+}
+
+// end of a recorded workgroup: every wave done, then thread 0 writes
+__device__ __forceinline__ void wg_finish(unsigned long long *rec)
+{
+    if (rec == nullptr) return;
+    __syncthreads();
+    if (threadIdx.x == 0) rec[3ull * blockIdx.x + 2] = __builtin_amdgcn_s_memrealtime();
+}
+
 // Momentum of system s summed from its chunk partials in a fixed order:
 // each wave on its own (lane-strided sums, then a butterfly whose lane-0
 // result every lane takes), so no workgroup barrier and the same bits in
@@ -251,6 +276,7 @@ struct KickArgs {
     double aE, cs, tau_abs;
     double r2seed;     // 1e-200, passed at run time so it stays a register operand
     double c158, c32;  // 15/8 and 3/2 of the r^-3 correction, likewise register operands
+    unsigned long long *rec = nullptr;   // workgroup records (profiling), else null
 };
 
 // workgroup b of a grid of g (multiple of 8) runs on XCD b % 8; give each
@@ -710,13 +736,17 @@ __device__ void sym_tile_exact(const KickArgs &ka, int jt, int jend, const int *
             for (int j = jt; j < je; ++j) crude_exact(ka, iu[u], j);
 }
 
-template <int BS, int IPL, int MODE, int PREC>
+// REC: the variant that writes workgroup records (profiling with records;
+// a separate instantiation, so the kernel timed otherwise carries no trace
+// of them: any extra live value changes this kernel's register allocation)
+template <int BS, int IPL, int MODE, int PREC, bool REC = false>
 __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_kick_sym(
     KickArgs ka)
 {
     static_assert(IPL == 1 || IPL == 2, "one or two i per lane");
     const Dev &d = ka.d;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if constexpr (REC) wg_start(ka.rec);
     int b = blockIdx.x;
     if (ka.remap) b = xcd_item(b, gridDim.x);
     if (b >= ka.nitems) return;
@@ -925,6 +955,7 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
         // no tile would leave pairs here
         if (qstart > 0) sym_flush<BS>(ka, qi, qj, qstart, cl, &cn, &cbase);
     }
+    if constexpr (REC) wg_finish(ka.rec);
 }
 
 // sum of the kick partials of body i (local index il of system s)
@@ -1950,6 +1981,7 @@ struct HermArgs {
     Dev d;
     double tau, G, epsH, eta, eta_s;
     int max_substeps;
+    unsigned long long *rec = nullptr;   // workgroup records (profiling), else null
 };
 
 constexpr int kCoopMin = 256;       // larger sets run on the whole grid (k_hermite_grid)
@@ -2455,6 +2487,7 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
     __shared__ double s_u[kHermLds], s_v[kHermLds], s_w[kHermLds], s_m[kHermLds];
     __shared__ double lds[kHermThreads / 64];
     const int t = threadIdx.x;
+    wg_start(a.rec);
     const int nwg = gridDim.x, wpb = kHermThreads / 64;
     if (d.ctr[C_STATUS] & S_FREEZE) return;   // a step left undone
     const int nbig = (int)d.ctr[C_NBIG];
@@ -2504,6 +2537,7 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
         atomicAdd(&d.ctr[C_TSUB], (unsigned long long)nsub_w);
     }
     if (lane == 0 && fail_w) latch(d.ctr, S_HERMITE);
+    wg_finish(a.rec);
 }
 
 

@@ -46,7 +46,9 @@ class Stats(C.Structure):
                 ("kepler_hist", C.c_int64 * 32), ("status", C.c_int64),
                 ("phase_us", C.c_double * 12), ("phase_calls", C.c_int64 * 12),
                 ("whole_system", C.c_int64), ("fallbacks", C.c_int64), ("overflows", C.c_int64),
-                ("global_sets", C.c_int64), ("kepler_restarts", C.c_int64)]
+                ("global_sets", C.c_int64), ("kepler_restarts", C.c_int64),
+                ("busy_max_us", C.c_double * 12), ("busy_mean_us", C.c_double * 12),
+                ("busy_calls", C.c_int64 * 12), ("busy_units", C.c_int64)]
 
     def as_dict(self):
         d = {}
@@ -354,8 +356,10 @@ class Context:
         self._c(lib().qsym_autotune(self.ctx, float(tau), us))
         return us[0], us[1]
 
-    def profile(self, enable=True):
-        self._c(lib().qsym_profile(self.ctx, 1 if enable else 0))
+    def profile(self, enable=True, records=False):
+        """Per-kernel timings; records=True also collects the workgroup
+        records behind the busy_* load-balance statistics."""
+        self._c(lib().qsym_profile(self.ctx, (2 if records else 1) if enable else 0))
 
     def set_guess(self, weights):
         """Weights of the learned Kepler start (kepler_mode 2): a host array

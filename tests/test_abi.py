@@ -44,7 +44,7 @@ def test_workspace_bytes_and_validation():
 def test_params_struct_layout_matches_header():
     from paper_1007_3458_amd import qsym
     assert C.sizeof(qsym.Params) == 7 * 8 + 4 * 4 + 8 + 8 + 2 * 4
-    assert C.sizeof(qsym.Stats) == 10 * 8 + 32 * 8 + 8 + 12 * 8 + 12 * 8 + 8 + 4 * 8
+    assert C.sizeof(qsym.Stats) == 10 * 8 + 32 * 8 + 8 + 12 * 8 + 12 * 8 + 8 + 4 * 8 + 3 * 12 * 8 + 8
 
 
 def test_product_path_does_not_import_oracle():

@@ -245,6 +245,79 @@ def test_batch_step_per_system(Q, orc):
         assert np.array_equal(mine, r.pairs), k
 
 
+def test_batch_energy_error_matches_oracle(Q):
+    """The 512-system batch over the benchmark's protocol (tau = 0.05, 10
+    steps, then 100 steps with the energy every 10 against the energy after
+    the first 10): every system's largest relative energy error equals the
+    oracle's, integrated system by system (tests/golden/
+    batch_energy_oracle.json, written by make_batch_energy.py beside it).
+    The two integrate the same initial conditions with the same arithmetic
+    up to rounding order, so the energy errors, which range over 2.4e-13 ..
+    3.4e-7 between systems, agree to a small fraction of themselves; the
+    bound 1e-3 relative + 1e-12 absolute leaves room for rounding amplified
+    through close encounters over 110 steps, and is far below the spread
+    between systems, so the worst system and its error are reproduced."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "batch_energy_oracle.json")))
+    dE_o = np.array([float.fromhex(x) for x in g["dE_max"]])
+    systems = inputs.batch()
+    assert [b.n for b in systems] == g["n"]
+    say("batch energy", len(systems))
+    ctx = Q.Context(systems)
+    ctx.step(g["tau"], g["warmup_steps"])
+    E0 = ctx.energy()
+    dE = np.zeros(len(systems))
+    for _ in range(g["steps"] // g["energy_every"]):
+        ctx.step(g["tau"], g["energy_every"])
+        dE = np.maximum(dE, np.abs(ctx.energy() / E0 - 1.0))
+    st = ctx.stats()
+    ctx.close()
+    assert st["status"] == 0 and st["overflows"] == 0
+    diff = np.abs(dE - dE_o)
+    worst = int(np.argmax(diff / (1e-3 * dE_o + 1e-12)))
+    say(f"  worst system gpu {int(np.argmax(dE))} ({dE.max():.4e}), oracle "
+        f"{int(np.argmax(dE_o))} ({dE_o.max():.4e}); largest disagreement system {worst}: "
+        f"{dE[worst]:.6e} vs {dE_o[worst]:.6e}")
+    assert np.all(diff <= 1e-3 * dE_o + 1e-12), worst
+    assert int(np.argmax(dE)) == int(np.argmax(dE_o))
+
+
+def test_batch_load_balance_records(Q):
+    """Workgroup records (profiling with records) on a 64-system slice of the
+    batch: the symmetric kick's recording variant gives the same state bit
+    for bit as the captured step, and the busy figures are consistent: at
+    most the device's compute units, mean <= max, and the busiest unit's
+    time within the launch's event time."""
+    import torch
+    systems = inputs.batch()[:64]
+    a = Q.Context(systems)
+    b = Q.Context(systems)
+    for c in (a, b):   # the batch's tuned shape: the symmetric kick, which records
+        c.set_kick_shape(2, 128, 256, remap=0, which=-1, sym=1)
+    a.step(0.05, 3)
+    b.profile(True, records=True)
+    b.step(0.05, 3)
+    st = b.stats()
+    b.profile(False)
+    qa, va = a.get_state()
+    qb, vb = b.get_state()
+    a.close()
+    b.close()
+    assert np.array_equal(qa, qb) and np.array_equal(va, vb)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    say("  busy units", st["busy_units"], "of", cus)
+    assert 0 < st["busy_units"] <= cus
+    for ph in (1, 5, 6):   # kick + crude sweep, Hermite, second kick
+        n = st["busy_calls"][ph]
+        assert n == 3, (ph, n)
+        mx, mean = st["busy_max_us"][ph], st["busy_mean_us"][ph]
+        say(f"  phase {ph}: max {mx / n:.1f} us mean {mean / n:.1f} us, event "
+            f"{st['phase_us'][ph] / st['phase_calls'][ph]:.1f} us")
+        assert 0 < mean <= mx <= 1.05 * st["phase_us"][ph] + 5.0 * n
+
+
 def test_batch_kick_sampled(Q, orc):
     """FP64 kick of the 512-system batch (551,375 bodies, tuned shape): the
     first, middle and last body of every system."""
