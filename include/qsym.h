@@ -234,8 +234,10 @@ int qsym_fine_test(const qsym_params *p, double m0, double tau, int64_t n, const
  * 1 for the kick with the fused crude sweep (-1: both, set only):
  * ipl = i-bodies per lane (1, 2, 4), block = threads per workgroup (128,
  * 256), jchunk = j-bodies per workgroup (a multiple of block and at least
- * the smallest j-chunk the workspace was sized for), remap = 1 for the
- * XCD-aware workgroup order, sym = 0 for the full-matrix kick (every
+ * the smallest j-chunk the workspace was sized for), remap bit 0 for the
+ * XCD-aware workgroup order, bit 1 (symmetric kick only) for the work
+ * items in order of decreasing pair count instead of chunk by chunk (the
+ * short diagonal and ragged items dispatched last), sym = 0 for the full-matrix kick (every
  * ordered pair) or 1, 2, 4, 8 for the symmetric kick (every unordered pair
  * once, the reaction applied to j; ipl 1 or 2 only; sym i-blocks of
  * block*ipl bodies per work item, jchunk a multiple of block*ipl; the

@@ -597,6 +597,58 @@ bool build_rows(qsym_ctx *c, const Shape &sh, int slots, std::vector<KickItem> &
 
 // kick work items for a launch shape; systems largest first, each system's
 // items j-chunk major (consecutive items share j data)
+// pairs i < j of a symmetric-kick item: i in [i0, i0 + ni), j in [j0, j0 + nj)
+long long item_pairs(const KickItem &it)
+{
+    const long long a = it.i0, b = (long long)it.i0 + it.ni, c0 = it.j0, e = (long long)it.j0 + it.nj;
+    // i below the chunk meets all of it; i inside it the part above i
+    long long p = std::max(0ll, std::min(b, c0) - a) * it.nj;
+    const long long lo = std::max(a, c0), hi = std::min(b, e);
+    if (hi > lo) p += (2 * e - lo - hi - 1) * (hi - lo) / 2;   // sum of e - 1 - i over [lo, hi)
+    return p;
+}
+
+// Dispatch order of the symmetric kick's items when the shape asks for it
+// (remap bit 1; else chunk by chunk): largest first (the
+// diagonal items, with a half or less of a full item's pairs, and the short
+// items of a ragged last chunk at the end), so the workgroups dispatched
+// last are the short ones and the compute units finish together.  With
+// the XCD-aware order (workgroup b runs item (b % 8) * per + b / 8) the
+// sorted items are dealt round robin into the eight XCDs' runs, each run
+// still largest first.  Results do not depend on the order: every item
+// writes its own partial slots.
+void order_items(std::vector<KickItem> &items, int remap)
+{
+    std::vector<std::pair<long long, int>> w(items.size());
+    for (size_t k = 0; k < items.size(); ++k) w[k] = {-item_pairs(items[k]), (int)k};
+    std::stable_sort(w.begin(), w.end(),
+                     [](const std::pair<long long, int> &x, const std::pair<long long, int> &y) {
+                         return x.first < y.first;
+                     });
+    std::vector<KickItem> out;
+    out.reserve(items.size());
+    if (!remap) {
+        for (const auto &x : w) out.push_back(items[x.second]);
+    } else {
+        // run r holds the item indices [r per, (r + 1) per) below n, per =
+        // grid / 8 (the grid's padding workgroups, indices n and up, have
+        // no item)
+        const int n = (int)items.size();
+        const int per = std::max(8, (n + 7) / 8 * 8) / 8;
+        std::vector<std::vector<int>> run(8);
+        auto cap = [&](int r) { return std::max(0, std::min(per, n - r * per)); };
+        int x = 0;
+        for (const auto &v : w) {
+            while ((int)run[x].size() >= cap(x)) x = (x + 1) % 8;
+            run[x].push_back(v.second);
+            x = (x + 1) % 8;
+        }
+        for (int r = 0; r < 8; ++r)
+            for (int k : run[r]) out.push_back(items[k]);
+    }
+    items.swap(out);
+}
+
 int build_items(qsym_ctx *c, const Shape &sh, std::vector<KickItem> &items, std::vector<int4> &sysK,
                 int slots, std::vector<int> &krow, int krow_base)
 {
@@ -642,6 +694,7 @@ int build_items(qsym_ctx *c, const Shape &sh, std::vector<KickItem> &items, std:
             }
         }
     }
+    if (sh.sym != 0 && (sh.remap & 2)) order_items(items, sh.remap & 1);
     return (int)items.size();
 }
 
@@ -696,10 +749,10 @@ template <int BS, int IPL>
 hipError_t launch_kick_bs(qsym_ctx *c, int mode, int prec, hipStream_t st)
 {
     const int w = mode ? 1 : 0;
+    const int xcd = c->shape[w].remap & 1;
     KickArgs ka{c->d, c->d.items + (size_t)w * c->L.max_items, c->p.G, c->L.cap, c->nitems[w],
-                c->shape[w].remap, c->p.hill_mode, c->p.aE, c->p.crude_safety, c->tau_crude, 1e-200,
-                1.875, 1.5};
-    const dim3 g(c->shape[w].remap ? c->grid_kick[w] : std::max(c->nitems[w], 1)), b(BS);
+                xcd, c->p.hill_mode, c->p.aE, c->p.crude_safety, c->tau_crude, 1e-200, 1.875, 1.5};
+    const dim3 g(xcd ? c->grid_kick[w] : std::max(c->nitems[w], 1)), b(BS);
     // workgroup records only for the symmetric kick (its recording variant)
     if (c->shape[w].sym) ka.rec = rec_slot(c, (int)g.x, st);
     if (c->shape[w].sym) {
@@ -1641,7 +1694,7 @@ int qsym_set_kick_shape(qsym_ctx *c, int32_t which, int32_t ipl, int32_t block, 
     if (!c) return QSYM_EINVAL;
     if ((which < -1 || which > 1) || (ipl != 1 && ipl != 2 && ipl != 4) ||
         (block != 128 && block != 256) || jchunk <= 0 || jchunk % block ||
-        jchunk < c->L.jchunk_min || (remap != 0 && remap != 1) ||
+        jchunk < c->L.jchunk_min || remap < 0 || remap > 3 || (remap > 1 && sym == 0) ||
         (sym != 0 && sym != 1 && sym != 2 && sym != 4 && sym != 8 && sym != kSymRows) ||
         (sym && (ipl > 2 || jchunk % ((long long)block * ipl))))
         return fail(c, QSYM_EINVAL, "kick shape out of range");
@@ -1705,7 +1758,7 @@ int qsym_autotune(qsym_ctx *c, double tau, double *us)
                     const long long jcs = (jc + BI - 1) / BI * BI;
                     if (ipls[ii] <= 2)
                         for (int sy = 1; sy <= 4; sy *= 2)
-                            for (int rm = 0; rm < 2; ++rm)
+                            for (int rm = 0; rm < 4; ++rm)
                                 cand.push_back(Shape{ipls[ii], blocks[bi], jcs, rm, sy});
                 }
         // balanced rows (the j-chunk plays no part: the smallest allowed)

@@ -61,6 +61,8 @@ SHAPES = [dict(ipl=1, block=128, jchunk=128, remap=0), dict(ipl=2, block=256, jc
           dict(ipl=1, block=256, jchunk=1024, remap=1, sym=1),
           dict(ipl=2, block=256, jchunk=512, remap=0, sym=1),
           dict(ipl=1, block=128, jchunk=512, remap=0, sym=4),
+          dict(ipl=2, block=128, jchunk=512, remap=3, sym=1),
+          dict(ipl=1, block=256, jchunk=256, remap=2, sym=2),
           # balanced rows: every row cut along j into items of equal pair count
           dict(ipl=1, block=256, jchunk=256, remap=0, sym=16),
           dict(ipl=2, block=256, jchunk=512, remap=0, sym=16),
