@@ -37,6 +37,43 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return r;
 }
 
+// Sums of three doubles over the first NB threads (NB a multiple of 64):
+// each wave by an xor butterfly (both partners add the same two values, so
+// every lane ends with the same bits), then the waves' totals in wave order
+// by thread 0, where the result is valid.  One barrier; the same bits for
+// the same inputs in every kernel that sums chunks of NB bodies.  lds holds
+// 3 NB / 64 doubles; every thread of the workgroup calls it.
+template <int NB>
+__device__ __forceinline__ void chunk_sum3(double v[3], double *lds)
+{
+    const int t = threadIdx.x;
+    if (t < NB) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double p0 = __shfl_xor(v[0], o, 64);
+            const double p1 = __shfl_xor(v[1], o, 64);
+            const double p2 = __shfl_xor(v[2], o, 64);
+            v[0] += p0;
+            v[1] += p1;
+            v[2] += p2;
+        }
+        if ((t & 63) == 0) {
+            lds[3 * (t >> 6)] = v[0];
+            lds[3 * (t >> 6) + 1] = v[1];
+            lds[3 * (t >> 6) + 2] = v[2];
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double a = lds[k];
+            for (int w = 1; w < NB / 64; ++w) a += lds[3 * w + k];
+            v[k] = a;
+        }
+    }
+}
+
 // LDS written by some lanes of a wave and read by others: the wave's LDS
 // operations complete in order, so a fence and a wave barrier suffice
 __device__ __forceinline__ void wave_lds_sync()
@@ -121,10 +158,9 @@ __global__ __launch_bounds__(kChunk) void k_momentum(Dev d)
         p[1] = mi * d.vy[i];
         p[2] = mi * d.vz[i];
     }
-    for (int k = 0; k < 3; ++k) {
-        double s = block_sum<kChunk>(p[k], lds);
-        if (t == 0) d.pm[3 * blockIdx.x + k] = s;
-    }
+    chunk_sum3<kChunk>(p, lds);
+    if (t == 0)
+        for (int k = 0; k < 3; ++k) d.pm[3 * blockIdx.x + k] = p[k];
 }
 
 // ------------------------------------------------------------------------
@@ -172,10 +208,9 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
             p[1] = mi * d.vy[i];
             p[2] = mi * d.vz[i];
         }
-        for (int k = 0; k < 3; ++k) {
-            const double sm = block_sum<kChunk>(p[k], lds);
-            if (t == 0) d.pm[3 * blockIdx.x + k] = sm;
-        }
+        chunk_sum3<kChunk>(p, lds);
+        if (t == 0)
+            for (int k = 0; k < 3; ++k) d.pm[3 * blockIdx.x + k] = p[k];
         if (blockIdx.x == 0 && t == 0) d.ctr[C_OVERFLOW] += 1;
         return;
     }
@@ -1108,10 +1143,10 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
         mom[2] = mi * vz;
     }
     if (a.momentum) {
-        for (int k = 0; k < 3; ++k) {
-            double sm = block_sum<BS * P>(mom[k], lds);
-            if (t == 0) d.pm[3 * blockIdx.x + k] = sm;
-        }
+        // the chunk's bodies are on the first BS threads (as in k_momentum)
+        chunk_sum3<BS>(mom, lds);
+        if (t == 0)
+            for (int k = 0; k < 3; ++k) d.pm[3 * blockIdx.x + k] = mom[k];
     }
     __syncthreads();
     if (a.do_kep) {
