@@ -42,7 +42,7 @@ struct Shape {
 // workspace layout: byte offsets of every array
 struct Layout {
     size_t off_state = 0, off_snap = 0, off_aux = 0, off_acc = 0, off_pm = 0, off_bsys = 0;
-    size_t off_sysoff = 0, off_sysm0 = 0, off_sysS = 0, off_syspoff = 0, off_sysc0 = 0;
+    size_t off_sysoff = 0, off_sysm0 = 0, off_sysS = 0, off_syspoff = 0, off_sysc0 = 0, off_sysk0 = 0;
     size_t off_bchunk = 0, off_kchunk = 0, off_items = 0, off_eitems = 0, off_syse0 = 0, off_cand = 0;
     size_t off_enc = 0, off_syseoff = 0, off_sysecnt = 0, off_setcount = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0, off_setlist = 0;
     size_t off_bigsys = 0, off_sysgoff = 0, off_gsa = 0, off_bk = 0, off_krow = 0;
@@ -71,7 +71,7 @@ struct Layout {
 };
 
 struct Tables {
-    std::vector<int> sys_off, sys_S, sys_c0, sys_e0, sys_eoff;
+    std::vector<int> sys_off, sys_S, sys_c0, sys_k0, sys_e0, sys_eoff;
     std::vector<long long> sys_poff, sys_goff;
     std::vector<long long> sys_u0, e_wcol;   // energy units per system, columns per wave
     std::vector<int> e_wrec, sys_r0;         // energy records per wave and per system
@@ -184,13 +184,14 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_snap, 6 * (size_t)L.np * D);
     take(L.off_aux, 3 * (size_t)L.np * D);
     take(L.off_acc, (size_t)L.acc_len * D);
-    take(L.off_pm, 3 * (size_t)L.nchunks * D);
+    take(L.off_pm, 3 * (size_t)L.nkchunks * D);
     take(L.off_bsys, (size_t)L.np * sizeof(int));
     take(L.off_sysoff, (size_t)(nsys + 1) * sizeof(int));
     take(L.off_sysm0, (size_t)std::max(nsys, 1) * D);
     take(L.off_sysS, 2 * (size_t)std::max(nsys, 1) * sizeof(int4));
     take(L.off_syspoff, (size_t)std::max(nsys, 1) * sizeof(long long));
     take(L.off_sysc0, (size_t)(nsys + 1) * sizeof(int));
+    take(L.off_sysk0, (size_t)(nsys + 1) * sizeof(int));
     take(L.off_bchunk, (size_t)L.nchunks * sizeof(int4));
     take(L.off_kchunk, (size_t)L.nkchunks * sizeof(int4));
     take(L.off_items, 2 * (size_t)L.max_items * sizeof(KickItem));
@@ -272,6 +273,7 @@ Dev bind(char *base, const Layout &L)
     d.sys_K = (int4 *)(base + L.off_sysS);
     d.sys_poff = (long long *)(base + L.off_syspoff);
     d.sys_c0 = (int *)(base + L.off_sysc0);
+    d.sys_k0 = (int *)(base + L.off_sysk0);
     d.bchunk = (int4 *)(base + L.off_bchunk);
     d.kchunk = (int4 *)(base + L.off_kchunk);
     d.items = (KickItem *)(base + L.off_items);
@@ -427,6 +429,7 @@ void build_tables(qsym_ctx *c)
     T.sys_poff.assign(nsys, 0);
     T.sys_goff.assign(nsys, -1);
     T.sys_c0.assign(nsys + 1, 0);
+    T.sys_k0.assign(nsys + 1, 0);
     T.sys_e0.assign(nsys + 1, 0);
     T.sys_eoff.assign(nsys + 1, 0);
     T.bchunk.clear();
@@ -442,6 +445,7 @@ void build_tables(qsym_ctx *c)
         T.sys_c0[s] = (int)T.bchunk.size();
         for (int b = 0; b < n; b += kChunk)
             T.bchunk.push_back(make_int4(s, (int)c->off[s] + b, std::min(kChunk, n - b), 0));
+        T.sys_k0[s] = (int)T.kchunk.size();
         for (int b = 0; b < n; b += kChunkK)
             T.kchunk.push_back(make_int4(s, (int)c->off[s] + b, std::min(kChunkK, n - b), 0));
         T.sys_e0[s] = (int)T.eitems.size();
@@ -464,6 +468,7 @@ void build_tables(qsym_ctx *c)
         }
     }
     T.sys_c0[nsys] = (int)T.bchunk.size();
+    T.sys_k0[nsys] = (int)T.kchunk.size();
     T.sys_e0[nsys] = (int)T.eitems.size();
     // energy schedule: every wave the same number of pair columns (64 per
     // unit), and the records (one per wave and system it touches) in system
@@ -1000,20 +1005,17 @@ hipError_t run_apply(qsym_ctx *c, double dt_kick, double dt_kep, int do_kick, in
                      int snapshot, int momentum, hipStream_t st, int phase, int which)
 {
     Timer tm(c, phase);
-    const bool small = do_kep && !momentum;
-    ApplyArgs a{c->d, small ? c->d.kchunk : c->d.bchunk, c->d.sys_K + (size_t)which * c->nsys,
-                dt_kick, dt_kep, c->p.G, do_kick, do_kep, snapshot, c->p.kepler_mode, momentum};
-    // systems of many bodies (tens of partial-sum slots per body, few
-    // chunks) share each body's reduction over four threads; many small
-    // systems keep one thread per body
-    const dim3 gk((unsigned)c->T.kchunk.size()), gb(nblocks_chunks(c));
-    if (c->apply_parts == 4) {
-        if (small) hipLaunchKernelGGL((k_apply_kepler<kChunkK, 4>), gk, dim3(kChunkK * 4), 0, st, a);
-        else hipLaunchKernelGGL((k_apply_kepler<kChunk, 4>), gb, dim3(kChunk * 4), 0, st, a);
-    } else {
-        if (small) hipLaunchKernelGGL((k_apply_kepler<kChunkK, 1>), gk, dim3(kChunkK), 0, st, a);
-        else hipLaunchKernelGGL((k_apply_kepler<kChunk, 1>), gb, dim3(kChunk), 0, st, a);
-    }
+    // kChunkK bodies per workgroup (the momentum partials are per such chunk)
+    ApplyArgs a{c->d, c->d.kchunk, c->d.sys_K + (size_t)which * c->nsys, dt_kick, dt_kep, c->p.G,
+                do_kick, do_kep, snapshot, c->p.kepler_mode, momentum};
+    // systems of many bodies (tens of partial-sum slots per body) share each
+    // body's reduction over four threads; many small systems keep one
+    // thread per body
+    const dim3 gk((unsigned)c->T.kchunk.size());
+    if (c->apply_parts == 4)
+        hipLaunchKernelGGL((k_apply_kepler<kChunkK, 4>), gk, dim3(kChunkK * 4), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_apply_kepler<kChunkK, 1>), gk, dim3(kChunkK), 0, st, a);
     return hipGetLastError();
 }
 
@@ -1307,6 +1309,8 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
     ok &= hipMemcpyAsync(c->d.sys_poff, T.sys_poff.data(), sizeof(long long) * nsys,
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.sys_c0, T.sys_c0.data(), sizeof(int) * T.sys_c0.size(),
+                         hipMemcpyHostToDevice, st) == hipSuccess;
+    ok &= hipMemcpyAsync(c->d.sys_k0, T.sys_k0.data(), sizeof(int) * T.sys_k0.size(),
                          hipMemcpyHostToDevice, st) == hipSuccess;
     ok &= hipMemcpyAsync(c->d.sys_e0, T.sys_e0.data(), sizeof(int) * T.sys_e0.size(),
                          hipMemcpyHostToDevice, st) == hipSuccess;

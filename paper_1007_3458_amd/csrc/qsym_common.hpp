@@ -102,13 +102,14 @@ struct Dev {
     double *x0, *y0, *z0, *vx0, *vy0, *vz0;     // state after the first kick
     double *A, *ch, *cv;                        // a_i; crude-sweep per-body terms
     double *acc;                                // kick partial sums
-    double *pm;                                 // momentum partials [chunk][3]
+    double *pm;                                 // momentum partials [Kepler-pass chunk][3]
     int *body_sys;                              // system of each body
     int *sys_off;                               // [nsys+1] first body of each system
     double *sys_m0;                             // central masses
     int4 *sys_K;                                // [2][nsys] partial-slot layout per kick shape
     long long *sys_poff;                        // offset of its partials in acc
     int *sys_c0;                                // [nsys+1] first O(N) chunk
+    int *sys_k0;                                // [nsys+1] first Kepler-pass chunk
     int4 *bchunk;                               // O(N) chunks (sys, first, count, 0)
     int4 *kchunk;                               // kChunkK-body chunks of the Kepler pass
     KickItem *items;                            // [2][max_items] kick work items

@@ -37,41 +37,36 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return r;
 }
 
-// Sums of three doubles over the first NB threads (NB a multiple of 64):
-// each wave by an xor butterfly (both partners add the same two values, so
-// every lane ends with the same bits), then the waves' totals in wave order
-// by thread 0, where the result is valid.  One barrier; the same bits for
-// the same inputs in every kernel that sums chunks of NB bodies.  lds holds
-// 3 NB / 64 doubles; every thread of the workgroup calls it.
-template <int NB>
-__device__ __forceinline__ void chunk_sum3(double v[3], double *lds)
+// Momentum partials: one per Kepler-pass chunk of kChunkK = 64 bodies (a
+// wave's worth), the sum over the chunk by an xor butterfly within the wave
+// (both partners add the same two values, so every lane ends with the same
+// bits).  A workgroup over a kChunk-body chunk writes the partials of its
+// four quarters, wave w the one of quarter w: the same bits as a
+// workgroup over that quarter alone.
+__device__ __forceinline__ void wave_sum3(double v[3])
 {
-    const int t = threadIdx.x;
-    if (t < NB) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const double p0 = __shfl_xor(v[0], o, 64);
-            const double p1 = __shfl_xor(v[1], o, 64);
-            const double p2 = __shfl_xor(v[2], o, 64);
-            v[0] += p0;
-            v[1] += p1;
-            v[2] += p2;
-        }
-        if ((t & 63) == 0) {
-            lds[3 * (t >> 6)] = v[0];
-            lds[3 * (t >> 6) + 1] = v[1];
-            lds[3 * (t >> 6) + 2] = v[2];
-        }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double p0 = __shfl_xor(v[0], o, 64);
+        const double p1 = __shfl_xor(v[1], o, 64);
+        const double p2 = __shfl_xor(v[2], o, 64);
+        v[0] += p0;
+        v[1] += p1;
+        v[2] += p2;
     }
-    __syncthreads();
-    if (t == 0) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            double a = lds[k];
-            for (int w = 1; w < NB / 64; ++w) a += lds[3 * w + k];
-            v[k] = a;
-        }
-    }
+}
+
+// partials of the quarters of O(N) chunk bc (workgroup of kChunk threads,
+// thread t holds body bc.y + t or zeros)
+__device__ __forceinline__ void chunk_momentum(const Dev &d, int4 bc, double p[3])
+{
+    static_assert(kChunk == 4 * kChunkK && kChunkK == 64, "a chunk is four Kepler-pass chunks");
+    wave_sum3(p);
+    const int t = threadIdx.x, w = t >> 6;
+    const int s = bc.x;
+    const int q = d.sys_k0[s] + (bc.y - d.sys_off[s]) / kChunkK + w;
+    if ((t & 63) == 0 && w * kChunkK < bc.z && q < d.sys_k0[s + 1])
+        for (int k = 0; k < 3; ++k) d.pm[3 * q + k] = p[k];
 }
 
 // LDS written by some lanes of a wave and read by others: the wave's LDS
@@ -119,7 +114,7 @@ __device__ __forceinline__ void wg_finish(unsigned long long *rec)
 // every wave of every workgroup.
 __device__ void system_momentum(const Dev &d, int s, double P[3])
 {
-    const int c0 = d.sys_c0[s], c1 = d.sys_c0[s + 1];
+    const int c0 = d.sys_k0[s], c1 = d.sys_k0[s + 1];
     const int lane = threadIdx.x & 63;
     double a[3] = {0.0, 0.0, 0.0};
     for (int c = c0 + lane; c < c1; c += 64) {
@@ -147,7 +142,6 @@ __device__ void system_momentum(const Dev &d, int s, double P[3])
 // ------------------------------------------------------------------------
 __global__ __launch_bounds__(kChunk) void k_momentum(Dev d)
 {
-    __shared__ double lds[kChunk];
     const int4 bc = d.bchunk[blockIdx.x];
     const int t = threadIdx.x;
     const int i = bc.y + t;
@@ -158,9 +152,7 @@ __global__ __launch_bounds__(kChunk) void k_momentum(Dev d)
         p[1] = mi * d.vy[i];
         p[2] = mi * d.vz[i];
     }
-    chunk_sum3<kChunk>(p, lds);
-    if (t == 0)
-        for (int k = 0; k < 3; ++k) d.pm[3 * blockIdx.x + k] = p[k];
+    chunk_momentum(d, bc, p);
 }
 
 // ------------------------------------------------------------------------
@@ -208,9 +200,7 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
             p[1] = mi * d.vy[i];
             p[2] = mi * d.vz[i];
         }
-        chunk_sum3<kChunk>(p, lds);
-        if (t == 0)
-            for (int k = 0; k < 3; ++k) d.pm[3 * blockIdx.x + k] = p[k];
+        chunk_momentum(d, bc, p);
         if (blockIdx.x == 0 && t == 0) d.ctr[C_OVERFLOW] += 1;
         return;
     }
@@ -1065,7 +1055,6 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
     // p-th thread group of BS sums every P-th slot from the p-th for the
     // chunk's consecutive bodies, and the P shares are added in order.  The
     // per-body steps then run on the first BS threads.
-    __shared__ double lds[BS * P];
     __shared__ double share[P > 1 ? P : 1][3][BS];
     __shared__ unsigned int hist[kHist];
     __shared__ unsigned int kmax, krestart;
@@ -1143,10 +1132,13 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
         mom[2] = mi * vz;
     }
     if (a.momentum) {
-        // the chunk's bodies are on the first BS threads (as in k_momentum)
-        chunk_sum3<BS>(mom, lds);
-        if (t == 0)
-            for (int k = 0; k < 3; ++k) d.pm[3 * blockIdx.x + k] = mom[k];
+        // the chunk's bodies are on the first wave (BS = kChunkK)
+        static_assert(BS == kChunkK, "one momentum partial per Kepler-pass chunk");
+        if (t < 64) {
+            wave_sum3(mom);
+            if (t == 0)
+                for (int k = 0; k < 3; ++k) d.pm[3 * blockIdx.x + k] = mom[k];
+        }
     }
     __syncthreads();
     if (a.do_kep) {
