@@ -373,17 +373,19 @@ __device__ __forceinline__ void pair64(const double4 &pj, double xi, double yi, 
 
 // FP32 pair term on an FP64 separation: the differences and r^2 stay FP64
 // (an FP64 add or fma costs the same issue slot as an FP32 one on this
-// chip, and r^2 in FP64 needs one conversion instead of three), only
-// m r^-3 is formed in FP32 from the hardware rsq (no refinement), and the
-// sum is accumulated in FP64.  The 1e-24 seed keeps the own pair finite
-// (r^-3 = 1e36 < FLT_MAX) and changes no physical pair.
-__device__ __forceinline__ void pair32(const double4 &pj, float mj, double xi, double yi, double zi,
+// chip, and r^2 in FP64 needs one conversion instead of three), only r^-3
+// is formed in FP32 from the hardware rsq (no refinement); it is widened
+// once and multiplied by the FP64 G m (the product of a float and a
+// double loses nothing a float product would keep, and saves the mass's
+// narrowing), and the sum is accumulated in FP64.  The 1e-24 seed keeps
+// the own pair finite (r^-3 = 1e36 < FLT_MAX) and changes no physical pair.
+__device__ __forceinline__ void pair32(const double4 &pj, double xi, double yi, double zi,
                                        double &ax, double &ay, double &az, double &r2)
 {
     const double dx = pj.x - xi, dy = pj.y - yi, dz = pj.z - zi;
     r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, 1e-24)));
     const float y = __builtin_amdgcn_rsqf((float)r2);
-    const double ms = (double)(mj * (y * y * y));
+    const double ms = pj.w * (double)(y * y * y);
     ax = fma(ms, dx, ax);
     ay = fma(ms, dy, ay);
     az = fma(ms, dz, az);
@@ -519,14 +521,13 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
 #pragma unroll 4
                 for (int jj = 0; jj < ntj; ++jj) {
                     const double4 pj = sj[jj];
-                    const float mjf = (float)pj.w;
 #pragma unroll
                     for (int u = 0; u < IPL; ++u) {
                         double r2;
                         if constexpr (PREC == 0)
                             pair64(pj, xi[u], yi[u], zi[u], seed, c158, c32, ax[u], ay[u], az[u], r2);
                         else
-                            pair32(pj, mjf, xi[u], yi[u], zi[u], ax[u], ay[u], az[u], r2);
+                            pair32(pj, xi[u], yi[u], zi[u], ax[u], ay[u], az[u], r2);
                         if (r2 < th2[u]) {
                             const unsigned k = atomicAdd(&qn, 1u);
                             if (k < (unsigned)kCrudeQ)
@@ -552,11 +553,10 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
 #pragma unroll 4
             for (int jj = 0; jj < ntj; ++jj) {
                 const double4 pj = sj[jj];
-                const float mjf = (float)pj.w;
 #pragma unroll
                 for (int u = 0; u < IPL; ++u) {
                     double r2;
-                    pair32(pj, mjf, xi[u], yi[u], zi[u], ax[u], ay[u], az[u], r2);
+                    pair32(pj, xi[u], yi[u], zi[u], ax[u], ay[u], az[u], r2);
                 }
             }
         }
@@ -647,18 +647,18 @@ __device__ __forceinline__ void pair_sym64(double xj, double yj, double zj, doub
     fz = fma(-msi, dz, fz);
 }
 
-// FP32 form: r^-3 from the FP32 rsq on the FP64 r^2 (as pair32)
+// FP32 form: r^-3 from the FP32 rsq on the FP64 r^2, widened once and
+// multiplied by the FP64 G m of either body (as pair32)
 __device__ __forceinline__ void pair_sym32(double xj, double yj, double zj, double gmj, double xi,
-                                           double yi, double zi, float mif, bool keep, double &ax,
+                                           double yi, double zi, double gmi, bool keep, double &ax,
                                            double &ay, double &az, double &fx, double &fy,
                                            double &fz, double &r2)
 {
     const double dx = xj - xi, dy = yj - yi, dz = zj - zi;
     r2 = fma(dz, dz, fma(dy, dy, fma(dx, dx, 1e-24)));
     const float y = __builtin_amdgcn_rsqf((float)r2);
-    float r3 = y * y * y;
-    if (!keep) r3 = 0.0f;
-    const double msj = (double)((float)gmj * r3), msi = (double)(mif * r3);
+    const double r3 = keep ? (double)(y * y * y) : 0.0;
+    const double msj = gmj * r3, msi = gmi * r3;
     ax = fma(msj, dx, ax);
     ay = fma(msj, dy, ay);
     az = fma(msj, dz, az);
@@ -680,7 +680,7 @@ template <int MODE, int PREC, int IPL, int M0, int M1>
 __device__ __forceinline__ void sym_subtile(const double *sx, const double *sy, const double *sz,
                                             const double *sm, int lane, const double *xi,
                                             const double *yi, const double *zi, const double *gmi,
-                                            const float *mif, const double *th2, const int *lt,
+                                            const double *th2, const int *lt,
                                             double seed, double c158, double c32, double *ax,
                                             double *ay, double *az, double &fx, double &fy,
                                             double &fz, int *qi, int *qj, unsigned *qn, int ib,
@@ -702,7 +702,7 @@ __device__ __forceinline__ void sym_subtile(const double *sx, const double *sy, 
                 pair_sym64(xj, yj, zj, gmj, xi[u], yi[u], zi[u], gmi[u], seed, c158, c32, keep,
                            ax[u], ay[u], az[u], fx, fy, fz, r2);
             else
-                pair_sym32(xj, yj, zj, gmj, xi[u], yi[u], zi[u], mif[u], keep, ax[u], ay[u], az[u],
+                pair_sym32(xj, yj, zj, gmj, xi[u], yi[u], zi[u], gmi[u], keep, ax[u], ay[u], az[u],
                            fx, fy, fz, r2);
             if constexpr (MODE != 0) {
                 if (keep && r2 < th2[u]) {
@@ -825,7 +825,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
         // lane group u of wave w holds i = ib + 64 (IPL w + u) + lane
         double xi[IPL], yi[IPL], zi[IPL], gmi[IPL], hi[IPL], Ai[IPL], vi[IPL];
         double ax[IPL], ay[IPL], az[IPL], th2[IPL];
-        float mif[IPL];
         int iu[IPL], lt[IPL];
         bool oku[IPL];
 #pragma unroll
@@ -838,7 +837,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
             yi[u] = oku[u] ? d.y[i] : kFar;
             zi[u] = oku[u] ? d.z[i] : kFar;
             gmi[u] = oku[u] ? G * d.m[i] : 0.0;
-            mif[u] = (float)gmi[u];
             hi[u] = Ai[u] = vi[u] = 0.0;
             if (MODE && oku[u]) {
                 hi[u] = d.ch[i];
@@ -915,15 +913,15 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
                     // nothing to add
                 } else if (rel >= 64 * IPL) {
                     sym_subtile<MODE, PREC, IPL, SYM_FULL, SYM_FULL>(
-                        px, py, pz, pm, lane, xi, yi, zi, gmi, mif, th2, lt, seed, c158, c32, ax, ay,
+                        px, py, pz, pm, lane, xi, yi, zi, gmi, th2, lt, seed, c158, c32, ax, ay,
                         az, fx, fy, fz, qi, qj, &qn, ib, jt + 64 * sub);
                 } else if (IPL == 2 && rel == 64) {
                     sym_subtile<MODE, PREC, IPL, SYM_FULL, SYM_DIAG>(
-                        px, py, pz, pm, lane, xi, yi, zi, gmi, mif, th2, lt, seed, c158, c32, ax, ay,
+                        px, py, pz, pm, lane, xi, yi, zi, gmi, th2, lt, seed, c158, c32, ax, ay,
                         az, fx, fy, fz, qi, qj, &qn, ib, jt + 64 * sub);
                 } else {   // rel == 0
                     sym_subtile<MODE, PREC, IPL, SYM_DIAG, SYM_SKIP>(
-                        px, py, pz, pm, lane, xi, yi, zi, gmi, mif, th2, lt, seed, c158, c32, ax, ay,
+                        px, py, pz, pm, lane, xi, yi, zi, gmi, th2, lt, seed, c158, c32, ax, ay,
                         az, fx, fy, fz, qi, qj, &qn, ib, jt + 64 * sub);
                 }
                 wpart[wv][0][64 * sub + lane] = fx;
