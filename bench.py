@@ -320,6 +320,8 @@ def main():
                     help="precision 1: skip the FP64 run on the same initial conditions")
     ap.add_argument("--no-forms", action="store_true",
                     help="precision 0: skip the FP32 form's run on the same initial conditions")
+    ap.add_argument("--no-balance", action="store_true",
+                    help="skip the load-balance pass (workgroup records) after the timed run")
     ap.add_argument("--swapped", action="store_true",
                     help="encounter-free steps with E_Kep and E_Int swapped (one kick per step)")
     ap.add_argument("--sweep", choices=["fused", "grid"], default="fused",
@@ -503,8 +505,9 @@ def main():
                               "achieved_tflops": ep * FLOP_ENERGY_PAIR / (r["energy_us"] * 1e-6) / 1e12,
                               "frac_fp64_peak": ep * FLOP_ENERGY_PAIR / (r["energy_us"] * 1e-6) / 1e12
                               / FP64_PEAK_TFLOPS}
-    out["load_balance"] = balance_report(ctx, args.tau, 10 if args.workload != "disk128k" else 4,
-                                         args.swapped)
+    if not args.no_balance:
+        out["load_balance"] = balance_report(ctx, args.tau, 10 if args.workload != "disk128k" else 4,
+                                             args.swapped)
     if args.workload == "batch" and not args.swapped:
         rep = oracle_energy_report(systems, args.tau, warmup, steps, r["dEmax"])
         if rep:

@@ -45,10 +45,9 @@ struct Layout {
     size_t off_sysoff = 0, off_sysm0 = 0, off_sysS = 0, off_syspoff = 0, off_sysc0 = 0, off_sysk0 = 0;
     size_t off_bchunk = 0, off_kchunk = 0, off_items = 0, off_eitems = 0, off_syse0 = 0, off_cand = 0;
     size_t off_enc = 0, off_syseoff = 0, off_sysecnt = 0, off_setcount = 0, off_setstart = 0, off_setmem = 0, off_setrc = 0, off_setlist = 0;
-    size_t off_bigsys = 0, off_sysgoff = 0, off_gsa = 0, off_bk = 0, off_krow = 0;
+    size_t off_sysgoff = 0, off_gsa = 0, off_bk = 0, off_krow = 0;
     long long krow_cap = 1;    // rows of the balanced-row kick shape, per kick
     long long gsa_slots = 0;   // global set-partition scratch (64-bit slots)
-    int nbigcap = 0;           // systems that may need it
     size_t off_gbar = 0, off_hpart = 0;
     size_t off_swcnt = 0, off_swslot = 0, off_swrec = 0, off_swlarge = 0, off_syssw = 0,
            off_swpart = 0;
@@ -157,7 +156,6 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     L.ecap = 0;
     L.setcap = 0;
     L.gsa_slots = 0;
-    L.nbigcap = 0;
     for (int s = 0; s < nsys; ++s) {
         const long long n = off[s + 1] - off[s];
         L.ecap += sys_enc_cap(n);
@@ -165,7 +163,6 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
         if (n > 0) L.setcap += n / 2 + 1;
         if (sys_enc_cap(n) > kCapE) {
             L.gsa_slots += gs_slots(n);
-            ++L.nbigcap;
         }
     }
     L.ecap = std::max<long long>(L.ecap, 1);
@@ -206,7 +203,6 @@ Layout make_layout(const qsym_params &p, const std::vector<long long> &off)
     take(L.off_setmem, (size_t)L.memcap * sizeof(int));
     take(L.off_setrc, (size_t)L.setcap * D);
     take(L.off_setlist, (size_t)L.setcap * sizeof(int));
-    take(L.off_bigsys, (size_t)std::max(nsys, 1) * sizeof(int));
     take(L.off_sysgoff, (size_t)std::max(nsys, 1) * sizeof(long long));
     take(L.off_gsa, (size_t)L.gsa_slots * sizeof(unsigned long long));
     take(L.off_bk, 6 * (size_t)L.np * D);
@@ -288,7 +284,6 @@ Dev bind(char *base, const Layout &L)
     d.gbar = (unsigned *)(base + L.off_gbar);
     d.hpart = (double *)(base + L.off_hpart);
     d.setcap = (int)L.setcap;
-    d.big_sys = (int *)(base + L.off_bigsys);
     d.sys_goff = (long long *)(base + L.off_sysgoff);
     d.gsa = (unsigned long long *)(base + L.off_gsa);
     d.bk = (double *)(base + L.off_bk);
@@ -1095,13 +1090,6 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
         SetsArgs sa{c->d, c->p.aH, c->p.planet_mass};
         hipLaunchKernelGGL(k_sets, dim3(c->nsys), dim3(kSetsThreads), 0, st, sa);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // systems with more pairs than LDS holds, in global memory (only
-        // systems whose segment exceeds kCapE can have them)
-        if (c->L.nbigcap > 0) {
-            hipLaunchKernelGGL(k_sets_big, dim3(std::min(c->L.nbigcap, 128)), dim3(kSetsBigThreads), 0,
-                               st, sa);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
     }
     // 5-7: corrections and Hermite per set
     {

@@ -10,7 +10,6 @@ constexpr int kChunk = 256;        // bodies per workgroup of the O(N) kernels
 constexpr int kChunkK = 64;        // bodies per workgroup of the Kepler pass
 constexpr int kCapE = 4096;        // encounter pairs of one system partitioned on chip (LDS)
 constexpr int kCapU = 2 * kCapE;   // bodies of one system taking part in encounters (LDS)
-constexpr int kSetsBigThreads = 1024;   // workgroup of the global-memory set partition
 constexpr int kHist = 32;
 // The Kepler pass's statistics (iteration histogram, total, largest) are
 // kept in kStatStripes copies, kStatStride entries (512 B) apart: the
@@ -45,8 +44,7 @@ enum Ctr {
     C_NBIG,       // larger sets (one workgroup each), last step
     C_WHOLE,      // systems integrated whole (all steps)
     C_NLARGE,     // grid sweep: bodies on the large list, last step
-    C_NBIGSYS,    // systems whose sets are partitioned in global memory, last step
-    C_TBIGSYS,    // the same, all steps
+    C_TBIGSYS,    // systems whose sets were partitioned in global memory, all steps
     C_FALLBACK,   // steps whose candidate list overflowed: all-pairs fine sweep instead
     C_OVERFLOW,   // steps left undone because a system's encounter pairs overflowed
     C_COUNT
@@ -125,7 +123,6 @@ struct Dev {
     double *set_rc;                             // [setcap] r_crit per set
     int *set_list;                              // [setcap] small sets from 0 up, big from the end down
     int setcap;                                 // set slots
-    int *big_sys;                               // [nsys] systems for the global set partition
     long long *sys_goff;                        // [nsys] their scratch offset in gsa (-1: none)
     unsigned long long *gsa;                    // global set-partition scratch
     double *bk;                                 // [6][np] state at the start of the step

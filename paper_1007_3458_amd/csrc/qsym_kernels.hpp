@@ -225,7 +225,6 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
         d.ctr[C_NSMALL] = 0;
         d.ctr[C_NBIG] = 0;
         d.ctr[C_NLARGE] = 0;
-        d.ctr[C_NBIGSYS] = 0;
         d.gbar[0] = 0u;
         d.gbar[1] = 0u;
         d.gbar[2] = 0u;
@@ -1435,6 +1434,10 @@ struct SetsArgs {
     double planet_mass;   // > 0: whole-system rule on (see k_sets)
 };
 
+template <int T>
+__device__ void sets_global(const SetsArgs &a, int sys, int *tmp, int &base_set, int &base_mem,
+                            int &s_whole);
+
 // binary search of v in the ascending u[0..n)
 __device__ __forceinline__ int lower_rank(const unsigned *u, int n, unsigned v)
 {
@@ -1474,8 +1477,8 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
         return;
     }
     if (cnt > kCapE) {
-        // beyond LDS: k_sets_big partitions this system in global memory
-        if (t == 0) d.big_sys[(int)atomicAdd(&d.ctr[C_NBIGSYS], 1ull)] = sys;
+        // beyond LDS: the same partition in the system's global scratch
+        sets_global<kSetsThreads>(a, sys, tmp, base_set, base_mem, s_whole);
         return;
     }
     const int ne = cnt;
@@ -1695,9 +1698,10 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
 }
 
 // ------------------------------------------------------------------------
-// Set partition of the systems with more encounter pairs than LDS holds
-// (Sec. 2.3 step 4, the same result as k_sets): one 1024-thread workgroup
-// per system, everything in the system's global scratch -- the bodies in
+// Set partition of a system with more encounter pairs than LDS holds
+// (Sec. 2.3 step 4, the same result as k_sets), run by that system's
+// workgroup of k_sets (T threads) with everything in the system's global
+// scratch -- the bodies in
 // encounters from a bitmap of the system (ascending, ranked by popcount
 // prefixes), union-find with union by minimum, roots numbered in ascending
 // order, members sorted by (root, body) with a bitonic sort, r_crit =
@@ -1715,16 +1719,13 @@ __device__ __forceinline__ int ld_i32(const int *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kSetsBigThreads) void k_sets_big(SetsArgs a)
+template <int T>
+__device__ void sets_global(const SetsArgs &a, int sys, int *tmp, int &base_set, int &base_mem,
+                            int &s_whole)
 {
     const Dev &d = a.d;
-    constexpr int T = kSetsBigThreads;
-    __shared__ int tmp[T / 64 + 1];
-    __shared__ int base_set, base_mem, s_whole;
     const int t = threadIdx.x;
-    const int nbs = (int)d.ctr[C_NBIGSYS];
-    for (int q = blockIdx.x; q < nbs; q += gridDim.x) {
-        const int sys = d.big_sys[q];
+    {
         const int ne = d.sys_ecnt[sys];
         const int2 *enc = d.enc + d.sys_eoff[sys];
         const int so = d.sys_off[sys], nsb = d.sys_off[sys + 1] - so;
@@ -1826,7 +1827,7 @@ __global__ __launch_bounds__(kSetsBigThreads) void k_sets_big(SetsArgs a)
                     atomicAdd(&d.ctr[C_TBIGSYS], 1ull);
                 }
                 __syncthreads();
-                continue;
+                return;
             }
         }
         // members sorted by (root rank, rank)
@@ -1913,7 +1914,7 @@ __global__ __launch_bounds__(kSetsBigThreads) void k_sets_big(SetsArgs a)
             atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
             atomicAdd(&d.ctr[C_TBIGSYS], 1ull);
         }
-        __syncthreads();   // the LDS words serve the next system
+        __syncthreads();
     }
 }
 
