@@ -356,7 +356,7 @@ struct qsym_ctx {
     long long busy_calls[kPhases] = {};
     int busy_units = 0;
     bool guess_loaded = false;
-    int grid_blocks = 256;   // workgroups of k_hermite_grid: the device's compute units
+    int grid_blocks = 256;   // workgroups of k_hermite: the device's compute units
     int cus = 256;           // the device's compute units
     int apply_parts = 1;     // threads per body of the partial-sum reduction (1 or 4)
     double tau_crude = 0.0;  // |tau| of the crude sweep being enqueued
@@ -1094,15 +1094,11 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
     // 5-7: corrections and Hermite per set
     {
         Timer tm(c, P_HERMITE);
+        // one workgroup per compute unit, all resident: the grid phase's
+        // barriers need them together
         HermArgs ha{c->d, tau, c->p.G, c->p.epsH, c->p.eta, c->p.eta_s, c->p.max_substeps,
-                    rec_slot(c, 256, st)};
-        hipLaunchKernelGGL(k_hermite, dim3(256), dim3(kHermThreads), 0, st, ha);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        // sets above kCoopMin members: the whole grid on one set at a time
-        // (one workgroup per compute unit, so every workgroup is resident)
-        ha.rec = nullptr;
-        GridArgs ga{ha, c->d.gbar, c->d.hpart};
-        hipLaunchKernelGGL(k_hermite_grid, dim3(c->grid_blocks), dim3(kGridThreads), 0, st, ga);
+                    rec_slot(c, c->grid_blocks, st), c->d.gbar, c->d.hpart};
+        hipLaunchKernelGGL(k_hermite, dim3(c->grid_blocks), dim3(kHermThreads), 0, st, ha);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // 9: kick tau/2 (all pairs), applied with the momentum partials
@@ -1265,12 +1261,12 @@ int qsym_create(const qsym_params *p, int32_t nsys, const int64_t *offsets, cons
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             return bail(QSYM_EHIP, "hipDeviceGetAttribute");
-        // k_hermite_grid's barriers need every workgroup resident at once:
+        // the Hermite's grid phase needs every workgroup resident at once:
         // one per compute unit, and only if the kernel fits one per unit
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_hermite_grid, kGridThreads, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_hermite, kHermThreads, 0) !=
                 hipSuccess || occ < 1)
-            return bail(QSYM_EHIP, "k_hermite_grid does not fit a compute unit");
+            return bail(QSYM_EHIP, "k_hermite does not fit a compute unit");
         c->grid_blocks = std::max(1, std::min(cus, kGridMax));
         c->cus = std::max(1, cus);
     }

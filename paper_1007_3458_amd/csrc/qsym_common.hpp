@@ -24,6 +24,7 @@ constexpr int kSetsThreads = 256;  // workgroup of the set-partition kernel
 constexpr int kHermThreads = 512;  // workgroup of the Hermite kernel
 constexpr int kHermWave = 64;      // lanes of the one-wave Hermite
 constexpr int kWaveMax = 16;       // sets up to this size run on one wave, larger on a workgroup
+constexpr int kCoopMin = 256;      // sets above this size run on the whole grid
 constexpr int kGridMax = 1024;     // largest grid of the grid-wide Hermite
 constexpr double kPi = 3.14159265358979323846;
 
@@ -42,6 +43,7 @@ enum Ctr {
     C_NU,         // bodies in encounters, last step
     C_NSMALL,     // sets of at most kWaveMax members (one wave each), last step
     C_NBIG,       // larger sets (one workgroup each), last step
+    C_NGRID,      // sets above kCoopMin members (the grid phase), last step
     C_WHOLE,      // systems integrated whole (all steps)
     C_NLARGE,     // grid sweep: bodies on the large list, last step
     C_TBIGSYS,    // systems whose sets were partitioned in global memory, all steps
@@ -127,7 +129,7 @@ struct Dev {
     unsigned long long *gsa;                    // global set-partition scratch
     double *bk;                                 // [6][np] state at the start of the step
     int *krow;                                  // [2][rows] items per row (balanced-row kick)
-    unsigned *gbar;                             // grid barrier of k_hermite_grid (3 words)
+    unsigned *gbar;                             // grid barrier of the Hermite's grid phase (3 words)
     double *hpart;                              // [2][kGridMax] its per-block step minima
     int *sw_cnt;                                // grid sweep: [sw_nb] bucket counts
     int *sw_slot;                               // [sw_nb][kSweepCap] bodies per bucket

@@ -224,6 +224,7 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
         d.ctr[C_NU] = 0;
         d.ctr[C_NSMALL] = 0;
         d.ctr[C_NBIG] = 0;
+        d.ctr[C_NGRID] = 0;
         d.ctr[C_NLARGE] = 0;
         d.gbar[0] = 0u;
         d.gbar[1] = 0u;
@@ -1616,6 +1617,7 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
                     d.set_list[(int)atomicAdd(&d.ctr[C_NSMALL], 1ull)] = bs;
                 else
                     d.set_list[d.setcap - 1 - (int)atomicAdd(&d.ctr[C_NBIG], 1ull)] = bs;
+                if (ns > kCoopMin) atomicAdd(&d.ctr[C_NGRID], 1ull);
                 atomicMax(&d.ctr[C_MAXSET], (unsigned long long)ns);
                 atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
                 atomicAdd(&d.ctr[C_WHOLE], 1ull);
@@ -1676,6 +1678,7 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
         const int n = (sid + 1 < nsets ? (int)rp[sid + 1] : nu) - (int)rp[sid];
         d.set_count[bs + sid] = n;
         if ((unsigned)n > big) big = (unsigned)n;
+        if (n > kCoopMin) atomicAdd(&d.ctr[C_NGRID], 1ull);   // rare: the grid phase
         flag[sid] = n <= kWaveMax ? 1 : 0x10000;
     }
     __syncthreads();
@@ -1821,6 +1824,7 @@ __device__ void sets_global(const SetsArgs &a, int sys, int *tmp, int &base_set,
                         d.set_list[(int)atomicAdd(&d.ctr[C_NSMALL], 1ull)] = bs;
                     else
                         d.set_list[d.setcap - 1 - (int)atomicAdd(&d.ctr[C_NBIG], 1ull)] = bs;
+                    if (nsb > kCoopMin) atomicAdd(&d.ctr[C_NGRID], 1ull);
                     atomicMax(&d.ctr[C_MAXSET], (unsigned long long)nsb);
                     atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
                     atomicAdd(&d.ctr[C_WHOLE], 1ull);
@@ -1891,6 +1895,7 @@ __device__ void sets_global(const SetsArgs &a, int sys, int *tmp, int &base_set,
             const int n = (sid + 1 < nsets ? ls[sid + 1] : nu) - ls[sid];
             d.set_count[bs + sid] = n;
             big = max(big, n);
+            if (n > kCoopMin) atomicAdd(&d.ctr[C_NGRID], 1ull);
             smallf[sid] = n <= kWaveMax ? 1 : 0;
             bigf[sid] = n <= kWaveMax ? 0 : 1;
         }
@@ -2008,10 +2013,10 @@ struct HermArgs {
     double tau, G, epsH, eta, eta_s;
     int max_substeps;
     unsigned long long *rec = nullptr;   // workgroup records (profiling), else null
+    unsigned *bar = nullptr;     // grid barrier: [0] arrivals (cumulative), [1] generation, [2] abort
+    double *hpart = nullptr;     // [2][gridDim] per-workgroup step minima of the grid sets
 };
 
-constexpr int kCoopMin = 256;       // larger sets run on the whole grid (k_hermite_grid)
-constexpr int kGridThreads = 256;   // workgroup of k_hermite_grid
 
 constexpr int kHermLds = kHermThreads;   // members of one set staged in LDS
 
@@ -2495,15 +2500,22 @@ __device__ void hermite_set_block(const HermArgs &a, int sidx, const SetLds &S, 
     fail_out = fail;
 }
 
-// Sec. 2.3 steps 5-7 for every set of at most kCoopMin members.  Sets of
-// more than kWaveMax members first, one workgroup each (hermite_set_block:
-// the set staged in LDS, each member's state in the registers of its lane
-// group); then the small sets, one wave each (hermite_set_wave), both in a
-// fixed assignment; every set is integrated on its own, so the assignment
-// changes nothing in the results.  Larger sets run on the whole grid
-// (k_hermite_grid): from about 250 members its two grid barriers per
+template <int NT>
+__device__ void hermite_grid_sets(const HermArgs &a, double *red, int *s_ok);
+
+// Sec. 2.3 steps 5-7 for every set.  Sets of more than kWaveMax and at most
+// kCoopMin members first, one workgroup each (hermite_set_block: the set
+// staged in LDS, each member's state in the registers of its lane group);
+// then the small sets, one wave each (hermite_set_wave), both in a fixed
+// assignment; every set is integrated on its own, so the assignment changes
+// nothing in the results.  Then, when the step has any, the sets above
+// kCoopMin members on the whole grid, one after the other
+// (hermite_grid_sets): from about 250 members its two grid barriers per
 // substep cost less than the n^2 / 512 pair terms per lane of one
-// workgroup.
+// workgroup.  The grid is one workgroup per compute unit, all resident
+// (checked when the context is created), and the sets' count is known to
+// every workgroup from the set kernel, so a step without such sets has no
+// grid barrier at all.
 __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
 {
     static_assert(kCoopMin <= kHermThreads && kHermThreads <= kHermLds,
@@ -2525,7 +2537,7 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
     int nsub_b = 0, fail_b = 0;   // statistics of thread 0, added after the loop
     for (int q = blockIdx.x; q < nbig; q += nwg) {
         const int sidx = d.set_list[d.setcap - 1 - q];
-        if (d.set_count[sidx] > kCoopMin) continue;   // k_hermite_grid takes it
+        if (d.set_count[sidx] > kCoopMin) continue;   // the grid phase takes it
         int nsub, fail;
         hermite_set_block(a, sidx, SetLds{s_x, s_y, s_z, s_u, s_v, s_w, s_m}, lds, nsub, fail);
         if (t == 0) {
@@ -2563,6 +2575,10 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
         atomicAdd(&d.ctr[C_TSUB], (unsigned long long)nsub_w);
     }
     if (lane == 0 && fail_w) latch(d.ctr, S_HERMITE);
+    if (d.ctr[C_NGRID] != 0) {
+        __shared__ int s_ok;
+        hermite_grid_sets<kHermThreads>(a, lds, &s_ok);
+    }
     wg_finish(a.rec);
 }
 
@@ -2570,7 +2586,7 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
 // ------------------------------------------------------------------------
 // Sets of more than kCoopMin members (the giant sets a nearly parabolic
 // body makes through its Hill radius, or a whole system): the same steps
-// as k_hermite, spread over the whole grid.  Member k belongs to lane group
+// as hermite_set_block, spread over the whole grid of k_hermite.  Member k belongs to lane group
 // k mod NG (L lanes, NG = grid lanes / L); its pair sums run over the staged
 // set in global memory; grid-wide barriers separate the phases of a
 // substep, and the step size is the minimum of per-block partial minima
@@ -2579,11 +2595,6 @@ __global__ __launch_bounds__(kHermThreads) void k_hermite(HermArgs a)
 // that runs out raises an abort flag that every block polls, every block
 // leaves, and the Hermite status bit is latched.
 // ------------------------------------------------------------------------
-struct GridArgs {
-    HermArgs h;
-    unsigned *bar;      // [0] arrivals (cumulative), [1] generation, [2] abort
-    double *hpart;      // [2][gridDim] per-block step minima
-};
 
 // longest wait at one barrier before giving up, in ticks of the 100 MHz
 // real-time counter (10 s: far beyond any phase of a legitimate set)
@@ -2599,7 +2610,7 @@ constexpr unsigned long long kGridWaitTicks = 1000000000ull;
 // fence in every wave instead costs thousands of whole-L2 write-backs and
 // invalidations per barrier.  Returns false when the wait ran out or
 // another block aborted.
-__device__ bool grid_sync(const GridArgs &ga, unsigned &phase, int *s_ok)
+__device__ bool grid_sync(unsigned *bar, unsigned &phase, int *s_ok)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -2607,15 +2618,15 @@ __device__ bool grid_sync(const GridArgs &ga, unsigned &phase, int *s_ok)
         int ok = 1;
         const unsigned target = phase + 1;
         const unsigned prev =
-            __hip_atomic_fetch_add(&ga.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (prev + 1 == gridDim.x * target) {
-            __hip_atomic_store(&ga.bar[1], target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[1], target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
             // relaxed polls (an acquire load would invalidate the caches on
             // every poll); the fence after the wait is the acquire
-            while (__hip_atomic_load(&ga.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (__hip_atomic_load(&ga.bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
                     __builtin_amdgcn_s_memrealtime() - t0 > kGridWaitTicks) {
                     ok = 0;
                     break;
@@ -2623,7 +2634,7 @@ __device__ bool grid_sync(const GridArgs &ga, unsigned &phase, int *s_ok)
                 __builtin_amdgcn_s_sleep(2);
             }
         }
-        if (!ok) __hip_atomic_store(&ga.bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!ok) __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __threadfence();
         *s_ok = ok;
         phase = target;
@@ -2632,30 +2643,26 @@ __device__ bool grid_sync(const GridArgs &ga, unsigned &phase, int *s_ok)
     return __builtin_amdgcn_readfirstlane(*s_ok) != 0;
 }
 
-// a failed barrier ends the kernel in this block (the others follow through
-// the abort flag) and reports the set as failed
+// a failed barrier ends the grid phase in this block (the others follow
+// through the abort flag) and reports the set as failed
 #define GSYNC()                                           \
     do {                                                  \
-        if (!grid_sync(ga, phase, &s_ok)) {               \
+        if (!grid_sync(a.bar, phase, s_ok)) {             \
             if (threadIdx.x == 0) latch(d.ctr, S_HERMITE); \
             return;                                       \
         }                                                 \
     } while (0)
 
-__global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
+template <int NT>
+__device__ void hermite_grid_sets(const HermArgs &a, double *red, int *s_ok)
 {
-    const HermArgs &a = ga.h;
     const Dev &d = a.d;
-    __shared__ double red[kGridThreads];
-    __shared__ int s_ok;
     const int t = threadIdx.x;
-    const int gtid = blockIdx.x * kGridThreads + t;
-    const int nthr = gridDim.x * kGridThreads;
+    const int gtid = blockIdx.x * NT + t;
+    const int nthr = gridDim.x * NT;
     const long long fs = d.memcap;
     unsigned phase = 0;
     int par = 0;
-    // every block reads the same status word (no kernel raises it meanwhile)
-    if (d.ctr[C_STATUS] & S_FREEZE) return;
     const int nbig = (int)d.ctr[C_NBIG];
     for (int q = 0; q < nbig; ++q) {
         const int sidx = d.set_list[d.setcap - 1 - q];
@@ -2725,14 +2732,14 @@ __global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
             }
         }
         {
-            const double bm = block_min_waves<kGridThreads>(hloc, red);
-            if (t == 0) ga.hpart[par * gridDim.x + blockIdx.x] = bm;
+            const double bm = block_min_waves<NT>(hloc, red);
+            if (t == 0) a.hpart[par * gridDim.x + blockIdx.x] = bm;
         }
         GSYNC();
         // the step minimum over the blocks' minima: one load per thread
         double h = INFINITY;
-        for (int b = t; b < (int)gridDim.x; b += kGridThreads) h = fmin(h, ga.hpart[par * gridDim.x + b]);
-        h = block_min_waves<kGridThreads>(h, red);
+        for (int b = t; b < (int)gridDim.x; b += NT) h = fmin(h, a.hpart[par * gridDim.x + b]);
+        h = block_min_waves<NT>(h, red);
         par ^= 1;
         const double sgn = a.tau >= 0.0 ? 1.0 : -1.0;
         const double T = fabs(a.tau);
@@ -2790,14 +2797,14 @@ __global__ __launch_bounds__(kGridThreads) void k_hermite_grid(GridArgs ga)
                 }
             }
             {
-                const double bm = block_min_waves<kGridThreads>(hn, red);
-                if (t == 0) ga.hpart[par * gridDim.x + blockIdx.x] = bm;
+                const double bm = block_min_waves<NT>(hn, red);
+                if (t == 0) a.hpart[par * gridDim.x + blockIdx.x] = bm;
             }
             GSYNC();
             double hnext = INFINITY;
-            for (int b = t; b < (int)gridDim.x; b += kGridThreads)
-                hnext = fmin(hnext, ga.hpart[par * gridDim.x + b]);
-            hnext = block_min_waves<kGridThreads>(hnext, red);
+            for (int b = t; b < (int)gridDim.x; b += NT)
+                hnext = fmin(hnext, a.hpart[par * gridDim.x + b]);
+            hnext = block_min_waves<NT>(hnext, red);
             par ^= 1;
             tt += h;
             ++nsub;
