@@ -84,11 +84,12 @@ __device__ __forceinline__ void latch(unsigned long long *ctr, unsigned long lon
 }
 
 // Workgroup records for the load-balance figure (profiling only; rec is
-// null otherwise): three words per workgroup of the launch, written by
-// thread 0: at the workgroup's start 1 + the compute unit (XCC id << 8 |
-// SE, SH and CU ids of HW_ID) and the 100 MHz real-time clock, after its
-// last barrier the clock again.  A workgroup that returns early leaves its
-// end (cleared) at zero.
+// null otherwise): three words per workgroup of the launch (cleared before
+// the launch): 1 + the compute unit (XCC id << 8 | SE, SH and CU ids of
+// HW_ID) and the 100 MHz real-time clock at the workgroup's start, written
+// by thread 0 when it starts, and its end, the latest of its waves' ends
+// (an atomic maximum per wave, so no barrier is added).  A workgroup that
+// returns early leaves its end at zero.
 __device__ __forceinline__ void wg_start(unsigned long long *rec)
 {
     if (rec == nullptr || threadIdx.x != 0) return;
@@ -100,12 +101,10 @@ __device__ __forceinline__ void wg_start(unsigned long long *rec)
     r[1] = __builtin_amdgcn_s_memrealtime();
 }
 
-// end of a recorded workgroup: every wave done, then thread 0 writes
 __device__ __forceinline__ void wg_finish(unsigned long long *rec)
 {
-    if (rec == nullptr) return;
-    __syncthreads();
-    if (threadIdx.x == 0) rec[3ull * blockIdx.x + 2] = __builtin_amdgcn_s_memrealtime();
+    if (rec == nullptr || (threadIdx.x & 63) != 0) return;
+    atomicMax(rec + 3ull * blockIdx.x + 2, (unsigned long long)__builtin_amdgcn_s_memrealtime());
 }
 
 // Momentum of system s summed from its chunk partials in a fixed order:
@@ -763,9 +762,20 @@ __device__ void sym_tile_exact(const KickArgs &ka, int jt, int jend, const int *
 
 // REC: the variant that writes workgroup records (profiling with records;
 // a separate instantiation, so the kernel timed otherwise carries no trace
-// of them: any extra live value changes this kernel's register allocation)
+// of them: any extra live value changes this kernel's register
+// allocation).  Its occupancy is held at the plain variant's (waves per
+// SIMD: 4 for the plain kick and the 128-thread, one-i crude kick, 3 for
+// the other crude kicks), so that its records show the timed kernel's
+// balance.
+template <int BS, int IPL, int MODE, int PREC>
+constexpr int kick_rec_waves()
+{
+    return MODE == 0 ? 4 : (IPL == 1 && BS == 128 ? 4 : 3);
+}
+
 template <int BS, int IPL, int MODE, int PREC, bool REC = false>
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_kick_sym(
+__global__ __launch_bounds__(BS)
+__attribute__((amdgpu_waves_per_eu(REC ? kick_rec_waves<BS, IPL, MODE, PREC>() : 1, 4))) void k_kick_sym(
     KickArgs ka)
 {
     static_assert(IPL == 1 || IPL == 2, "one or two i per lane");
