@@ -330,13 +330,15 @@ struct qsym_ctx {
     int nitems[2] = {0, 0};
     int grid_kick[2] = {0, 0};
     Tables T;
-    // captured steps: [0] the hybrid step, [1] the encounter-free swapped step
+    // captured steps: [0] a hybrid step's body and the drift fused with the
+    // next step's first, [1] the encounter-free swapped step, [2] a hybrid
+    // step's body and its last drift
     struct StepGraph {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         double tau = 0.0;
         bool valid = false;
-    } g[2];
+    } g[3];
     int profile = 0;   // 1: kernel timings, 2: and workgroup records
     // profiling: event pairs recorded around launches without waiting; the
     // pending pairs are read (and the events recycled) at the next flush
@@ -738,7 +740,7 @@ int upload_shape(qsym_ctx *c, int which)
     HIPCHK(c, hipMemcpyAsync(c->d.sys_K + (size_t)which * c->nsys, sysK.data(), sizeof(int4) * c->nsys,
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->g[0].valid = c->g[1].valid = false;
+    for (auto &g : c->g) g.valid = false;
     return QSYM_OK;
 }
 
@@ -977,11 +979,11 @@ struct Timer {
 // its encounter pairs
 hipError_t run_drift(qsym_ctx *c, double dt, int prepass, double tau_crude, int reset,
                      hipStream_t st, int phase, int count_step = 0, int backup = 0,
-                     int restore = 0)
+                     int restore = 0, int fused = 0)
 {
     Timer tm(c, phase);
     DriftArgs a{c->d, dt, c->p.G, tau_crude, c->p.aE, c->p.crude_safety, prepass, c->p.hill_mode,
-                reset, count_step, prepass && c->p.sweep == 1, backup, restore};
+                reset, count_step, prepass && c->p.sweep == 1, backup, restore, fused};
     hipLaunchKernelGGL(k_drift, dim3(nblocks_chunks(c)), dim3(kChunk), 0, st, a);
     return hipGetLastError();
 }
@@ -1065,13 +1067,28 @@ int fine_grid(qsym_ctx *c)
 }
 
 // one full hybrid step (Sec. 2.3) enqueued on st
-hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
+// the first drift of a hybrid step (1: drift tau/2 + per-body encounter
+// terms, reset per-step counters, copy of the state at the step's start);
+// between two steps of one call the previous step's last drift is made in
+// the same launch (fused), otherwise it is a launch of its own (last)
+hipError_t enqueue_first_drift(qsym_ctx *c, double tau, hipStream_t st, int fused)
+{
+    const double half = tau / 2.0;
+    return run_drift(c, half, 1, tau, 1, st, P_DRIFT, fused, 1, fused, fused);
+}
+
+hipError_t enqueue_last_drift(qsym_ctx *c, double tau, hipStream_t st)
+{
+    // 10: drift tau/2 (or, for a step that could not hold its encounter
+    // pairs, the state at its start)
+    return run_drift(c, tau / 2.0, 0, 0.0, 0, st, P_DRIFT2, 1, 0, 1);
+}
+
+// steps 2-9 of a hybrid step (Sec. 2.3), between its two drifts
+hipError_t enqueue_step_body(qsym_ctx *c, double tau, hipStream_t st)
 {
     hipError_t e;
     const double half = tau / 2.0;
-    // 1: drift tau/2 + per-body encounter terms, reset per-step counters,
-    // copy of the state at the step's start
-    if ((e = run_drift(c, half, 1, tau, 1, st, P_DRIFT, 0, 1, 0)) != hipSuccess) return e;
     // 2: kick tau/2 with the crude sweep
     if ((e = run_kick1(c, tau, st)) != hipSuccess) return e;
     // 2-3: apply the kick, snapshot (q0, v0), Kepler tau -> (q1, v1)
@@ -1103,10 +1120,23 @@ hipError_t enqueue_step(qsym_ctx *c, double tau, hipStream_t st)
     }
     // 9: kick tau/2 (all pairs), applied with the momentum partials
     if ((e = run_kick(c, 0, 0.0, st, P_KICK2)) != hipSuccess) return e;
-    if ((e = run_apply(c, half, 0.0, 1, 0, 0, 1, st, P_APPLY2, 0)) != hipSuccess) return e;
-    // 10: drift tau/2 (or, for a step that could not hold its encounter
-    // pairs, the state at its start)
-    return run_drift(c, half, 0, 0.0, 0, st, P_DRIFT2, 1, 0, 1);
+    return run_apply(c, half, 0.0, 1, 0, 0, 1, st, P_APPLY2, 0);
+}
+
+// body + the fused drift between this step and the next (graph of the steps
+// before a call's last), body + the last drift (graph of its last step)
+hipError_t enqueue_step_mid(qsym_ctx *c, double tau, hipStream_t st)
+{
+    hipError_t e = enqueue_step_body(c, tau, st);
+    if (e != hipSuccess) return e;
+    return enqueue_first_drift(c, tau, st, 1);
+}
+
+hipError_t enqueue_step_last(qsym_ctx *c, double tau, hipStream_t st)
+{
+    hipError_t e = enqueue_step_body(c, tau, st);
+    if (e != hipSuccess) return e;
+    return enqueue_last_drift(c, tau, st);
 }
 
 void enter(qsym_ctx *c)
@@ -1175,15 +1205,25 @@ int run_steps(qsym_ctx *c, double tau, int64_t nsteps, int kind)
     if (c->p.kepler_mode == 2 && !c->guess_loaded)
         return fail(c, QSYM_EINVAL, "kepler_mode 2 needs weights (qsym_set_guess)");
     if (nsteps == 0 || c->ntot == 0) return QSYM_OK;
-    auto enqueue = kind == 0 ? enqueue_step : enqueue_swapped;
     enter(c);
+    // a hybrid call of n steps: the first drift, then n - 1 times the step
+    // body with the fused drift between steps, then the last body and drift
     if (c->profile) {
-        for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, enqueue(c, tau, c->stream));
+        if (kind == 0) {
+            HIPCHK(c, enqueue_first_drift(c, tau, c->stream, 0));
+            for (int64_t k = 0; k < nsteps; ++k)
+                HIPCHK(c, (k + 1 < nsteps ? enqueue_step_mid : enqueue_step_last)(c, tau, c->stream));
+        } else {
+            for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, enqueue_swapped(c, tau, c->stream));
+        }
         leave(c);
         return QSYM_OK;
     }
-    auto &G = c->g[kind];
-    if (!G.valid || G.tau != tau) {
+    // captured once per tau: [swapped step], [hybrid body + fused drift],
+    // [hybrid body + last drift]
+    auto graph = [&](int slot, hipError_t (*enqueue)(qsym_ctx *, double, hipStream_t)) -> int {
+        auto &G = c->g[slot];
+        if (G.valid && G.tau == tau) return QSYM_OK;
         if (G.exec) { hipGraphExecDestroy(G.exec); G.exec = nullptr; }
         if (G.graph) { hipGraphDestroy(G.graph); G.graph = nullptr; }
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -1199,8 +1239,19 @@ int run_steps(qsym_ctx *c, double tau, int64_t nsteps, int kind)
         HIPCHK(c, hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
         G.tau = tau;
         G.valid = true;
+        return QSYM_OK;
+    };
+    int rc;
+    if (kind == 1) {
+        if ((rc = graph(1, enqueue_swapped)) != QSYM_OK) return rc;
+        for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, hipGraphLaunch(c->g[1].exec, c->stream));
+    } else {
+        if (nsteps > 1 && (rc = graph(0, enqueue_step_mid)) != QSYM_OK) return rc;
+        if ((rc = graph(2, enqueue_step_last)) != QSYM_OK) return rc;
+        HIPCHK(c, enqueue_first_drift(c, tau, c->stream, 0));
+        for (int64_t k = 0; k + 1 < nsteps; ++k) HIPCHK(c, hipGraphLaunch(c->g[0].exec, c->stream));
+        HIPCHK(c, hipGraphLaunch(c->g[2].exec, c->stream));
     }
-    for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, hipGraphLaunch(G.exec, c->stream));
     leave(c);
     return QSYM_OK;
 }

@@ -169,6 +169,7 @@ struct DriftArgs {
     int sweep_stats;   // grid crude sweep next: per-chunk sums of (a, h or h a, ve), clear its table
     int backup;        // first drift of a hybrid step: keep the state at the step's start
     int restore;       // last drift of a hybrid step: put it back when the step could not be done
+    int fused;         // the previous step's last drift (dt, counted) before this step's first
 };
 
 __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
@@ -203,15 +204,6 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
         if (blockIdx.x == 0 && t == 0) d.ctr[C_OVERFLOW] += 1;
         return;
     }
-    if (a.backup && !frozen && (int)threadIdx.x < bc.z) {
-        const int i = bc.y + threadIdx.x;
-        d.bk[i] = d.x[i];
-        d.bk[S + i] = d.y[i];
-        d.bk[2 * S + i] = d.z[i];
-        d.bk[3 * S + i] = d.vx[i];
-        d.bk[4 * S + i] = d.vy[i];
-        d.bk[5 * S + i] = d.vz[i];
-    }
     double P[3];
     system_momentum(d, s, P);
     if (a.reset && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -237,9 +229,27 @@ __global__ __launch_bounds__(kChunk) void k_drift(DriftArgs a)
     const double m0 = d.sys_m0[s];
     double sw[3] = {0.0, 0.0, 0.0};
     if (ok) {
-        const double x = d.x[i] + a.dt * (P[0] / m0);
-        const double y = d.y[i] + a.dt * (P[1] / m0);
-        const double z = d.z[i] + a.dt * (P[2] / m0);
+        double x = d.x[i], y = d.y[i], z = d.z[i];
+        if (a.fused) {
+            // the previous step's last E_Dft(dt): the same addition a launch
+            // of its own would make (a drift leaves P unchanged, so the same
+            // P serves both)
+            x = x + a.dt * (P[0] / m0);
+            y = y + a.dt * (P[1] / m0);
+            z = z + a.dt * (P[2] / m0);
+        }
+        if (a.backup && !frozen) {
+            // the state at this step's start
+            d.bk[i] = x;
+            d.bk[S + i] = y;
+            d.bk[2 * S + i] = z;
+            d.bk[3 * S + i] = d.vx[i];
+            d.bk[4 * S + i] = d.vy[i];
+            d.bk[5 * S + i] = d.vz[i];
+        }
+        x = x + a.dt * (P[0] / m0);
+        y = y + a.dt * (P[1] / m0);
+        z = z + a.dt * (P[2] / m0);
         d.x[i] = x;
         d.y[i] = y;
         d.z[i] = z;
