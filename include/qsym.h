@@ -160,8 +160,12 @@ int qsym_set_state(qsym_ctx *ctx, const double *m, const double *h, const double
 int qsym_get_state(qsym_ctx *ctx, double *q, double *v, int32_t where);
 
 /* nsteps hybrid steps of size tau (Sec. 2.3).  Asynchronous: the first call
- * for a given tau captures one step into a HIP graph that is replayed
- * nsteps times.  A negative tau integrates backwards (used with a_E = 0). */
+ * for a given tau captures the step into HIP graphs that are replayed: the
+ * step's body with the drift that ends it and begins the next (one launch;
+ * the same additions in the same order as two), and the body with the last
+ * drift, so a call is one drift launch and nsteps graph launches.  The
+ * result does not depend on how steps are split over calls.  A negative
+ * tau integrates backwards (used with a_E = 0). */
 int qsym_step(qsym_ctx *ctx, double tau, int64_t nsteps);
 /* nsteps encounter-free steps with the Keplerian and interaction operators
  * swapped (Sec. 2, after the second-order composition: without the

@@ -330,15 +330,15 @@ struct qsym_ctx {
     int nitems[2] = {0, 0};
     int grid_kick[2] = {0, 0};
     Tables T;
-    // captured steps: [0] a hybrid step's body and the drift fused with the
-    // next step's first, [1] the encounter-free swapped step, [2] a hybrid
-    // step's body and its last drift
+    // captured steps: [kind] a step's body and the drift fused with the
+    // next step's first, [2 + kind] a step's body and its last drift (kind
+    // 0 hybrid, 1 the encounter-free swapped step)
     struct StepGraph {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         double tau = 0.0;
         bool valid = false;
-    } g[3];
+    } g[4];
     int profile = 0;   // 1: kernel timings, 2: and workgroup records
     // profiling: event pairs recorded around launches without waiting; the
     // pending pairs are read (and the events recycled) at the next flush
@@ -1186,15 +1186,35 @@ int sync_status(qsym_ctx *c)
 // (Sec. 2, after the composition): E_Dft(tau/2) E_Kep(tau/2) E_Int(tau)
 // E_Kep(tau/2) E_Dft(tau/2); one all-pairs kick per step.  The kick and the
 // second Kepler half-step share one pass over the bodies.
-hipError_t enqueue_swapped(qsym_ctx *c, double tau, hipStream_t st)
+// the swapped step E_Dft(tau/2) E_Kep(tau/2) E_Int(tau) E_Kep(tau/2)
+// E_Dft(tau/2): its first drift (fused with the previous step's last
+// between two steps of one call), its body, its last drift
+hipError_t enqueue_swapped_first_drift(qsym_ctx *c, double tau, hipStream_t st, int fused)
+{
+    return run_drift(c, tau / 2.0, 0, 0.0, 1, st, P_DRIFT, fused, 0, 0, fused);
+}
+
+hipError_t enqueue_swapped_body(qsym_ctx *c, double tau, hipStream_t st)
 {
     hipError_t e;
     const double half = tau / 2.0;
-    if ((e = run_drift(c, half, 0, 0.0, 1, st, P_DRIFT)) != hipSuccess) return e;
     if ((e = run_apply(c, 0.0, half, 0, 1, 0, 0, st, P_APPLY1, 0)) != hipSuccess) return e;
     if ((e = run_kick(c, 0, 0.0, st, P_KICK2)) != hipSuccess) return e;
-    if ((e = run_apply(c, tau, half, 1, 1, 0, 1, st, P_APPLY2, 0)) != hipSuccess) return e;
-    return run_drift(c, half, 0, 0.0, 0, st, P_DRIFT2, 1);
+    return run_apply(c, tau, half, 1, 1, 0, 1, st, P_APPLY2, 0);
+}
+
+hipError_t enqueue_swapped_mid(qsym_ctx *c, double tau, hipStream_t st)
+{
+    hipError_t e = enqueue_swapped_body(c, tau, st);
+    if (e != hipSuccess) return e;
+    return enqueue_swapped_first_drift(c, tau, st, 1);
+}
+
+hipError_t enqueue_swapped_last(qsym_ctx *c, double tau, hipStream_t st)
+{
+    hipError_t e = enqueue_swapped_body(c, tau, st);
+    if (e != hipSuccess) return e;
+    return run_drift(c, tau / 2.0, 0, 0.0, 0, st, P_DRIFT2, 1);
 }
 
 // nsteps steps of one kind (0 hybrid, 1 swapped): eager launches in
@@ -1206,22 +1226,23 @@ int run_steps(qsym_ctx *c, double tau, int64_t nsteps, int kind)
         return fail(c, QSYM_EINVAL, "kepler_mode 2 needs weights (qsym_set_guess)");
     if (nsteps == 0 || c->ntot == 0) return QSYM_OK;
     enter(c);
-    // a hybrid call of n steps: the first drift, then n - 1 times the step
-    // body with the fused drift between steps, then the last body and drift
+    // a call of n steps: the first drift, then n - 1 times the step body
+    // with the fused drift between steps, then the last body and drift
+    using Enq = hipError_t (*)(qsym_ctx *, double, hipStream_t);
+    const Enq mid = kind == 0 ? enqueue_step_mid : enqueue_swapped_mid;
+    const Enq last = kind == 0 ? enqueue_step_last : enqueue_swapped_last;
+    auto first = [&]() {
+        return kind == 0 ? enqueue_first_drift(c, tau, c->stream, 0)
+                         : enqueue_swapped_first_drift(c, tau, c->stream, 0);
+    };
     if (c->profile) {
-        if (kind == 0) {
-            HIPCHK(c, enqueue_first_drift(c, tau, c->stream, 0));
-            for (int64_t k = 0; k < nsteps; ++k)
-                HIPCHK(c, (k + 1 < nsteps ? enqueue_step_mid : enqueue_step_last)(c, tau, c->stream));
-        } else {
-            for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, enqueue_swapped(c, tau, c->stream));
-        }
+        HIPCHK(c, first());
+        for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, (k + 1 < nsteps ? mid : last)(c, tau, c->stream));
         leave(c);
         return QSYM_OK;
     }
-    // captured once per tau: [swapped step], [hybrid body + fused drift],
-    // [hybrid body + last drift]
-    auto graph = [&](int slot, hipError_t (*enqueue)(qsym_ctx *, double, hipStream_t)) -> int {
+    // captured once per tau and kind: [body + fused drift], [body + last drift]
+    auto graph = [&](int slot, Enq enqueue) -> int {
         auto &G = c->g[slot];
         if (G.valid && G.tau == tau) return QSYM_OK;
         if (G.exec) { hipGraphExecDestroy(G.exec); G.exec = nullptr; }
@@ -1242,16 +1263,11 @@ int run_steps(qsym_ctx *c, double tau, int64_t nsteps, int kind)
         return QSYM_OK;
     };
     int rc;
-    if (kind == 1) {
-        if ((rc = graph(1, enqueue_swapped)) != QSYM_OK) return rc;
-        for (int64_t k = 0; k < nsteps; ++k) HIPCHK(c, hipGraphLaunch(c->g[1].exec, c->stream));
-    } else {
-        if (nsteps > 1 && (rc = graph(0, enqueue_step_mid)) != QSYM_OK) return rc;
-        if ((rc = graph(2, enqueue_step_last)) != QSYM_OK) return rc;
-        HIPCHK(c, enqueue_first_drift(c, tau, c->stream, 0));
-        for (int64_t k = 0; k + 1 < nsteps; ++k) HIPCHK(c, hipGraphLaunch(c->g[0].exec, c->stream));
-        HIPCHK(c, hipGraphLaunch(c->g[2].exec, c->stream));
-    }
+    if (nsteps > 1 && (rc = graph(kind, mid)) != QSYM_OK) return rc;
+    if ((rc = graph(2 + kind, last)) != QSYM_OK) return rc;
+    HIPCHK(c, first());
+    for (int64_t k = 0; k + 1 < nsteps; ++k) HIPCHK(c, hipGraphLaunch(c->g[kind].exec, c->stream));
+    HIPCHK(c, hipGraphLaunch(c->g[2 + kind].exec, c->stream));
     leave(c);
     return QSYM_OK;
 }
