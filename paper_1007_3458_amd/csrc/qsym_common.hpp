@@ -20,7 +20,7 @@ constexpr int kStatStripes = 64;
 constexpr int kStatStride = 64;   // entries: [0, kHist) histogram, kHist total, kHist + 1 largest,
                                   // kHist + 2 solves restarted from the first-order guess
 constexpr int kSMax = 64;          // largest j-split of one system
-constexpr int kSetsThreads = 256;  // workgroup of the set-partition kernel
+constexpr int kSetsThreads = 512;  // workgroup of the set-partition kernel
 constexpr int kHermThreads = 512;  // workgroup of the Hermite kernel
 constexpr int kHermWave = 64;      // lanes of the one-wave Hermite
 constexpr int kWaveMax = 16;       // sets up to this size run on one wave, larger on a workgroup
