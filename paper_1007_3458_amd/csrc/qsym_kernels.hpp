@@ -701,9 +701,11 @@ __device__ __forceinline__ void sym_subtile(const double *sx, const double *sy, 
 #pragma unroll UNR
     for (int k = 0; k < 64; ++k) {
         const double xj = sx[lane + k], yj = sy[lane + k], zj = sz[lane + k], gmj = sm[lane + k];
+        bool hit[IPL];
 #pragma unroll
         for (int u = 0; u < IPL; ++u) {
             const int M = u == 0 ? M0 : M1;
+            hit[u] = false;
             if (M == SYM_SKIP) continue;
             const bool keep = M == SYM_DIAG ? (k > 0 && lane + k < 64) : true;
             double r2;
@@ -713,12 +715,26 @@ __device__ __forceinline__ void sym_subtile(const double *sx, const double *sy, 
             else
                 pair_sym32(xj, yj, zj, gmj, xi[u], yi[u], zi[u], gmi[u], keep, ax[u], ay[u], az[u],
                            fx, fy, fz, r2);
-            if constexpr (MODE != 0) {
-                if (keep && r2 < th2[u]) {
-                    const unsigned q = atomicAdd(qn, 1u);
-                    if (q < (unsigned)kCrudeQ) {
-                        qi[q] = ib + lt[u];
-                        qj[q] = jsub + ((lane + k) & 63);
+            if constexpr (MODE != 0) hit[u] = keep && r2 < th2[u];
+        }
+        if constexpr (MODE != 0) {
+            // one branch per rotation step for the lane's IPL pairs
+            bool any = hit[0];
+#pragma unroll
+            for (int u = 1; u < IPL; ++u) any = any || hit[u];
+            if (any) {
+                unsigned cnt = 0u;
+#pragma unroll
+                for (int u = 0; u < IPL; ++u) cnt += hit[u] ? 1u : 0u;
+                unsigned q = atomicAdd(qn, cnt);
+#pragma unroll
+                for (int u = 0; u < IPL; ++u) {
+                    if (hit[u]) {
+                        if (q < (unsigned)kCrudeQ) {
+                            qi[q] = ib + lt[u];
+                            qj[q] = jsub + ((lane + k) & 63);
+                        }
+                        ++q;
                     }
                 }
             }
