@@ -682,13 +682,14 @@ __device__ __forceinline__ void pair_sym32(double xj, double yj, double zj, doub
 enum { SYM_FULL = 0, SYM_DIAG = 1, SYM_SKIP = 2 };
 
 // 64 rotation steps of one wave over one sub-tile; lane group u (i_u =
-// u-th i of the lane) meets it as M0 (u = 0) / M1 (u = 1).  s* point at
-// the doubled sub-tile (x, y, z, G m rows of 128).  Crude-sweep hits are
-// queued as body pairs (ib + lt, jsub + j offset) in qi, qj.
+// u-th i of the lane) meets it as M0 (u = 0) / M1 (u = 1).  sxy, szm
+// point at the doubled sub-tile ((x, y) and (z, G m) rows of 128).
+// Crude-sweep hits are queued as body pairs (ib + lt, jsub + j offset) in
+// qi, qj.
 template <int MODE, int PREC, int IPL, int M0, int M1>
-__device__ __forceinline__ void sym_subtile(const double *sx, const double *sy, const double *sz,
-                                            const double *sm, int lane, const double *xi,
-                                            const double *yi, const double *zi, const double *gmi,
+__device__ __forceinline__ void sym_subtile(const double2 *sxy, const double2 *szm, int lane,
+                                            const double *xi, const double *yi,
+                                            const double *zi, const double *gmi,
                                             const double *th2, const int *lt,
                                             double seed, double c158, double c32, double *ax,
                                             double *ay, double *az, double &fx, double &fy,
@@ -700,7 +701,8 @@ __device__ __forceinline__ void sym_subtile(const double *sx, const double *sy, 
     constexpr int UNR = MODE != 0 ? 2 : 8;
 #pragma unroll UNR
     for (int k = 0; k < 64; ++k) {
-        const double xj = sx[lane + k], yj = sy[lane + k], zj = sz[lane + k], gmj = sm[lane + k];
+        const double2 pxy = sxy[lane + k], pzm = szm[lane + k];
+        const double xj = pxy.x, yj = pxy.y, zj = pzm.x, gmj = pzm.y;
         bool hit[IPL];
 #pragma unroll
         for (int u = 0; u < IPL; ++u) {
@@ -817,7 +819,9 @@ __attribute__((amdgpu_waves_per_eu(REC ? kick_rec_waves<BS, IPL, MODE, PREC>() :
     constexpr int BI = BS * IPL;
 
     // the j-tile, each sub-tile of 64 stored twice in a row (128 entries)
-    __shared__ double tx[NW][128], ty[NW][128], tz[NW][128], tm[NW][128];
+    // (x, y) and (z, G m) of a j side by side: one 16-byte read each per
+    // rotation step, at offsets from one address per unrolled group
+    __shared__ double2 txy[NW][128], tzm[NW][128];
     __shared__ double wpart[NW][3][BS];
     __shared__ double smax[3][NW];
     // crude sweep: pairs under the tile bound, queued over the tiles of the
@@ -891,10 +895,8 @@ __attribute__((amdgpu_waves_per_eu(REC ? kick_rec_waves<BS, IPL, MODE, PREC>() :
             {
                 const double xj = okj ? d.x[j] : kFar, yj = okj ? d.y[j] : kFar;
                 const double zj = okj ? d.z[j] : kFar, mj = okj ? G * d.m[j] : 0.0;
-                tx[wv][lane] = xj; tx[wv][lane + 64] = xj;
-                ty[wv][lane] = yj; ty[wv][lane + 64] = yj;
-                tz[wv][lane] = zj; tz[wv][lane + 64] = zj;
-                tm[wv][lane] = mj; tm[wv][lane + 64] = mj;
+                txy[wv][lane] = txy[wv][lane + 64] = make_double2(xj, yj);
+                tzm[wv][lane] = tzm[wv][lane + 64] = make_double2(zj, mj);
             }
             // this thread's reaction entry, read early (latency hidden by the
             // pairs); the item's first i-block starts it from zero
@@ -941,23 +943,22 @@ __attribute__((amdgpu_waves_per_eu(REC ? kick_rec_waves<BS, IPL, MODE, PREC>() :
                 const int jw = jt + 64 * sub;
                 double fx = 0.0, fy = 0.0, fz = 0.0;
                 const int rel = jw - iw;   // a multiple of 64
-                const double *px = &tx[sub][0], *py = &ty[sub][0], *pz = &tz[sub][0],
-                             *pm = &tm[sub][0];
+                const double2 *pxy = &txy[sub][0], *pzm = &tzm[sub][0];
                 // whole waves past the i-block's end or sub-tiles past the
                 // chunk's end have no pairs (uniform per wave)
                 if (!wave_i || jw >= jend || rel < 0) {
                     // nothing to add
                 } else if (rel >= 64 * IPL) {
                     sym_subtile<MODE, PREC, IPL, SYM_FULL, SYM_FULL>(
-                        px, py, pz, pm, lane, xi, yi, zi, gmi, th2, lt, seed, c158, c32, ax, ay,
+                        pxy, pzm, lane, xi, yi, zi, gmi, th2, lt, seed, c158, c32, ax, ay,
                         az, fx, fy, fz, qi, qj, &qn, ib, jt + 64 * sub);
                 } else if (IPL == 2 && rel == 64) {
                     sym_subtile<MODE, PREC, IPL, SYM_FULL, SYM_DIAG>(
-                        px, py, pz, pm, lane, xi, yi, zi, gmi, th2, lt, seed, c158, c32, ax, ay,
+                        pxy, pzm, lane, xi, yi, zi, gmi, th2, lt, seed, c158, c32, ax, ay,
                         az, fx, fy, fz, qi, qj, &qn, ib, jt + 64 * sub);
                 } else {   // rel == 0
                     sym_subtile<MODE, PREC, IPL, SYM_DIAG, SYM_SKIP>(
-                        px, py, pz, pm, lane, xi, yi, zi, gmi, th2, lt, seed, c158, c32, ax, ay,
+                        pxy, pzm, lane, xi, yi, zi, gmi, th2, lt, seed, c158, c32, ax, ay,
                         az, fx, fy, fz, qi, qj, &qn, ib, jt + 64 * sub);
                 }
                 wpart[wv][0][64 * sub + lane] = fx;
