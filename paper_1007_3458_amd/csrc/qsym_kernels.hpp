@@ -2154,7 +2154,12 @@ __device__ void set_pair_acc(const SetLds &S, int n, int a, int l, int L, double
 }
 
 // partial pair acceleration and jerk of H'_Kep (Sec. 2.2) on member a from
-// members b = l, l+L, ... at the staged state
+// members b = l, l+L, ... at the staged state.  A pair beyond r_crit adds
+// exactly zero and is skipped; but a wave runs the pair term whenever any of
+// its lanes has a pair inside, and in a set of a hundred members a lane's
+// 27 pairs hold about six inside.  So each lane first marks its pairs
+// inside (32 at a time, a bit each) and then takes only those, in the same
+// ascending order and with the same arithmetic as a loop over all of them.
 __device__ void herm_pairs(const SetLds &S, int n, int a, int l, int L, double G, double rc,
                            double eps, double acc[3], double jrk[3])
 {
@@ -2163,29 +2168,39 @@ __device__ void herm_pairs(const SetLds &S, int n, int a, int l, int L, double G
     const double U0 = S.u[a], U1 = S.v[a], U2 = S.w[a];
     const double eps2 = eps * eps;
     for (int c = 0; c < 3; ++c) acc[c] = jrk[c] = 0.0;
-    // dot products and sums as explicit fused multiply-adds (the library
-    // contracts nothing by itself)
-    for (int b = l; b < n; b += L) {
-        if (b == a) continue;
-        const double dd[3] = {S.x[b] - X0, S.y[b] - X1, S.z[b] - X2};
-        const double w[3] = {S.u[b] - U0, S.v[b] - U1, S.w[b] - U2};
-        const double s2 = fma(dd[2], dd[2], fma(dd[1], dd[1], fma(dd[0], dd[0], eps2)));
-        // beyond r_crit W = 0 and K'' = 0: the pair adds exactly zero
-        if (s2 == 0.0 || s2 >= tc.rc2) continue;
-        double s, is;
-        inv_dist(s2, s, is);
-        const double is2 = is * is;
-        double K, Kp, Kpp;
-        transition(s, tc, K, Kp, Kpp);
-        const double W = fma(s, Kp, 1.0 - K);
-        const double gm = G * S.m[b] * (is2 * is);
-        const double gmW = gm * W;
-        const double dw = fma(dd[2], w[2], fma(dd[1], w[1], dd[0] * w[0]));
-        const double c3 = 3.0 * dw * is2;
-        const double dK = dw * Kpp;
-        for (int c = 0; c < 3; ++c) {
-            acc[c] = fma(gmW, dd[c], acc[c]);
-            jrk[c] = fma(gm, fma(dK, dd[c], fma(-c3, dd[c], w[c]) * W), jrk[c]);
+    for (int b0 = l; b0 < n; b0 += 32 * L) {
+        unsigned inside = 0u;
+        for (int t = 0; t < 32; ++t) {
+            const int b = b0 + t * L;
+            if (b >= n) break;
+            const double d0 = S.x[b] - X0, d1 = S.y[b] - X1, d2 = S.z[b] - X2;
+            const double s2 = fma(d2, d2, fma(d1, d1, fma(d0, d0, eps2)));
+            // beyond r_crit W = 0 and K'' = 0: the pair adds exactly zero
+            if (b != a && !(s2 == 0.0 || s2 >= tc.rc2)) inside |= 1u << t;
+        }
+        // dot products and sums as explicit fused multiply-adds (the
+        // library contracts nothing by itself)
+        while (inside) {
+            const int b = b0 + __builtin_ctz(inside) * L;
+            inside &= inside - 1u;
+            const double dd[3] = {S.x[b] - X0, S.y[b] - X1, S.z[b] - X2};
+            const double w[3] = {S.u[b] - U0, S.v[b] - U1, S.w[b] - U2};
+            const double s2 = fma(dd[2], dd[2], fma(dd[1], dd[1], fma(dd[0], dd[0], eps2)));
+            double s, is;
+            inv_dist(s2, s, is);
+            const double is2 = is * is;
+            double K, Kp, Kpp;
+            transition(s, tc, K, Kp, Kpp);
+            const double W = fma(s, Kp, 1.0 - K);
+            const double gm = G * S.m[b] * (is2 * is);
+            const double gmW = gm * W;
+            const double dw = fma(dd[2], w[2], fma(dd[1], w[1], dd[0] * w[0]));
+            const double c3 = 3.0 * dw * is2;
+            const double dK = dw * Kpp;
+            for (int c = 0; c < 3; ++c) {
+                acc[c] = fma(gmW, dd[c], acc[c]);
+                jrk[c] = fma(gm, fma(dK, dd[c], fma(-c3, dd[c], w[c]) * W), jrk[c]);
+            }
         }
     }
 }
