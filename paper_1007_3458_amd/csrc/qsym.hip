@@ -92,20 +92,21 @@ long long sys_enc_cap(long long n)
     return std::min<long long>(kEncPerBody * n + 64, 1LL << 26);
 }
 
-// energy pair sum: units of 64 i x 64 j over each system's upper triangle,
-// 64 columns each; at least 8 units per wave where the work allows, at most
+// energy pair sum: units of 128 i x 64 j over each system's upper triangle
+// (row b, i in [128 b, 128 b + 128), meets the 64-blocks of j from 2 b on),
+// 64 columns each; at least 4 units per wave where the work allows, at most
 // 4096 waves (16 per compute unit)
 long long energy_units(long long n)
 {
-    const long long nb = (n + 63) / 64;
-    return nb * (nb + 1) / 2;
+    const long long nj = (n + 63) / 64, ni = (n + 127) / 128;
+    return ni * nj - ni * (ni - 1);
 }
 
 int energy_waves(const std::vector<long long> &off)
 {
     long long units = 0;
     for (size_t s = 0; s + 1 < off.size(); ++s) units += energy_units(off[s + 1] - off[s]);
-    const long long w = std::max<long long>(1, std::min<long long>((units + 7) / 8, 4096));
+    const long long w = std::max<long long>(1, std::min<long long>((units + 3) / 4, 4096));
     return (int)((w + 3) / 4 * 4);
 }
 

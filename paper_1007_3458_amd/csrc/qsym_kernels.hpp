@@ -2896,21 +2896,19 @@ __device__ void hermite_grid_sets(const HermArgs &a, double *red, int *s_ok)
 }
 
 // ------------------------------------------------------------------------
-// Energy (Sec. 2, H = H_Dft + H_Kep + H_Int): pair potentials over i < j
-// per work item, then per system the O(N) terms and a fixed-order sum.
-// ------------------------------------------------------------------------
-// ------------------------------------------------------------------------
 // Energy (Sec. 2: H = H_Dft + H_Kep + H_Int).  The pair sum takes every
 // pair i < j of a system once, m_j / r_ij with r^-1 from the hardware
 // reciprocal square root refined by the binomial series of (1 - e)^(-1/2),
 // e = 1 - r^2 y0^2 (exact to FP64 rounding, as the kick's r^-3).  The
-// pairs are cut into units of 64 i (one per lane) x 64 j (staged in the
-// wave's own LDS slice, so no workgroup barrier) over the upper triangle of
-// every system, and the units' 64 columns are dealt to the waves in equal
-// contiguous ranges that may begin or end inside a unit: every wave gets
-// the same number of pair columns.  A wave adds its sums per system into a
+// pairs are cut into units of 128 i (two per lane: the i-block's two
+// halves) x 64 j (staged in the wave's own LDS slice, so no workgroup
+// barrier) over the upper triangle of every system.  Two i per lane halve
+// the LDS traffic per pair: every lane reads every j of the slice, and
+// with one i per lane those reads, not the arithmetic, bound the sum.  The
+// units' 64 columns are dealt to the waves in equal contiguous ranges that
+// may begin or end inside a unit.  A wave adds its sums per system into a
 // record -- the kinetic, central-potential and momentum terms of the
-// bodies whose diagonal unit begins in its range, and the pair sum -- and
+// bodies whose first unit begins in its range, and the pair sum -- and
 // k_energy_final adds each system's records in order (deterministic).  A
 // coincident pair (r = 0, which the definition leaves out) makes a lane's
 // unit sum NaN through rsq(0) = inf: that lane sums the unit again with
@@ -2925,38 +2923,63 @@ struct EnergyArgs {
     int nsys;
 };
 
-// sum over the unit's columns [c0, c1) of m_j / r for the lane's i;
-// MASK: every pair tested (j > i on the diagonal unit, r > 0)
-template <bool MASK>
-__device__ __forceinline__ double energy_cols(const double *sx, const double *sy,
-                                              const double *sz, const double *sm, int c0, int c1,
-                                              double xi, double yi, double zi, int lane,
-                                              bool diag)
+// sum over the unit's columns [c0, c1) of m_j / r for one i, every pair
+// tested (r > 0, and j > i on a diagonal sub-block)
+__device__ __forceinline__ double energy_cols_masked(const double *sx, const double *sy,
+                                                     const double *sz, const double *sm, int c0,
+                                                     int c1, double xi, double yi, double zi,
+                                                     int lane, bool diag)
 {
     double acc = 0.0;
-    if constexpr (!MASK) {
-#pragma unroll 8
-        for (int k = c0; k < c1; ++k) {
-            const double dx = sx[k] - xi, dy = sy[k] - yi, dz = sz[k] - zi;
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            const double y0 = __builtin_amdgcn_rsq(r2);
-            const double e = fma(-r2, y0 * y0, 1.0);
-            const double w = fma(e, fma(e, 0.375, 0.5), 1.0);
-            acc = fma(sm[k] * y0, w, acc);
-        }
-    } else {
-        for (int k = c0; k < c1; ++k) {
-            const double dx = sx[k] - xi, dy = sy[k] - yi, dz = sz[k] - zi;
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            const bool keep = r2 > 0.0 && (!diag || k > lane);
-            const double rk = keep ? r2 : 1.0;
-            const double y0 = __builtin_amdgcn_rsq(rk);
-            const double e = fma(-rk, y0 * y0, 1.0);
-            const double w = fma(e, fma(e, 0.375, 0.5), 1.0);
-            acc = fma(keep ? sm[k] * y0 : 0.0, w, acc);
-        }
+    for (int k = c0; k < c1; ++k) {
+        const double dx = sx[k] - xi, dy = sy[k] - yi, dz = sz[k] - zi;
+        const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        const bool keep = r2 > 0.0 && (!diag || k > lane);
+        const double rk = keep ? r2 : 1.0;
+        const double y0 = __builtin_amdgcn_rsq(rk);
+        const double e = fma(-rk, y0 * y0, 1.0);
+        const double w = fma(e, fma(e, 0.375, 0.5), 1.0);
+        acc = fma(keep ? sm[k] * y0 : 0.0, w, acc);
     }
     return acc;
+}
+
+// both i of the lane over the columns [c0, c1): the first half meets the
+// whole slice, the second half too (DIAG1 = false) or only j > i (the
+// slice is its own 64-block, DIAG1 = true)
+template <bool DIAG1>
+__device__ __forceinline__ void energy_cols2(const double *sx, const double *sy, const double *sz,
+                                             const double *sm, int c0, int c1, double x0,
+                                             double y0, double z0, double x1, double y1,
+                                             double z1, int lane, double &acc0, double &acc1)
+{
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll 4
+    for (int k = c0; k < c1; ++k) {
+        const double xj = sx[k], yj = sy[k], zj = sz[k], mj = sm[k];
+        {
+            const double dx = xj - x0, dy = yj - y0, dz = zj - z0;
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            const double y = __builtin_amdgcn_rsq(r2);
+            const double e = fma(-r2, y * y, 1.0);
+            const double w = fma(e, fma(e, 0.375, 0.5), 1.0);
+            a0 = fma(mj * y, w, a0);
+        }
+        {
+            const double dx = xj - x1, dy = yj - y1, dz = zj - z1;
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            // on the diagonal block only j > i (the rest through a finite
+            // stand-in that adds zero)
+            const bool keep = !DIAG1 || k > lane;
+            const double rk = keep ? r2 : 1.0;
+            const double y = __builtin_amdgcn_rsq(rk);
+            const double e = fma(-rk, y * y, 1.0);
+            const double w = fma(e, fma(e, 0.375, 0.5), 1.0);
+            a1 = fma(keep ? mj * y : 0.0, w, a1);
+        }
+    }
+    acc0 = a0;
+    acc1 = a1;
 }
 
 // sum over the wave, the same bits on every lane (lane 0's butterfly)
@@ -2965,6 +2988,13 @@ __device__ __forceinline__ double wave_sum0(double v)
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
     return wave_uniform(v);
+}
+
+// first unit of row b of a system with nj 64-blocks of j: row b' holds the
+// j-blocks t >= 2 b', nj - 2 b' units
+__device__ __forceinline__ long long energy_row0(long long b, long long nj)
+{
+    return b * nj - b * (b - 1);
 }
 
 __global__ __launch_bounds__(256) void k_energy_pairs(EnergyArgs a)
@@ -2978,8 +3008,7 @@ __global__ __launch_bounds__(256) void k_energy_pairs(EnergyArgs a)
     if (C0 >= C1) return;   // (waves only; no workgroup barrier follows)
     double *sx = lds[wv][0], *sy = lds[wv][1], *sz = lds[wv][2], *sm = lds[wv][3];
     // the system and unit (b, t) of the first column: systems by binary
-    // search of their first units, (b, t) from the row starts
-    // S(b) = b nb - b (b - 1) / 2 of the system's upper triangle
+    // search of their first units, the row b from the row starts
     long long U = C0 >> 6;
     int lo = 0, hi = a.nsys - 1;
     while (lo < hi) {
@@ -2988,27 +3017,27 @@ __global__ __launch_bounds__(256) void k_energy_pairs(EnergyArgs a)
     }
     int s = lo;
     while (d.sys_u0[s + 1] <= U) ++s;   // systems without units
-    int so = d.sys_off[s], n = d.sys_off[s + 1] - so, nb = (n + 63) >> 6;
+    int so = d.sys_off[s], n = d.sys_off[s + 1] - so;
+    int nj = (n + 63) >> 6, ni = (n + 127) >> 7;
     const long long v = U - d.sys_u0[s];
-    int b = (int)((2.0 * nb + 1.0 - sqrt((2.0 * nb + 1.0) * (2.0 * nb + 1.0) - 8.0 * (double)v)) / 2.0);
-    b = max(0, min(b, nb - 1));
-    while (b > 0 && (long long)b * nb - (long long)b * (b - 1) / 2 > v) --b;
-    while (b + 1 < nb && (long long)(b + 1) * nb - (long long)(b + 1) * b / 2 <= v) ++b;
-    int t = b + (int)(v - ((long long)b * nb - (long long)b * (b - 1) / 2));
+    const double q = (double)nj + 1.0;
+    int b = (int)((q - sqrt(fmax(q * q - 4.0 * (double)v, 0.0))) / 2.0);
+    b = max(0, min(b, ni - 1));
+    while (b > 0 && energy_row0(b, nj) > v) --b;
+    while (b + 1 < ni && energy_row0(b + 1, nj) <= v) ++b;
+    int t = 2 * b + (int)(v - energy_row0(b, nj));
     int rec = d.e_wrec[w];
     double R[kERec] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double G = a.G;
-    // operands of this lane's i and j: loaded one unit ahead, so the loads
-    // of the next unit are in flight during the pairs of this one
-    double xi, yi, zi, mi;
-    bool iok;
-    auto load_i = [&](int so_, int n_, int b_, double &x, double &y, double &z, double &m, bool &ok) {
-        const int i = so_ + 64 * b_ + lane;
-        ok = 64 * b_ + lane < n_;
-        x = ok ? d.x[i] : kFarI;
-        y = ok ? d.y[i] : kFarI;
-        z = ok ? d.z[i] : kFarI;
-        m = ok ? d.m[i] : 0.0;
+    // operands of this lane's two i and its j: loaded one unit ahead, so
+    // the loads of the next unit are in flight during the pairs of this one
+    auto load_i = [&](int so_, int n_, int i_, double &x, double &y, double &z, double &m,
+                      bool &ok) {
+        ok = i_ < n_;
+        x = ok ? d.x[so_ + i_] : kFarI;
+        y = ok ? d.y[so_ + i_] : kFarI;
+        z = ok ? d.z[so_ + i_] : kFarI;
+        m = ok ? d.m[so_ + i_] : 0.0;
     };
     auto load_j = [&](int so_, int n_, int t_, double &x, double &y, double &z, double &m) {
         const int j = so_ + 64 * t_ + lane;
@@ -3018,7 +3047,10 @@ __global__ __launch_bounds__(256) void k_energy_pairs(EnergyArgs a)
         z = ok ? d.z[j] : kFar;
         m = ok ? d.m[j] : 0.0;
     };
-    load_i(so, n, b, xi, yi, zi, mi, iok);
+    double x0, y0, z0, m0, x1, y1, z1, m1;
+    bool ok0, ok1;
+    load_i(so, n, 128 * b + lane, x0, y0, z0, m0, ok0);
+    load_i(so, n, 128 * b + 64 + lane, x1, y1, z1, m1, ok1);
     double jx, jy, jz, jm;
     load_j(so, n, t, jx, jy, jz, jm);
     long long C = C0;
@@ -3031,51 +3063,69 @@ __global__ __launch_bounds__(256) void k_energy_pairs(EnergyArgs a)
         sz[lane] = jz;
         sm[lane] = jm;
         wave_lds_sync();
-        // the next unit: the next tile of the row, the next row, the next
-        // system with units; its operands requested now
+        // the next unit: the next j-block of the row, the next row, the
+        // next system with units; its operands requested now
         const bool more = ubase + c1 < C1;
-        int s2 = s, so2 = so, n2 = n, nb2 = nb, b2 = b, t2 = t + 1;
+        int s2 = s, so2 = so, n2 = n, nj2 = nj, ni2 = ni, b2 = b, t2 = t + 1;
         bool newsys = false;
-        double pxi = 0.0, pyi = 0.0, pzi = 0.0, pmi = 0.0;
-        bool piok = false;
+        double px0 = 0.0, py0 = 0.0, pz0 = 0.0, pm0 = 0.0;
+        double px1 = 0.0, py1 = 0.0, pz1 = 0.0, pm1 = 0.0;
+        bool pok0 = false, pok1 = false;
         if (more) {
-            if (t2 == nb2) {
+            if (t2 == nj2) {
                 b2 = b + 1;
-                if (b2 == nb2) {
+                if (b2 == ni2) {
                     newsys = true;
                     do {
                         ++s2;
                     } while (d.sys_u0[s2 + 1] == d.sys_u0[s2]);
                     so2 = d.sys_off[s2];
                     n2 = d.sys_off[s2 + 1] - so2;
-                    nb2 = (n2 + 63) >> 6;
+                    nj2 = (n2 + 63) >> 6;
+                    ni2 = (n2 + 127) >> 7;
                     b2 = 0;
                 }
-                t2 = b2;
-                load_i(so2, n2, b2, pxi, pyi, pzi, pmi, piok);
+                t2 = 2 * b2;
+                load_i(so2, n2, 128 * b2 + lane, px0, py0, pz0, pm0, pok0);
+                load_i(so2, n2, 128 * b2 + 64 + lane, px1, py1, pz1, pm1, pok1);
             }
             load_j(so2, n2, t2, jx, jy, jz, jm);
         }
-        const bool diag = t == b;
-        double acc;
-        if (diag) {
-            acc = energy_cols<true>(sx, sy, sz, sm, c0, c1, xi, yi, zi, lane, true);
-            if (c0 == 0 && iok) {
+        double acc0 = 0.0, acc1 = 0.0;
+        if (t == 2 * b) {
+            // the slice is the first half's own 64-block; the second half
+            // lies past it
+            acc0 = energy_cols_masked(sx, sy, sz, sm, c0, c1, x0, y0, z0, lane, true);
+            if (c0 == 0) {
                 // the bodies of this i-block: kinetic, central and momentum
-                // terms (once: in the range holding the block's diagonal unit)
-                const int i = so + 64 * b + lane;
-                const double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
-                R[0] += 0.5 * mi * (vx * vx + vy * vy + vz * vz);
-                R[1] += G * d.sys_m0[s] * mi / dnorm3(xi, yi, zi);
-                R[2] += mi * vx;
-                R[3] += mi * vy;
-                R[4] += mi * vz;
+                // terms (once: in the range holding the block's first unit)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (!(u == 0 ? ok0 : ok1)) continue;
+                    const int i = so + 128 * b + 64 * u + lane;
+                    const double xi = u == 0 ? x0 : x1, yi = u == 0 ? y0 : y1;
+                    const double zi = u == 0 ? z0 : z1, mi = u == 0 ? m0 : m1;
+                    const double vx = d.vx[i], vy = d.vy[i], vz = d.vz[i];
+                    R[0] += 0.5 * mi * (vx * vx + vy * vy + vz * vz);
+                    R[1] += G * d.sys_m0[s] * mi / dnorm3(xi, yi, zi);
+                    R[2] += mi * vx;
+                    R[3] += mi * vy;
+                    R[4] += mi * vz;
+                }
             }
         } else {
-            acc = energy_cols<false>(sx, sy, sz, sm, c0, c1, xi, yi, zi, lane, false);
-            if (isnan(acc)) acc = energy_cols<true>(sx, sy, sz, sm, c0, c1, xi, yi, zi, lane, false);
+            const bool diag1 = t == 2 * b + 1;
+            if (diag1)
+                energy_cols2<true>(sx, sy, sz, sm, c0, c1, x0, y0, z0, x1, y1, z1, lane, acc0, acc1);
+            else
+                energy_cols2<false>(sx, sy, sz, sm, c0, c1, x0, y0, z0, x1, y1, z1, lane, acc0, acc1);
+            if (isnan(acc0))
+                acc0 = energy_cols_masked(sx, sy, sz, sm, c0, c1, x0, y0, z0, lane, false);
+            if (isnan(acc1))
+                acc1 = energy_cols_masked(sx, sy, sz, sm, c0, c1, x1, y1, z1, lane, diag1);
         }
-        R[5] = fma(mi, acc, R[5]);
+        R[5] = fma(m0, acc0, R[5]);
+        R[5] = fma(m1, acc1, R[5]);
         wave_lds_sync();   // the slice is restaged for the next unit
         if (!more) break;
         if (newsys) {
@@ -3088,16 +3138,14 @@ __global__ __launch_bounds__(256) void k_energy_pairs(EnergyArgs a)
             ++rec;
         }
         if (b2 != b || newsys) {
-            xi = pxi;
-            yi = pyi;
-            zi = pzi;
-            mi = pmi;
-            iok = piok;
+            x0 = px0; y0 = py0; z0 = pz0; m0 = pm0; ok0 = pok0;
+            x1 = px1; y1 = py1; z1 = pz1; m1 = pm1; ok1 = pok1;
         }
         s = s2;
         so = so2;
         n = n2;
-        nb = nb2;
+        nj = nj2;
+        ni = ni2;
         b = b2;
         t = t2;
         C = ubase + c1;
