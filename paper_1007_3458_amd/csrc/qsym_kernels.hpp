@@ -1027,6 +1027,40 @@ __attribute__((amdgpu_waves_per_eu(REC ? kick_rec_waves<BS, IPL, MODE, PREC>() :
 // share `part` of P of the partial-sum slots of local body il: the body's
 // slots (its i-side chunks, then for the symmetric kick the j-side
 // i-ranges that reach it) in list order, every P-th from the part-th
+// slots q = part, part + P, ... < qe of the list whose entry q is slot
+// q0 + q below qs and slot base + (q - qs) from qs on, added in list order.
+// Four slots are requested before any is added, so the loads' latencies
+// overlap (a loop that adds each value as it arrives waits once per slot).
+__device__ __forceinline__ void sum_slot_list(const double *p, long long ns, int part, int P,
+                                              int qe, int qs, long long q0, long long base,
+                                              double &ax, double &ay, double &az)
+{
+    int q = part;
+    for (; q + 3 * P < qe; q += 4 * P) {
+        double vx[4], vy[4], vz[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int qq = q + u * P;
+            const long long sl = qq < qs ? q0 + qq : base + (qq - qs);
+            vx[u] = p[(3 * sl) * ns];
+            vy[u] = p[(3 * sl + 1) * ns];
+            vz[u] = p[(3 * sl + 2) * ns];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ax += vx[u];
+            ay += vy[u];
+            az += vz[u];
+        }
+    }
+    for (; q < qe; q += P) {
+        const long long sl = q < qs ? q0 + q : base + (q - qs);
+        ax += p[(3 * sl) * ns];
+        ay += p[(3 * sl + 1) * ns];
+        az += p[(3 * sl + 2) * ns];
+    }
+}
+
 __device__ __forceinline__ void sum_partials(const Dev &d, const int4 *sysK, int s, int il,
                                              int part, int P, double a[3])
 {
@@ -1040,29 +1074,16 @@ __device__ __forceinline__ void sum_partials(const Dev &d, const int4 *sysK, int
         // and including its own
         const int r = il / K.y;
         const int kr = d.krow[K.z + r];
-        for (int q = part; q < kr + r + 1; q += P) {
-            const long long sl = q < kr ? q : K.x + (q - kr);
-            ax += p[(3 * sl) * ns];
-            ay += p[(3 * sl + 1) * ns];
-            az += p[(3 * sl + 2) * ns];
+        sum_slot_list(p, ns, part, P, kr + r + 1, kr, 0, K.x, ax, ay, az);
+    } else {
+        int c0 = 0, c1 = K.x, r1 = 0;
+        if (K.z > 0) {
+            const int cx = il / K.y;
+            c0 = cx;
+            r1 = (min((cx + 1) * K.y, ns) + K.z - 1) / K.z;
         }
-        a[0] = ax;
-        a[1] = ay;
-        a[2] = az;
-        return;
-    }
-    int c0 = 0, c1 = K.x, r1 = 0;
-    if (K.z > 0) {
-        const int cx = il / K.y;
-        c0 = cx;
-        r1 = (min((cx + 1) * K.y, ns) + K.z - 1) / K.z;
-    }
-    const int ni = c1 - c0;
-    for (int q = part; q < ni + r1; q += P) {
-        const long long sl = q < ni ? c0 + q : K.x + (q - ni);
-        ax += p[(3 * sl) * ns];
-        ay += p[(3 * sl + 1) * ns];
-        az += p[(3 * sl + 2) * ns];
+        const int ni = c1 - c0;
+        sum_slot_list(p, ns, part, P, ni + r1, ni, c0, K.x, ax, ay, az);
     }
     a[0] = ax;
     a[1] = ay;
