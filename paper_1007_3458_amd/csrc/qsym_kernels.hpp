@@ -116,7 +116,21 @@ __device__ void system_momentum(const Dev &d, int s, double P[3])
     const int c0 = d.sys_k0[s], c1 = d.sys_k0[s + 1];
     const int lane = threadIdx.x & 63;
     double a[3] = {0.0, 0.0, 0.0};
-    for (int c = c0 + lane; c < c1; c += 64) {
+    // four partials requested before any is added (the same order), so
+    // their loads overlap
+    int c = c0 + lane;
+    for (; c + 192 < c1; c += 256) {
+        double v[4][3];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[u][k] = d.pm[3 * (c + 64 * u) + k];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) a[k] += v[u][k];
+    }
+    for (; c < c1; c += 64) {
         a[0] += d.pm[3 * c];
         a[1] += d.pm[3 * c + 1];
         a[2] += d.pm[3 * c + 2];
