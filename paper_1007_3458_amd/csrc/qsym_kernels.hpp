@@ -1125,22 +1125,14 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
     // p-th thread group of BS sums every P-th slot from the p-th for the
     // chunk's consecutive bodies, and the P shares are added in order.  The
     // per-body steps then run on the first BS threads.
+    static_assert(BS == 64, "the chunk's bodies are one wave (the statistics are wave sums)");
     __shared__ double share[P > 1 ? P : 1][3][BS];
-    __shared__ unsigned int hist[kHist];
-    __shared__ unsigned int kmax, krestart;
-    __shared__ unsigned long long ksum;
     __shared__ int bad;
     const Dev &d = a.d;
     const int4 bc = a.chunks[blockIdx.x];
     const int s = bc.x;
     const int t = threadIdx.x;
-    if (t < kHist) hist[t] = 0;
-    if (t == 0) {
-        kmax = 0;
-        krestart = 0;
-        ksum = 0;
-        bad = 0;
-    }
+    if (t == 0) bad = 0;
     double sh[3] = {0.0, 0.0, 0.0};
     if (P > 1 && a.do_kick) {
         const int bt = t % BS, part = t / BS;
@@ -1151,6 +1143,7 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
     }
     __syncthreads();
     double mom[3] = {0.0, 0.0, 0.0};
+    int kit = -1, krs = 0;   // this body's Kepler iterations and restart
     if (t < BS && t < bc.z) {
         const int i = bc.y + t;
         double x = d.x[i], y = d.y[i], z = d.z[i];
@@ -1179,12 +1172,9 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
         }
         if (a.do_kep) {
             int fail, restart;
-            const int it = kepler_advance(a.G * d.sys_m0[s], a.kepler_mode, d.guess, a.dt_kep, x, y,
-                                          z, vx, vy, vz, fail, restart);
-            atomicAdd(&hist[it < kHist ? it : kHist - 1], 1u);
-            atomicMax(&kmax, (unsigned)it);
-            atomicAdd(&ksum, (unsigned long long)it);
-            if (restart) atomicAdd(&krestart, 1u);
+            kit = kepler_advance(a.G * d.sys_m0[s], a.kepler_mode, d.guess, a.dt_kep, x, y, z, vx,
+                                 vy, vz, fail, restart);
+            krs = restart;
             if (fail) atomicOr(&bad, (int)S_KEPLER);
         }
         if (!(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) && isfinite(vy) &&
@@ -1210,16 +1200,31 @@ __global__ __launch_bounds__(BS * P) void k_apply_kepler(ApplyArgs a)
                 for (int k = 0; k < 3; ++k) d.pm[3 * blockIdx.x + k] = mom[k];
         }
     }
-    __syncthreads();
-    if (a.do_kep) {
+    if (a.do_kep && t < 64) {
+        // the chunk's iteration statistics by ballots over its wave (one
+        // per iteration count present, counted upward until every body is
+        // counted), instead of 64 lanes' atomics on one LDS word each
         unsigned long long *ks = d.kstat + (size_t)(blockIdx.x & (kStatStripes - 1)) * kStatStride;
-        if (t < kHist && hist[t]) atomicAdd(&ks[t], (unsigned long long)hist[t]);
+        unsigned long long rem = __ballot(kit >= 0);
+        unsigned long long sum = 0, top = 0;
+        for (int b = 0; rem != 0ull; ++b) {
+            const unsigned long long m = __ballot(kit == b);
+            if (m) {
+                const unsigned long long c = (unsigned long long)__popcll(m);
+                if (t == 0) atomicAdd(&ks[b < kHist ? b : kHist - 1], c);
+                sum += c * (unsigned long long)b;
+                top = (unsigned long long)b;
+                rem &= ~m;
+            }
+        }
+        const unsigned long long nrs = (unsigned long long)__popcll(__ballot(krs != 0));
         if (t == 0) {
-            atomicAdd(&ks[kHist], ksum);
-            atomicMax(&ks[kHist + 1], (unsigned long long)kmax);
-            if (krestart) atomicAdd(&ks[kHist + 2], (unsigned long long)krestart);
+            atomicAdd(&ks[kHist], sum);
+            atomicMax(&ks[kHist + 1], top);
+            if (nrs) atomicAdd(&ks[kHist + 2], nrs);
         }
     }
+    __syncthreads();
     if (t == 0 && bad) latch(d.ctr, (unsigned long long)bad);
 }
 
