@@ -1516,6 +1516,16 @@ template <int T>
 __device__ void sets_global(const SetsArgs &a, int sys, int *tmp, int &base_set, int &base_mem,
                             int &s_whole);
 
+// the largest set of the workgroup's sets onto the step's counter: a wave
+// maximum first, so one atomic per wave goes to the counter's word, not one
+// per thread that met a set
+__device__ __forceinline__ void note_max_set(unsigned long long *ctr, unsigned big)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) big = max(big, (unsigned)__shfl_xor((int)big, o, 64));
+    if ((threadIdx.x & 63) == 0 && big) atomicMax(ctr, (unsigned long long)big);
+}
+
 // binary search of v in the ascending u[0..n)
 __device__ __forceinline__ int lower_rank(const unsigned *u, int n, unsigned v)
 {
@@ -1773,7 +1783,7 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
         else
             d.set_list[d.setcap - 1 - (base_mem + (pos >> 16))] = bs + sid;
     }
-    if (big) atomicMax(&d.ctr[C_MAXSET], (unsigned long long)big);
+    note_max_set(&d.ctr[C_MAXSET], big);
     if (t == 0) atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
 }
 
@@ -1991,7 +2001,7 @@ __device__ void sets_global(const SetsArgs &a, int sys, int *tmp, int &base_set,
             else
                 d.set_list[d.setcap - 1 - (base_mem + bigf[sid])] = bs + sid;
         }
-        if (big) atomicMax(&d.ctr[C_MAXSET], (unsigned long long)big);
+        note_max_set(&d.ctr[C_MAXSET], (unsigned)big);
         if (t == 0) {
             atomicAdd(&d.ctr[C_TENC], (unsigned long long)ne);
             atomicAdd(&d.ctr[C_TBIGSYS], 1ull);
