@@ -222,6 +222,19 @@ def test_step_lockstep(Q, orc, name, nsteps):
         assert enc > 0
 
 
+def test_step_lockstep_large_workgroup_set(Q, orc):
+    """A 217-member set on one workgroup (two lanes a member, up to 109
+    pairs a lane): each lane marks its pairs inside r_crit in several
+    32-pair passes before taking them."""
+    s = inputs.make_disk("crowd220", 3, 216, 1e-4, 4.9, 5.1, "uniform", "uniform", 0.05, 0.01)
+    _, _, r = orc.step(orc.make_params(), 0.05, s.m, s.h, s.q, s.v)
+    assert r.rc == 0
+    assert 128 < np.bincount(r.label[r.label >= 0]).max() <= 256
+    say("lockstep 217-member set")
+    enc, border = _lockstep(Q, orc, s, 3)
+    assert enc > 0 and border == 0
+
+
 def test_step_lockstep_hermite_heavy(Q, orc):
     """Massive crowded bodies: many Hermite substeps per set."""
     s = crowded(120, 9, m=3e-5)
