@@ -1457,14 +1457,18 @@ __device__ void block_sort_u32(unsigned *v, int n2)
     }
 }
 
+// inclusive scan over the wave by DPP moves (VALU operations, no LDS round
+// trips): row_shr 1, 2, 4, 8 within each row of 16 (a lane with no source
+// adds 0), then row_bcast 15 carries row 0's total into row 1 and row 2's
+// into row 3, and row_bcast 31 the total of rows 0-1 into rows 2 and 3
 __device__ __forceinline__ int wave_incl_scan(int v)
 {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15, rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31, rows 2, 3
     return v;
 }
 
@@ -1584,10 +1588,14 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
         const int nw = (nsb + 31) >> 5;
         for (int k = t; k < nw; k += blockDim.x) bits[k] = 0u;
         __syncthreads();
+        // the pairs are read once and kept in lab (free until the labels
+        // are set up) for the ranks below
         for (int k = t; k < ne; k += blockDim.x) {
             const int2 p = enc[k];
             atomicOr(&bits[(p.x - so) >> 5], 1u << ((p.x - so) & 31));
             atomicOr(&bits[(p.y - so) >> 5], 1u << ((p.y - so) & 31));
+            lab[2 * k] = (unsigned)(p.x - so);
+            lab[2 * k + 1] = (unsigned)(p.y - so);
         }
         __syncthreads();
         for (int k = t; k < nw; k += blockDim.x) wpre[k] = __popc(bits[k]);
@@ -1602,8 +1610,7 @@ __global__ __launch_bounds__(kSetsThreads) void k_sets(SetsArgs a)
             }
         }
         for (int k = t; k < ne; k += blockDim.x) {
-            const int2 p = enc[k];
-            const int bx = p.x - so, by = p.y - so;
+            const int bx = (int)lab[2 * k], by = (int)lab[2 * k + 1];
             const int ri = wpre[bx >> 5] + __popc(bits[bx >> 5] & ((1u << (bx & 31)) - 1u));
             const int rj = wpre[by >> 5] + __popc(bits[by >> 5] & ((1u << (by & 31)) - 1u));
             rp[k] = ((unsigned)ri << 16) | (unsigned)rj;
