@@ -335,11 +335,37 @@ __device__ __forceinline__ int xcd_item(int b, int g)
     return (b & 7) * per + (b >> 3);
 }
 
+// a double moved between lanes by the DPP pattern CTRL (both halves, every
+// row and bank enabled)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// maximum over the wave (fmax: NaN only where every lane has NaN): the row
+// maxima through four DPP levels (quad_perm [1,0,3,2] and [2,3,0,1],
+// row_half_mirror, row_mirror), then the four rows read into scalar
+// registers; every lane gets the same value
 __device__ __forceinline__ double wave_max(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    v = fmax(v, dpp_f64<0xB1>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0x141>(v));
+    v = fmax(v, dpp_f64<0x140>(v));
+    return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+                fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
 
 // Crude sweep, exact form (Sec. 2.4 reading): evaluated only for the pairs
@@ -628,17 +654,6 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(1, 4))) void
 // entry l + k needs no wrap-around and every read takes its offset from
 // the instruction.
 // ------------------------------------------------------------------------
-
-// a double moved between lanes by the DPP pattern CTRL (both halves, every
-// row and bank enabled)
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
 
 // lane l receives v of lane (l + 1) mod 64: DPP wave_rol:1 (control 0x134;
 // its lane layout checked on the device: lane l reads lane l + 1, lane 63
@@ -2335,14 +2350,6 @@ __device__ __forceinline__ double herm_correct(const HermStep &k, double eta, co
     const double n2 = dnorm3(A2e[0], A2e[1], A2e[2]);
     const double n3 = dnorm3(A3v[0], A3v[1], A3v[2]);
     return sqrt(eta * (na * n2 + nj * nj) / (nj * n3 + n2 * n2));
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int lane)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // minimum over the wave (fmin: NaN only where every lane has NaN): the
