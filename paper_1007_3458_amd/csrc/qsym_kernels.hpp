@@ -728,10 +728,24 @@ __device__ __forceinline__ void sym_subtile(const double2 *sxy, const double2 *s
     // the crude test's queue pushes split the loop body into blocks, and a
     // deep unroll then keeps too many values live: unroll less with it
     constexpr int UNR = MODE != 0 ? 2 : 8;
+    // with the crude test each rotation step is a block of its own (its
+    // branch), so the crude kicks read the next step's j while this one
+    // runs (a scheduling barrier keeps the reads there; entry lane + 64
+    // still lies in the doubled sub-tile); the plain kick's unrolled body
+    // overlaps them by itself
+    double2 nxy = sxy[lane], nzm = szm[lane];
 #pragma unroll UNR
     for (int k = 0; k < 64; ++k) {
-        const double2 pxy = sxy[lane + k], pzm = szm[lane + k];
-        const double xj = pxy.x, yj = pxy.y, zj = pzm.x, gmj = pzm.y;
+        double xj, yj, zj, gmj;
+        if constexpr (MODE != 0) {
+            xj = nxy.x; yj = nxy.y; zj = nzm.x; gmj = nzm.y;
+            nxy = sxy[lane + k + 1];
+            nzm = szm[lane + k + 1];
+            __builtin_amdgcn_sched_barrier(0);
+        } else {
+            const double2 pxy = sxy[lane + k], pzm = szm[lane + k];
+            xj = pxy.x; yj = pxy.y; zj = pzm.x; gmj = pzm.y;
+        }
         bool hit[IPL];
 #pragma unroll
         for (int u = 0; u < IPL; ++u) {
