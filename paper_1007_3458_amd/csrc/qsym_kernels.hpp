@@ -2221,21 +2221,33 @@ __device__ void set_pair_acc(const SetLds &S, int n, int a, int l, int L, double
     const TransConst tc = trans_const(rc);
     const double xi = S.x[a], yi = S.y[a], zi = S.z[a];
     out[0] = out[1] = out[2] = 0.0;
-    for (int b = l; b < n; b += L) {
-        if (b == a) continue;
-        const double dd0 = S.x[b] - xi, dd1 = S.y[b] - yi, dd2 = S.z[b] - zi;
-        const double s2 = fma(dd2, dd2, fma(dd1, dd1, dd0 * dd0));
-        // beyond r_crit K = 1, K' = 0: W = 0, the pair adds exactly zero
-        if (s2 == 0.0 || s2 >= tc.rc2) continue;
-        double s, is;
-        inv_dist(s2, s, is);
-        double K, Kp, Kpp;
-        transition(s, tc, K, Kp, Kpp);
-        const double W = fma(s, Kp, 1.0 - K);
-        const double fct = G * S.m[b] * W * (is * is * is);
-        out[0] = fma(fct, dd0, out[0]);
-        out[1] = fma(fct, dd1, out[1]);
-        out[2] = fma(fct, dd2, out[2]);
+    // the pairs inside r_crit marked first and only those taken, in the
+    // same order (as herm_pairs below)
+    for (int b0 = l; b0 < n; b0 += 32 * L) {
+        unsigned in = 0u;
+        for (int t = 0; t < 32; ++t) {
+            const int b = b0 + t * L;
+            if (b >= n) break;
+            const double dd0 = S.x[b] - xi, dd1 = S.y[b] - yi, dd2 = S.z[b] - zi;
+            const double s2 = fma(dd2, dd2, fma(dd1, dd1, dd0 * dd0));
+            // beyond r_crit K = 1, K' = 0: W = 0, the pair adds exactly zero
+            if (b != a && !(s2 == 0.0 || s2 >= tc.rc2)) in |= 1u << t;
+        }
+        while (in) {
+            const int b = b0 + __builtin_ctz(in) * L;
+            in &= in - 1u;
+            const double dd0 = S.x[b] - xi, dd1 = S.y[b] - yi, dd2 = S.z[b] - zi;
+            const double s2 = fma(dd2, dd2, fma(dd1, dd1, dd0 * dd0));
+            double s, is;
+            inv_dist(s2, s, is);
+            double K, Kp, Kpp;
+            transition(s, tc, K, Kp, Kpp);
+            const double W = fma(s, Kp, 1.0 - K);
+            const double fct = G * S.m[b] * W * (is * is * is);
+            out[0] = fma(fct, dd0, out[0]);
+            out[1] = fma(fct, dd1, out[1]);
+            out[2] = fma(fct, dd2, out[2]);
+        }
     }
 }
 
